@@ -1,0 +1,336 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every test here checks the oracle against something other than itself:
+closed forms of the implicit scheme (Sec. II, Eq. 1, Eq. 2, Eq. 5), exact
+properties of the linear weights and gather (Eq. 3, Eq. 4) and of the moment
+sum (Sec. II moment equation), and a brute-force numpy reference that shares
+no cell-index logic and solves the implicit velocity equation by a dense
+linear solve instead of Eq. 2's closed form.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import brute
+from oracle import oracle as O
+from paper_2008_04397_amd import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+G = W.Grid(8, 6, 5)            # small grid, distinct sizes per axis
+F6 = ("ex", "ey", "ez", "bx", "by", "bz")
+
+
+def _rand_fields(g, seed, scale=1.0):
+    r = np.random.default_rng(seed)
+    return {k: r.uniform(-scale, scale, g.nodes) for k in F6}
+
+
+def _close_per_component(a, b, rel):
+    """|a - b| <= rel * max|b| separately for each of the ten moments."""
+    for k in range(a.shape[0]):
+        scale = np.abs(b[k]).max()
+        assert np.abs(a[k] - b[k]).max() <= rel * scale, (k, np.abs(a[k] - b[k]).max(), scale)
+
+
+def _one(x, y, z, u, v, w, q=1.0):
+    return {k: np.array([val], dtype=np.float64)
+            for k, val in zip(("x", "y", "z", "u", "v", "w", "q"), (x, y, z, u, v, w, q))}
+
+
+# --------------------------------------------------------------------- P1
+
+def test_p1_weights_partition_of_unity_and_match_brute():
+    r = np.random.default_rng(1)
+    for _ in range(500):
+        x, y, z = r.uniform(0, G.Lx), r.uniform(0, G.Ly), r.uniform(0, G.Lz)
+        node, w = O.weights(G, x, y, z)
+        assert abs(w.sum() - 1.0) <= 4 * np.finfo(float).eps
+        assert np.all(w >= 0) and np.all(w <= 1)
+        Wb = brute.weights_all(G, x, y, z)
+        dense = np.zeros(G.nodes)
+        np.add.at(dense, node, w)
+        np.testing.assert_allclose(dense, Wb, rtol=0, atol=1e-14)
+
+
+# --------------------------------------------------------------------- P2
+
+def test_p2_uniform_field_is_returned_exactly():
+    f = W.uniform_fields(G, E=(0.3, -1.25, 2.0), B=(1e-3, 7.0, -0.5))
+    r = np.random.default_rng(2)
+    x, y, z = r.uniform(0, G.Lx, 300), r.uniform(0, G.Ly, 300), r.uniform(0, G.Lz, 300)
+    out = O.gather(G, f, x, y, z)
+    ref = np.array([0.3, -1.25, 2.0, 1e-3, 7.0, -0.5])[:, None]
+    np.testing.assert_allclose(out, np.broadcast_to(ref, out.shape), rtol=4e-16, atol=0)
+
+
+# --------------------------------------------------------------------- P3
+
+def test_p3_multilinear_field_reproduced_on_interior_cells():
+    gx, gy, gz = brute.node_coords(G)
+
+    def F(x, y, z):
+        return 0.7 + 1.3 * x - 2.1 * y + 0.4 * z + 0.9 * x * y - 0.6 * x * z + 0.25 * y * z + 0.11 * x * y * z
+
+    f = {k: F(gx, gy, gz) * (i + 1) for i, k in enumerate(F6)}
+    dx, dy, dz = G.d
+    r = np.random.default_rng(3)
+    # interior: the cell must not wrap, so stay below the last node on each axis
+    x = r.uniform(0, (G.nx - 1) * dx, 400)
+    y = r.uniform(0, (G.ny - 1) * dy, 400)
+    z = r.uniform(0, (G.nz - 1) * dz, 400)
+    out = O.gather(G, f, x, y, z)
+    for i in range(6):
+        np.testing.assert_allclose(out[i], F(x, y, z) * (i + 1), rtol=1e-13, atol=1e-13)
+
+
+# --------------------------------------------------------------------- P4
+
+@pytest.mark.parametrize("c", [1.0, 2.5])
+def test_p4_mean_velocity_solves_the_implicit_equation(c):
+    """vbar = (v^n + v^{n+1})/2 satisfies vbar = v^n + beta E + (beta/c) vbar x B."""
+    r = np.random.default_rng(4)
+    E = r.uniform(-0.5, 0.5, 3)
+    B = r.uniform(-2, 2, 3)
+    f = W.uniform_fields(G, E=E, B=B)
+    sp = W.random_particles(G, 200, vth=0.3, seed=4)
+    for qom in (-64.0, 1.0, 3.7):
+        dt = 0.25
+        new = O.mover(G, dt, c, 3, qom, f, sp)
+        v0 = np.stack([sp["u"], sp["v"], sp["w"]], 1)
+        v1 = np.stack([new["u"], new["v"], new["w"]], 1)
+        vbar = 0.5 * (v0 + v1)
+        beta = qom * dt / 2
+        rhs = v0 + beta * E + (beta / c) * np.cross(vbar, B)
+        scale = np.abs(vbar).max() + abs(beta) * np.abs(E).max()
+        assert np.abs(vbar - rhs).max() <= 1e-13 * max(1.0, scale * abs(beta) * np.abs(B).max())
+
+
+# --------------------------------------------------------------------- P5
+
+@pytest.mark.parametrize("qom", [-64.0, 1.0])
+def test_p5_gyration_closed_form(qom):
+    """Uniform B, E = 0: the implicit step is an exact rotation by
+    theta = 2 atan(|qom| |B| dt / (2c)) with sense -sign(qom) about B, around
+    a fixed centre at the Larmor radius |v_perp| c / (|qom| |B|)."""
+    g = W.Grid(16, 16, 16, 40.0, 40.0, 40.0)
+    B0, dt, c = 0.0195, 0.25, 1.0
+    f = W.uniform_fields(g, B=(0.0, 0.0, B0))
+    u0, v0, w0 = 0.03, -0.02, 0.004
+    x0 = np.array([20.0, 20.0, 5.0])
+    sp = _one(*x0, u0, v0, w0)
+    b = abs(qom) * B0 * dt / (2 * c)
+    theta = 2 * math.atan(b)
+    vperp = complex(u0, v0)
+    # closed-form orbit: w_n = w_0 e^{-i s n theta}, s = sign(qom);
+    # x_n = x_0 + dt w_0/(1 + i s b) * (1 - e^{-i s n theta}) / (1 - e^{-i s theta})
+    s = math.copysign(1.0, qom)
+    rot = complex(math.cos(theta), -s * math.sin(theta))
+    r_larmor = abs(vperp) * c / (abs(qom) * B0)
+    centre = complex(x0[0], x0[1]) + dt * vperp / ((1 + 1j * s * b) * (1 - rot))
+    assert abs(abs(centre - complex(x0[0], x0[1])) - r_larmor) <= 1e-12 * r_larmor
+    st = sp
+    for n in range(1, 41):
+        st = O.mover(g, dt, c, 3, qom, f, st)
+        wn = vperp * rot ** n
+        xn = complex(x0[0], x0[1]) + dt * vperp / (1 + 1j * s * b) * (1 - rot ** n) / (1 - rot)
+        assert abs(complex(st["u"][0], st["v"][0]) - wn) <= 1e-13
+        assert abs(complex(st["x"][0], st["y"][0]) - xn) <= 1e-12
+        assert abs(st["w"][0] - w0) <= 1e-15
+        assert abs(st["z"][0] - (x0[2] + n * w0 * dt)) <= 1e-12
+        # speed conserved, radius fixed
+        assert abs(abs(complex(st["u"][0], st["v"][0])) - abs(vperp)) <= 1e-15
+        assert abs(abs(complex(st["x"][0], st["y"][0]) - centre) - r_larmor) <= 1e-10
+
+
+def test_p5_rotation_angle_at_the_small_box_constants():
+    """At B0 = 0.0195, dt = 0.25, qom = -64: theta = 0.30951 rad per step."""
+    b = 64 * 0.0195 * 0.25 / 2
+    assert abs(2 * math.atan(b) - 0.30951) < 5e-6
+
+
+# --------------------------------------------------------------------- P6
+
+@pytest.mark.parametrize("c", [1.0, 3.0])
+def test_p6_exb_drift(c):
+    g = W.Grid(8, 8, 8, 100.0, 100.0, 100.0)
+    E = np.array([0.0, 0.002, 0.0])
+    B = np.array([0.0, 0.0, 0.04])
+    f = W.uniform_fields(g, E=E, B=B)
+    vE = c * np.cross(E, B) / np.dot(B, B)
+    sp = _one(50.0, 50.0, 50.0, *vE)
+    st = sp
+    for n in range(1, 21):
+        st = O.mover(g, 0.25, c, 3, -64.0, f, st)
+        np.testing.assert_allclose([st["u"][0], st["v"][0], st["w"][0]], vE, rtol=0, atol=1e-15)
+        np.testing.assert_allclose([st["x"][0], st["y"][0], st["z"][0]],
+                                   [50.0 + n * 0.25 * vE[0], 50.0 + n * 0.25 * vE[1], 50.0], rtol=0, atol=1e-12)
+
+
+# --------------------------------------------------------------------- P7
+
+def test_p7_parallel_acceleration():
+    g = W.Grid(8, 8, 8, 100.0, 100.0, 100.0)
+    Bhat = np.array([1.0, 2.0, 2.0]) / 3.0
+    E = 0.003 * Bhat
+    B = 0.05 * Bhat
+    f = W.uniform_fields(g, E=E, B=B)
+    v0 = np.array([0.01, -0.02, 0.015])
+    sp = _one(50.0, 50.0, 50.0, *v0)
+    qom, dt = -2.0, 0.25
+    st = sp
+    vpar0 = v0 @ Bhat
+    for n in range(1, 11):
+        st = O.mover(g, dt, 1.0, 3, qom, f, st)
+        vn = np.array([st["u"][0], st["v"][0], st["w"][0]])
+        assert abs(vn @ Bhat - (vpar0 + n * qom * 0.003 * dt)) <= 1e-15
+        vperp = vn - (vn @ Bhat) * Bhat
+        assert abs(np.linalg.norm(vperp) - np.linalg.norm(v0 - vpar0 * Bhat)) <= 1e-15
+
+
+# --------------------------------------------------------------------- P8
+
+def test_p8_iterations_do_not_matter_in_uniform_fields():
+    f = W.uniform_fields(G, E=(0.01, -0.02, 0.005), B=(0.3, 0.1, -0.2))
+    sp = W.random_particles(G, 100, 0.05, seed=8)
+    ref = O.mover(G, 0.25, 1.0, 1, -64.0, f, sp)
+    for niter in (2, 3, 5):
+        out = O.mover(G, 0.25, 1.0, niter, -64.0, f, sp)
+        for k in ("x", "y", "z", "u", "v", "w"):
+            np.testing.assert_allclose(out[k], ref[k], rtol=1e-14, atol=1e-15)
+
+
+# --------------------------------------------------------------------- P9
+
+def test_p9_periodic_shift_and_face_crossing():
+    f = _rand_fields(G, 9, 0.05)
+    sp = W.random_particles(G, 100, 0.05, seed=9)
+    ref = O.mover(G, 0.25, 1.0, 3, -64.0, f, sp)
+    for ax, L in (("x", G.Lx), ("y", G.Ly), ("z", G.Lz)):
+        for sh in (L, -L, 3 * L):
+            sp2 = dict(sp)
+            sp2[ax] = sp[ax] + sh
+            out = O.mover(G, 0.25, 1.0, 3, -64.0, f, sp2)
+            d = (out[ax] - ref[ax] + L / 2) % L - L / 2
+            assert np.abs(d).max() <= 1e-13 * max(1.0, abs(sh))
+            for k in ("u", "v", "w"):
+                np.testing.assert_allclose(out[k], ref[k], rtol=1e-11, atol=1e-15)
+    # a particle a quarter cell below the upper face is 3/4 of the way from
+    # node n-1 to node n (= node 0): weights 1/4 on node n-1, 3/4 on node 0
+    dx = G.d[0]
+    node, w = O.weights(G, G.Lx - dx / 4, 0.0, 0.0)
+    dense = np.zeros(G.nodes)
+    np.add.at(dense, node, w)
+    assert abs(dense[((G.nx - 1) * G.ny) * G.nz] - 0.25) < 1e-15
+    assert abs(dense[0] - 0.75) < 1e-15
+    # x exactly L wraps to 0
+    out = O.mover(G, 0.25, 1.0, 3, 1.0, W.uniform_fields(G), _one(G.Lx - 1e-3, 1.0, 1.0, 1e-3 / 0.25, 0, 0))
+    assert 0.0 <= out["x"][0] < G.Lx
+
+
+# --------------------------------------------------------------------- P10
+
+def test_p10_total_moments_equal_particle_sums():
+    sp = W.random_particles(G, 2000, 0.05, seed=10)
+    m = O.deposit(G, sp)
+    u, v, w, q = sp["u"], sp["v"], sp["w"], sp["q"]
+    tot = [q, q * u, q * v, q * w, q * u * u, q * u * v, q * u * w, q * v * v, q * v * w, q * w * w]
+    for k in range(10):
+        assert abs(m[k].sum() - tot[k].sum()) <= 1e-12 * np.abs(tot[k]).sum()
+
+
+# --------------------------------------------------------------------- P11
+
+def test_p11_node_and_cell_centre_special_cases():
+    dx, dy, dz = G.d
+    # exactly on node (3, 2, 1)
+    node, w = O.weights(G, 3 * dx, 2 * dy, 1 * dz)
+    dense = np.zeros(G.nodes)
+    np.add.at(dense, node, w)
+    assert dense[(3 * G.ny + 2) * G.nz + 1] == 1.0
+    assert np.count_nonzero(dense) == 1
+    # cell centre of cell (3, 2, 1)
+    node, w = O.weights(G, 3.5 * dx, 2.5 * dy, 1.5 * dz)
+    np.testing.assert_allclose(w, 0.125, rtol=0, atol=1e-16)
+    assert len(set(node.tolist())) == 8
+
+
+# --------------------------------------------------------------------- P12
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_p12_brute_force_gather_mover_deposit(seed):
+    g = W.Grid(5, 4, 3, 3.0, 2.0, 1.5)
+    f = _rand_fields(g, 100 + seed, 0.8)
+    sp = W.random_particles(g, 8, 0.2, seed=200 + seed)
+    out = O.gather(g, f, sp["x"], sp["y"], sp["z"])
+    for p in range(8):
+        np.testing.assert_allclose(out[:, p], brute.gather(g, f, sp["x"][p], sp["y"][p], sp["z"][p]),
+                                   rtol=1e-13, atol=1e-14)
+    for qom, c in ((-64.0, 1.0), (1.0, 1.0), (2.0, 0.5)):
+        new = O.mover(g, 0.25, c, 3, qom, f, sp)
+        ref = brute.mover(g, 0.25, c, 3, qom, f, sp)
+        for k in ("x", "y", "z", "u", "v", "w"):
+            np.testing.assert_allclose(new[k], ref[k], rtol=1e-11, atol=1e-13)
+        np.testing.assert_allclose(O.deposit(g, new), brute.deposit(g, ref), rtol=1e-11, atol=1e-13)
+
+
+# --------------------------------------------------------------------- P13
+
+def test_p13_permutation_changes_nothing_but_rounding():
+    h = W.harris_32x16x4()
+    f = W.make_fields(h)
+    sp = W.species_slab(h, W.SHEET_E, 0, 4)
+    perm = np.random.default_rng(13).permutation(sp["x"].size)
+    spp = {k: v[perm] for k, v in sp.items()}
+    a = O.step(h.grid, h.dt, h.c, h.niter, h.qom_e, f, sp)
+    b = O.step(h.grid, h.dt, h.c, h.niter, h.qom_e, f, spp)
+    inv = np.argsort(b[0]["id"])
+    for k in ("x", "y", "z", "u", "v", "w"):
+        assert np.array_equal(a[0][k], b[0][k][inv])
+    _close_per_component(a[1], b[1], 1e-13)
+
+
+# --------------------------------------------------------------------- P14
+
+def test_p14_union_equals_sum_of_parts():
+    """Per species: the deposit of all particles equals the sum of the
+    deposits of any split of them (the basis of particle decomposition)."""
+    h = W.harris_32x16x4()
+    for s in range(4):
+        sp = W.species_slab(h, s, 0, 3)
+        whole = O.deposit(h.grid, sp)
+        parts = np.zeros_like(whole)
+        for sl in np.array_split(np.arange(sp["x"].size), 5):
+            O.deposit(h.grid, {k: v[sl] for k, v in sp.items()}, parts)
+        _close_per_component(parts, whole, 1e-13)
+
+
+# --------------------------------------------------------------------- P15
+
+def test_p15_linearity_in_q_and_mover_independent_of_q():
+    sp = W.random_particles(G, 300, 0.05, seed=15)
+    m1 = O.deposit(G, sp)
+    sp2 = dict(sp)
+    sp2["q"] = sp["q"] * -3.0
+    _close_per_component(O.deposit(G, sp2), -3.0 * m1, 1e-14)
+    f = _rand_fields(G, 15, 0.05)
+    a = O.mover(G, 0.25, 1.0, 3, -64.0, f, sp)
+    b = O.mover(G, 0.25, 1.0, 3, -64.0, f, sp2)
+    for k in ("x", "y", "z", "u", "v", "w"):
+        assert np.array_equal(a[k], b[k])
+
+
+# --------------------------------------------------------------- workload
+
+def test_paper_workload_particle_count():
+    """Sec. IV: 128x64x64 cells, 4 species x 125 ppc, about 2.6E8 particles."""
+    with open(os.path.join(HERE, "golden", "paper_workload.json")) as fh:
+        gold = json.load(fh)
+    h = W.Harris(W.Grid(*gold["cells"]), ppc=gold["ppc"])
+    assert gold["species"] == 4
+    assert W._lattice_side(h.ppc) == 5
+    assert abs(h.n_total - gold["particles_approx"]) / gold["particles_approx"] < 0.01
+    assert abs(h.qom_e / h.qom_i) == gold["charge_to_mass_ratio"]
+    assert h.niter == gold["mover_iterations"]
