@@ -1,0 +1,228 @@
+/*
+ * spic.h -- C ABI of the MI355X (gfx950) implicit particle-in-cell mover and
+ * moment gathering library (libspic.so).
+ *
+ * The method is the implicit PIC particle stage of sputniPIC
+ * (arXiv 2008.04397, Sec. II and Sec. III):
+ *   - per particle, a fixed number of predictor-corrector iterations of the
+ *     implicit mean velocity (Eq. 1, Eq. 2), each gathering E and B at the
+ *     current half-step position with linear weights (Eq. 3, Eq. 4), then the
+ *     update of velocity and position (Eq. 5) in a periodic box;
+ *   - the particle-to-grid moments rho, J and the pressure tensor P of each
+ *     species (Sec. II, moment equation), deposited from the updated state in
+ *     the same pass as the move (Sec. III-B, fused mover and gathering).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every call returns an int status: SPIC_OK (0) or a negative error code.
+ *    No call throws or aborts.  On error, spic_last_error(ctx) returns a
+ *    human-readable message (valid until the next call on that ctx).
+ *  - Argument validation happens on the host before anything is enqueued: a
+ *    call that returns an error has enqueued no work.
+ *  - Device pointers are HIP device addresses on the ctx's device.  All
+ *    particle, field and moment buffers are owned by the caller and must stay
+ *    valid until the enqueued work completes.  The library owns only its
+ *    scratch (sort keys and offsets, staging slots, work lists), allocated
+ *    within the ctx's HBM budget and freed by spic_ctx_destroy.
+ *  - Work is enqueued on the caller's HIP stream (hip_stream, a hipStream_t;
+ *    NULL means the null stream) and the call returns without waiting.
+ *    Faults inside kernels surface at the next synchronisation.
+ *  - Grid: a periodic box [0,Lx) x [0,Ly) x [0,Lz) with nx, ny, nz cells and
+ *    as many distinct nodes per axis, node (i,j,k) at (i*Lx/nx, j*Ly/ny,
+ *    k*Lz/nz) and flat index (i*ny + j)*nz + k.  n_d >= 2 on every axis.
+ *  - Particles (Sec. III-D: structure-of-arrays): one array per coordinate
+ *    x, y, z, velocity u, v, w and charge q, each of n elements of the
+ *    species' dtype, contiguous.  x, y, z, u, v, w are updated in place;
+ *    q is only read by the mover; sorts permute all seven arrays together.
+ *    Positions may lie anywhere; they are wrapped into the box by the mover.
+ *  - Moments: [10][nodes] of the accumulation dtype, in the order rho, Jx,
+ *    Jy, Jz, Pxx, Pxy, Pxz, Pyy, Pyz, Pzz; each entry is the plain sum
+ *    sum_p q {1, v, v (x) v} W over the particles (no volume factor).
+ *  - Units are normalised (Sec. III-C), c = 1 unless the caller says
+ *    otherwise; qom is the species' charge-to-mass ratio q/m.
+ *  - NaN inputs propagate; they are not checked.
+ */
+#ifndef SPIC_H
+#define SPIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPIC_ABI_VERSION 1
+
+/* status codes */
+#define SPIC_OK             0
+#define SPIC_E_ARG         -1  /* NULL pointer, bad size, bad dtype, misalignment     */
+#define SPIC_E_BUDGET      -2  /* the request cannot fit the ctx's HBM budget          */
+#define SPIC_E_HIP         -3  /* HIP runtime error (text in spic_last_error)          */
+#define SPIC_E_UNSUPPORTED -4  /* valid but unsupported combination (e.g. dtypes)      */
+#define SPIC_E_STATE       -5  /* unknown ticket, or a call that does not fit the state */
+
+/* element types */
+#define SPIC_F32 1
+#define SPIC_F64 2
+
+typedef struct spic_ctx_s *spic_ctx;
+
+/* Periodic box (see conventions above). */
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t reserved;   /* must be 0 */
+    double Lx, Ly, Lz;
+} spic_grid;
+
+/* Time step and mover controls.
+ *  dt           time step (Eq. 1, Eq. 2, Eq. 5)
+ *  c            speed of light in the normalised units (Eq. 2); > 0
+ *  niter_mover  predictor-corrector iterations (three in the paper); >= 1
+ *  sort_every   re-sort the particles by cell every sort_every steps
+ *               (Sec. III-A, Sec. VI: sorting restores locality); 0 = never.
+ *               Sorting permutes the particle arrays (and id, if given).
+ *  step         the caller's step counter: a sort runs before the move when
+ *               sort_every > 0 and step % sort_every == 0. */
+typedef struct {
+    double dt;
+    double c;
+    int32_t niter_mover;
+    int32_t sort_every;
+    int64_t step;
+} spic_params;
+
+/* Node-centred E and B (Sec. II, Eq. 4): six device arrays of `nodes`
+ * elements of `dtype`, read only. */
+typedef struct {
+    int32_t dtype;
+    int32_t reserved;   /* must be 0 */
+    const void *ex, *ey, *ez, *bx, *by, *bz;
+} spic_fields;
+
+/* One particle species (Sec. III-B: species are independent streams).
+ *  dtype          SPIC_F32 or SPIC_F64 for x, y, z, u, v, w, q
+ *  host_resident  0: arrays are device memory.  1: arrays are pinned host
+ *                 memory (hipHostMalloc); only spic_batch_submit accepts
+ *                 this, streaming the species through HBM in batches
+ *                 (Sec. III-B, particle batching).
+ *  n              particle count (>= 0; 0 is a no-op)
+ *  qom            charge-to-mass ratio q/m
+ *  id             optional int64 particle ids (may be NULL), permuted
+ *                 together with the particles when they are sorted. */
+typedef struct {
+    int32_t dtype;
+    int32_t host_resident;
+    int64_t n;
+    double qom;
+    void *x, *y, *z, *u, *v, *w;
+    void *q;            /* read by the mover, permuted by sorts */
+    int64_t *id;
+} spic_species;
+
+/* Moment output of one species: a device array [10][nodes].
+ *  acc_dtype  SPIC_F64 (default; accumulation in FP64) or SPIC_F32 (plain
+ *             single precision accumulation, for precision studies). */
+typedef struct {
+    int32_t acc_dtype;
+    int32_t reserved;   /* must be 0 */
+    void *m;
+} spic_moment_array;
+
+/* One multi-step run for spic_batch_submit: nsteps fused steps of every
+ * species with fixed fields; the moments written are those of the last
+ * step.  params.step is the step counter of the first step. */
+typedef struct {
+    spic_grid grid;
+    spic_params params;
+    spic_fields fields;
+    spic_species *species;
+    spic_moment_array *moments;   /* nspecies entries, or NULL for no moments */
+    int32_t nspecies;
+    int32_t nsteps;
+} spic_run;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device` whose library-owned scratch never
+ * exceeds hbm_budget_bytes (0 = no limit).  *out receives the handle.
+ * device = -1 creates a host-only context that makes no HIP call: every
+ * entry point validates its arguments as usual and then, instead of
+ * enqueuing work, returns SPIC_E_STATE (used to check arguments, and for
+ * admission decisions, on machines without a GPU). */
+int spic_ctx_create(int device, uint64_t hbm_budget_bytes, spic_ctx *out);
+
+/* Wait for the ctx's own streams, free all library-owned memory and the
+ * handle.  NULL is accepted. */
+int spic_ctx_destroy(spic_ctx ctx);
+
+/* Message of the last error on ctx (never NULL; "" when none). */
+const char *spic_last_error(spic_ctx ctx);
+
+/* Name of a status code. */
+const char *spic_status_str(int status);
+
+/* SPIC_ABI_VERSION of the library. */
+int spic_version(void);
+
+/* Tuning knobs (block size, kernel path, sort tile shape), keyed by name;
+ * see the implementation for the list.  Unknown keys return SPIC_E_ARG. */
+int spic_set_option(spic_ctx ctx, const char *key, int64_t value);
+int spic_get_option(spic_ctx ctx, const char *key, int64_t *value);
+
+/* ------------------------------------------------------------- hot path */
+
+/* One implicit step of nsp species (Sec. II: Eq. 1-5), fused with the
+ * moment gathering of the moved particles when mom != NULL (Sec. III-B).
+ *  grid, params, fields  as above; fields.dtype must equal the particles'
+ *                        dtype, or be SPIC_F64 with SPIC_F32 particles
+ *  sp[nsp]               species, device resident, updated in place (and
+ *                        permuted when a sort runs, see spic_params)
+ *  mom                   NULL (move only) or nsp moment outputs; each is
+ *                        overwritten with the moments of the new state
+ *  hip_stream            stream to enqueue on
+ * Errors: SPIC_E_ARG (validation), SPIC_E_UNSUPPORTED (dtype combination),
+ * SPIC_E_BUDGET (sort scratch does not fit), SPIC_E_HIP (launch failure). */
+int spic_mover(spic_ctx ctx, const spic_grid *grid, const spic_params *params,
+               const spic_fields *fields, spic_species *sp, int32_t nsp,
+               spic_moment_array *mom, void *hip_stream);
+
+/* Moments of nsp species from their current state (Sec. II, moment
+ * equation), without moving them.  Overwrites mom[s] unless accumulate != 0,
+ * in which case the moments are added to what mom[s] holds. */
+int spic_moments(spic_ctx ctx, const spic_grid *grid, const spic_species *sp, int32_t nsp,
+                 spic_moment_array *mom, int32_t accumulate, void *hip_stream);
+
+/* Sort the particles of nsp species by cell (Sec. III-A: ordering particles
+ * by position restores the locality of the field and moment accesses).
+ * Permutes x, y, z, u, v, w, q and id (when given) together; the
+ * per-particle state is unchanged, only its order. */
+int spic_sort(spic_ctx ctx, const spic_grid *grid, spic_species *sp, int32_t nsp,
+              void *hip_stream);
+
+/* ---------------------------------------------------------------- batches */
+
+/* Submit nruns independent multi-step runs (Sec. III-B, particle batching):
+ * runs whose species are device resident are executed together, step by
+ * step, in one launch per step over all their (run, species, tile) work
+ * items; runs with host_resident species are streamed through HBM in
+ * batches on two streams (copy of the next batch overlapping the kernel on
+ * the current one) within the ctx's budget.  Work runs on the ctx's own
+ * streams; tickets_out[i] identifies run i.  The caller's arrays must stay
+ * valid until the ticket completes.
+ * Errors: SPIC_E_ARG, SPIC_E_BUDGET (a run cannot fit even when streamed),
+ * SPIC_E_UNSUPPORTED, SPIC_E_HIP. */
+int spic_batch_submit(spic_ctx ctx, const spic_run *runs, int32_t nruns, uint64_t *tickets_out);
+
+/* Block until the ticket's run is complete; device_seconds_out (may be
+ * NULL) receives the device time of the run.  SPIC_E_STATE for an unknown
+ * ticket. */
+int spic_wait(spic_ctx ctx, uint64_t ticket, double *device_seconds_out);
+
+/* *done = 1 when the ticket's run is complete, else 0. */
+int spic_poll(spic_ctx ctx, uint64_t ticket, int32_t *done);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPIC_H */

@@ -1,0 +1,64 @@
+// spic_ctx.h -- the library context behind the opaque spic_ctx handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+
+#include "spic_impl.h"
+
+namespace spic {
+struct BatchEngine;  // spic_batch.hip
+}
+
+struct spic_ctx_s {
+    struct Scratch {
+        void *ptr = nullptr;
+        size_t bytes = 0;
+    };
+
+    int device = 0;        // -1: host-only context (validation only)
+    uint64_t budget = 0;   // 0 = unlimited
+    uint64_t used = 0;     // bytes of library scratch currently allocated
+    std::string err;
+    std::mutex mu;         // serialises the ABI calls on one ctx
+    std::map<std::string, int64_t> options;
+    std::map<std::string, Scratch> scratch;
+    std::unique_ptr<spic::BatchEngine> batch;
+
+    spic_ctx_s();
+    ~spic_ctx_s();
+
+    int fail(int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+    int hip(hipError_t e, const char *what);
+    int host_only();
+
+    int check_grid(const spic_grid *g);
+    int check_params(const spic_params *p);
+    int check_fields(const spic_fields *f);
+    int check_species(const spic_species *sp, int32_t nsp, bool allow_host);
+    int check_moments(const spic_moment_array *m, const spic_species *sp, int32_t nsp);
+    int check_combo(const spic_fields *f, const spic_species *sp, int32_t nsp);
+
+    // scratch owned by the library, within the budget; `tag` names a slot
+    // that is grown on demand and reused across calls
+    int reserve(const char *tag, size_t bytes, void **out);
+    void release_all();
+
+    int64_t opt(const char *k, int64_t dflt) const;
+    spic::LaunchCfg launch_cfg() const;
+
+    // operations (validated arguments, device already current)
+    int mover(const spic_grid &g, const spic_params &p, const spic_fields &f, spic_species *sp, int32_t nsp,
+              spic_moment_array *mom, hipStream_t s);
+    int moments(const spic_grid &g, const spic_species *sp, int32_t nsp, spic_moment_array *mom, bool accumulate,
+                hipStream_t s);
+    int sort(const spic_grid &g, spic_species *sp, int32_t nsp, hipStream_t s);
+    int batch_submit(const spic_run *runs, int32_t nruns, uint64_t *tickets);
+    int wait(uint64_t ticket, double *secs);
+    int poll(uint64_t ticket, int32_t *done);
+    void shutdown();
+};

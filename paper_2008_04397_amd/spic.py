@@ -1,0 +1,287 @@
+"""Python binding of libspic.so (include/spic.h), argument marshalling only.
+
+Every function keeps the C name and forwards to the library; all arithmetic
+of the mover, the moment gathering and the sort runs in the HIP kernels.
+Device memory and streams come from PyTorch (torch tensors on a HIP device,
+``torch.cuda.Stream``).  If the library is not built, importing the functions
+works but the first call raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libspic.so")
+
+SPIC_OK, SPIC_E_ARG, SPIC_E_BUDGET, SPIC_E_HIP, SPIC_E_UNSUPPORTED, SPIC_E_STATE = 0, -1, -2, -3, -4, -5
+SPIC_F32, SPIC_F64 = 1, 2
+
+EXPORTED = ("spic_ctx_create", "spic_ctx_destroy", "spic_last_error", "spic_status_str", "spic_version",
+            "spic_set_option", "spic_get_option", "spic_mover", "spic_moments", "spic_sort",
+            "spic_batch_submit", "spic_wait", "spic_poll")
+
+
+class SpicError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s (%d): %s" % (_status_name(status), status, message))
+        self.status = status
+        self.message = message
+
+
+class spic_grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("reserved", C.c_int32),
+                ("Lx", C.c_double), ("Ly", C.c_double), ("Lz", C.c_double)]
+
+
+class spic_params(C.Structure):
+    _fields_ = [("dt", C.c_double), ("c", C.c_double), ("niter_mover", C.c_int32), ("sort_every", C.c_int32),
+                ("step", C.c_int64)]
+
+
+class spic_fields(C.Structure):
+    _fields_ = [("dtype", C.c_int32), ("reserved", C.c_int32)] + [(k, C.c_void_p) for k in
+                                                                   ("ex", "ey", "ez", "bx", "by", "bz")]
+
+
+class spic_species(C.Structure):
+    _fields_ = ([("dtype", C.c_int32), ("host_resident", C.c_int32), ("n", C.c_int64), ("qom", C.c_double)]
+                + [(k, C.c_void_p) for k in ("x", "y", "z", "u", "v", "w", "q")] + [("id", C.c_void_p)])
+
+
+class spic_moment_array(C.Structure):
+    _fields_ = [("acc_dtype", C.c_int32), ("reserved", C.c_int32), ("m", C.c_void_p)]
+
+
+class spic_run(C.Structure):
+    _fields_ = [("grid", spic_grid), ("params", spic_params), ("fields", spic_fields),
+                ("species", C.POINTER(spic_species)), ("moments", C.POINTER(spic_moment_array)),
+                ("nspecies", C.c_int32), ("nsteps", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libspic.so is not built (%s); run `python -m paper_2008_04397_amd.build`"
+                               % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.spic_ctx_create.argtypes = [C.c_int, C.c_uint64, C.POINTER(vp)]
+        L.spic_ctx_destroy.argtypes = [vp]
+        L.spic_last_error.argtypes = [vp]
+        L.spic_last_error.restype = C.c_char_p
+        L.spic_status_str.argtypes = [C.c_int]
+        L.spic_status_str.restype = C.c_char_p
+        L.spic_version.argtypes = []
+        L.spic_set_option.argtypes = [vp, C.c_char_p, C.c_int64]
+        L.spic_get_option.argtypes = [vp, C.c_char_p, C.POINTER(C.c_int64)]
+        L.spic_mover.argtypes = [vp, C.POINTER(spic_grid), C.POINTER(spic_params), C.POINTER(spic_fields),
+                                 C.POINTER(spic_species), C.c_int32, C.POINTER(spic_moment_array), vp]
+        L.spic_moments.argtypes = [vp, C.POINTER(spic_grid), C.POINTER(spic_species), C.c_int32,
+                                   C.POINTER(spic_moment_array), C.c_int32, vp]
+        L.spic_sort.argtypes = [vp, C.POINTER(spic_grid), C.POINTER(spic_species), C.c_int32, vp]
+        L.spic_batch_submit.argtypes = [vp, C.POINTER(spic_run), C.c_int32, C.POINTER(C.c_uint64)]
+        L.spic_wait.argtypes = [vp, C.c_uint64, C.POINTER(C.c_double)]
+        L.spic_poll.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int32)]
+        for f in EXPORTED:
+            if f not in ("spic_last_error", "spic_status_str"):
+                getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _status_name(st: int) -> str:
+    try:
+        return lib().spic_status_str(st).decode()
+    except Exception:
+        return str(st)
+
+
+# ------------------------------------------------------------------ helpers
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _dtype_code(t) -> int:
+    import torch
+    dt = t.dtype
+    if dt in (torch.float32, np.float32):
+        return SPIC_F32
+    if dt in (torch.float64, np.float64):
+        return SPIC_F64
+    raise ValueError("unsupported dtype %s" % dt)
+
+
+def make_grid(g) -> spic_grid:
+    return spic_grid(int(g.nx), int(g.ny), int(g.nz), 0, float(g.Lx), float(g.Ly), float(g.Lz))
+
+
+def make_params(dt: float, c: float = 1.0, niter: int = 3, sort_every: int = 0, step: int = 0) -> spic_params:
+    return spic_params(float(dt), float(c), int(niter), int(sort_every), int(step))
+
+
+def make_fields(f: Dict[str, "object"]) -> spic_fields:
+    code = _dtype_code(f["ex"])
+    return spic_fields(code, 0, *[_ptr(f[k]) for k in ("ex", "ey", "ez", "bx", "by", "bz")])
+
+
+def make_species(sp: Dict[str, "object"], qom: float, host_resident: bool = False) -> spic_species:
+    n = int(sp["x"].numel() if hasattr(sp["x"], "numel") else sp["x"].size)
+    return spic_species(_dtype_code(sp["x"]), int(bool(host_resident)), n, float(qom),
+                        *[_ptr(sp[k]) for k in ("x", "y", "z", "u", "v", "w", "q")], _ptr(sp.get("id")))
+
+
+def make_moments(m) -> spic_moment_array:
+    return spic_moment_array(_dtype_code(m), 0, _ptr(m))
+
+
+def _arr(ctype, items):
+    items = list(items)
+    return (ctype * max(1, len(items)))(*items)
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ------------------------------------------------------------------ context
+
+class Context:
+    """Owns a spic_ctx handle (device, HBM budget for library scratch)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        h = C.c_void_p()
+        st = lib().spic_ctx_create(int(device), int(hbm_budget_bytes), C.byref(h))
+        if st != SPIC_OK:
+            raise SpicError(st, "spic_ctx_create(device=%d)" % device)
+        self.handle = h
+        self.device = device
+
+    def check(self, st: int):
+        if st != SPIC_OK:
+            raise SpicError(st, lib().spic_last_error(self.handle).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().spic_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_option(self, key: str, value: int):
+        return self.check(lib().spic_set_option(self.handle, key.encode(), int(value)))
+
+    def get_option(self, key: str) -> int:
+        v = C.c_int64()
+        self.check(lib().spic_get_option(self.handle, key.encode(), C.byref(v)))
+        return v.value
+
+
+def spic_ctx_create(device: int = 0, hbm_budget_bytes: int = 0) -> Context:
+    return Context(device, hbm_budget_bytes)
+
+
+def spic_ctx_destroy(ctx: Context):
+    ctx.close()
+
+
+def spic_version() -> int:
+    return int(lib().spic_version())
+
+
+def spic_status_str(st: int) -> str:
+    return lib().spic_status_str(int(st)).decode()
+
+
+def spic_mover(ctx: Context, grid, params: spic_params, fields, species: Sequence[dict], qoms: Sequence[float],
+               moments: Optional[Sequence] = None, stream=None, raw: bool = False) -> int:
+    """One fused step of every species (moments overwritten when given)."""
+    g = make_grid(grid)
+    f = make_fields(fields)
+    sp = _arr(spic_species, [make_species(s, q) for s, q in zip(species, qoms)])
+    mom = _arr(spic_moment_array, [make_moments(m) for m in moments]) if moments is not None else None
+    st = lib().spic_mover(ctx.handle, C.byref(g), C.byref(params), C.byref(f), sp, len(species), mom,
+                          _stream(stream))
+    return st if raw else ctx.check(st)
+
+
+def spic_moments(ctx: Context, grid, species: Sequence[dict], moments: Sequence, accumulate: bool = False,
+                 stream=None, qoms: Optional[Sequence[float]] = None, raw: bool = False) -> int:
+    g = make_grid(grid)
+    qoms = list(qoms) if qoms is not None else [0.0] * len(species)
+    sp = _arr(spic_species, [make_species(s, q) for s, q in zip(species, qoms)])
+    mom = _arr(spic_moment_array, [make_moments(m) for m in moments])
+    st = lib().spic_moments(ctx.handle, C.byref(g), sp, len(species), mom, int(bool(accumulate)), _stream(stream))
+    return st if raw else ctx.check(st)
+
+
+def spic_sort(ctx: Context, grid, species: Sequence[dict], stream=None, raw: bool = False) -> int:
+    g = make_grid(grid)
+    sp = _arr(spic_species, [make_species(s, 0.0) for s in species])
+    st = lib().spic_sort(ctx.handle, C.byref(g), sp, len(species), _stream(stream))
+    return st if raw else ctx.check(st)
+
+
+def spic_wait(ctx: Context, ticket: int) -> float:
+    secs = C.c_double()
+    ctx.check(lib().spic_wait(ctx.handle, int(ticket), C.byref(secs)))
+    return secs.value
+
+
+def spic_poll(ctx: Context, ticket: int) -> bool:
+    done = C.c_int32()
+    ctx.check(lib().spic_poll(ctx.handle, int(ticket), C.byref(done)))
+    return bool(done.value)
+
+
+# --------------------------------------------------------- tensor helpers
+
+def to_device(arrs: Dict[str, np.ndarray], dtype, device="cuda") -> Dict[str, "object"]:
+    """Copy a dict of numpy arrays to device tensors (floats cast to dtype)."""
+    import torch
+    out = {}
+    for k, v in arrs.items():
+        t = torch.from_numpy(np.ascontiguousarray(v))
+        if t.is_floating_point():
+            t = t.to(dtype)
+        out[k] = t.to(device)
+    return out
+
+
+def to_host(arrs: Dict[str, "object"]) -> Dict[str, np.ndarray]:
+    return {k: v.detach().cpu().numpy() for k, v in arrs.items()}
+
+
+def moment_buffers(grid, nsp: int, dtype=None, device="cuda"):
+    import torch
+    dtype = dtype or torch.float64
+    return [torch.zeros((10, grid.nx * grid.ny * grid.nz), dtype=dtype, device=device) for _ in range(nsp)]

@@ -1,0 +1,123 @@
+"""The C ABI on the CPU: the library loads, exports every declared entry
+point, and validates arguments (through a host-only context, device -1,
+which makes no HIP call)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2008_04397_amd import spic
+from paper_2008_04397_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "spic.h")) as fh:
+        txt = fh.read()
+    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(spic_\w+)\s*\(", txt, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = spic.lib()
+    names = _declared()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(spic.EXPORTED)
+
+
+def test_version_and_status_strings():
+    assert spic.spic_version() == 1
+    assert spic.spic_status_str(0) == "SPIC_OK"
+    assert spic.spic_status_str(-2) == "SPIC_E_BUDGET"
+    assert spic.spic_status_str(-99) == "SPIC_E_UNKNOWN"
+
+
+def test_null_ctx_is_rejected():
+    L = spic.lib()
+    assert L.spic_mover(None, None, None, None, None, 0, None, None) == spic.SPIC_E_ARG
+    assert L.spic_set_option(None, b"block", 256) == spic.SPIC_E_ARG
+    assert L.spic_ctx_destroy(None) == spic.SPIC_OK
+
+
+class _HostArrays:
+    """Aligned host arrays standing in for device pointers (never touched:
+    a host-only context only validates)."""
+
+    def __init__(self, n=16, nn=8 * 8 * 8, dtype=np.float64):
+        self.sp = {k: np.zeros(n, dtype) for k in ("x", "y", "z", "u", "v", "w", "q")}
+        self.f = {k: np.zeros(nn, dtype) for k in ("ex", "ey", "ez", "bx", "by", "bz")}
+        self.m = np.zeros((10, nn), np.float64)
+
+
+@pytest.fixture
+def hctx():
+    ctx = spic.Context(-1, 1 << 20)
+    yield ctx
+    ctx.close()
+
+
+def _call(ctx, grid, params, arrs, qom=-64.0, moments=True, mutate=None):
+    g = spic.make_grid(grid)
+    f = spic.make_fields(arrs.f)
+    sp = spic.make_species(arrs.sp, qom)
+    m = spic.make_moments(arrs.m)
+    if mutate:
+        mutate(g, params, f, sp, m)
+    return spic.lib().spic_mover(ctx.handle, C.byref(g), C.byref(params), C.byref(f), C.byref(sp), 1,
+                                 C.byref(m) if moments else None, None)
+
+
+def test_valid_arguments_reach_the_host_only_stop(hctx):
+    a = _HostArrays()
+    st = _call(hctx, W.Grid(8, 8, 8), spic.make_params(0.25), a)
+    assert st == spic.SPIC_E_STATE
+    assert "host-only" in spic.lib().spic_last_error(hctx.handle).decode()
+
+
+@pytest.mark.parametrize("what,mut,code", [
+    ("nx<2", lambda g, p, f, s, m: setattr(g, "nx", 1), spic.SPIC_E_ARG),
+    ("L<=0", lambda g, p, f, s, m: setattr(g, "Ly", 0.0), spic.SPIC_E_ARG),
+    ("reserved", lambda g, p, f, s, m: setattr(g, "reserved", 1), spic.SPIC_E_ARG),
+    ("niter 0", lambda g, p, f, s, m: setattr(p, "niter_mover", 0), spic.SPIC_E_ARG),
+    ("c<=0", lambda g, p, f, s, m: setattr(p, "c", 0.0), spic.SPIC_E_ARG),
+    ("dt nan", lambda g, p, f, s, m: setattr(p, "dt", float("nan")), spic.SPIC_E_ARG),
+    ("sort<0", lambda g, p, f, s, m: setattr(p, "sort_every", -1), spic.SPIC_E_ARG),
+    ("n<0", lambda g, p, f, s, m: setattr(s, "n", -1), spic.SPIC_E_ARG),
+    ("null x", lambda g, p, f, s, m: setattr(s, "x", None), spic.SPIC_E_ARG),
+    ("misaligned", lambda g, p, f, s, m: setattr(s, "u", s.u + 4), spic.SPIC_E_ARG),
+    ("bad dtype", lambda g, p, f, s, m: setattr(s, "dtype", 7), spic.SPIC_E_ARG),
+    ("null field", lambda g, p, f, s, m: setattr(f, "bz", None), spic.SPIC_E_ARG),
+    ("host resident", lambda g, p, f, s, m: setattr(s, "host_resident", 1), spic.SPIC_E_ARG),
+    ("f64 parts f32 fields", lambda g, p, f, s, m: setattr(f, "dtype", spic.SPIC_F32), spic.SPIC_E_UNSUPPORTED),
+    ("f64 parts f32 acc", lambda g, p, f, s, m: setattr(m, "acc_dtype", spic.SPIC_F32), spic.SPIC_E_UNSUPPORTED),
+    ("null moments", lambda g, p, f, s, m: setattr(m, "m", None), spic.SPIC_E_ARG),
+])
+def test_invalid_arguments_are_rejected_before_any_work(hctx, what, mut, code):
+    a = _HostArrays()
+    st = _call(hctx, W.Grid(8, 8, 8), spic.make_params(0.25), a, mutate=mut)
+    assert st == code, (what, spic.lib().spic_last_error(hctx.handle))
+
+
+def test_empty_species_is_valid(hctx):
+    a = _HostArrays(n=0)
+    assert _call(hctx, W.Grid(8, 8, 8), spic.make_params(0.25), a) == spic.SPIC_E_STATE
+
+
+def test_options(hctx):
+    hctx.set_option("block", 128)
+    assert hctx.get_option("block") == 128
+    with pytest.raises(spic.SpicError):
+        hctx.set_option("block", 100)
+    with pytest.raises(spic.SpicError):
+        hctx.set_option("no_such_knob", 1)
+
+
+def test_python_binding_refuses_to_run_without_the_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(spic, "_lib", None)
+    monkeypatch.setattr(spic, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        spic.lib()
