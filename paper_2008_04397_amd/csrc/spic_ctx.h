@@ -29,6 +29,18 @@ struct spic_ctx_s {
     std::map<std::string, Scratch> scratch;
     std::unique_ptr<spic::BatchEngine> batch;
 
+    // Sort layout of a species, keyed by its x array, count, dtype and
+    // grid: the tile geometry and the per-tile particle ranges (a scratch
+    // slot) written by the last sort.  The tiled path uses them; they only
+    // steer work to workgroups, so a stale layout is still correct.
+    struct Layout {
+        spic::TileGeom tg;
+        std::string slot;
+    };
+    std::map<std::string, Layout> layouts;
+    std::string layout_key(const spic_grid &g, const spic_species &s) const;
+    spic::TileGeom tile_geom(const spic_grid &g) const;
+
     spic_ctx_s();
     ~spic_ctx_s();
 

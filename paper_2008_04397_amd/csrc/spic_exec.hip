@@ -2,6 +2,10 @@
 // and the sort, on validated arguments.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdio>
+#include <string>
+
 #include "spic_ctx.h"
 #include "spic_impl.h"
 
@@ -24,6 +28,19 @@ static SpeciesWork work_of(const spic_species &s, const spic_moment_array *m) {
     return w;
 }
 
+std::string spic_ctx_s::layout_key(const spic_grid &g, const spic_species &s) const {
+    char buf[160];
+    snprintf(buf, sizeof buf, "%p/%lld/%d/%d.%d.%d", s.x, (long long)s.n, s.dtype, g.nx, g.ny, g.nz);
+    return buf;
+}
+
+TileGeom spic_ctx_s::tile_geom(const spic_grid &g) const {
+    return make_tile_geom(g, (int)opt("tile_x", 4), (int)opt("tile_y", 4), (int)opt("tile_z", 4),
+                          (int)opt("halo", 1));
+}
+
+static constexpr size_t kMaxLds = 64 * 1024;
+
 int spic_ctx_s::mover(const spic_grid &g, const spic_params &p, const spic_fields &f, spic_species *sp,
                       int32_t nsp, spic_moment_array *mom, hipStream_t s) {
     const int64_t nn = (int64_t)g.nx * g.ny * g.nz;
@@ -32,13 +49,27 @@ int spic_ctx_s::mover(const spic_grid &g, const spic_params &p, const spic_field
         int rc = sort(g, sp, nsp, s);
         if (rc) return rc;
     }
+    const bool generic_only = opt("path", 0) == 1;
     for (int i = 0; i < nsp; ++i) {
         SpeciesWork w = work_of(sp[i], mom ? &mom[i] : nullptr);
         if (w.mom) {
             int rc = hip(launch_fill(w.mom, w.acc_dtype, 10 * nn, s), "zero moments");
             if (rc) return rc;
         }
-        int rc = hip(launch_fused_generic(g, p, f, w, cfg, s), "fused mover");
+        const Layout *lay = nullptr;
+        if (!generic_only) {
+            auto it = layouts.find(layout_key(g, sp[i]));
+            if (it != layouts.end() && tiled_lds_bytes(it->second.tg, w.dtype, w.acc_dtype) <= kMaxLds)
+                lay = &it->second;
+        }
+        int rc;
+        if (lay) {
+            void *toff = nullptr;
+            if ((rc = reserve(lay->slot.c_str(), (size_t)(lay->tg.ntiles + 1) * 4, &toff))) return rc;
+            rc = hip(launch_fused_tiled(g, p, f, w, lay->tg, (const uint32_t *)toff, cfg, s), "fused mover (tiled)");
+        } else {
+            rc = hip(launch_fused_generic(g, p, f, w, cfg, s), "fused mover");
+        }
         if (rc) return rc;
     }
     return SPIC_OK;
@@ -57,8 +88,28 @@ int spic_ctx_s::moments(const spic_grid &g, const spic_species *sp, int32_t nsp,
     return SPIC_OK;
 }
 
-int spic_ctx_s::sort(const spic_grid &, spic_species *, int32_t, hipStream_t) {
-    return fail(SPIC_E_UNSUPPORTED, "sort is not built yet");
+int spic_ctx_s::sort(const spic_grid &g, spic_species *sp, int32_t nsp, hipStream_t s) {
+    const TileGeom tg = tile_geom(g);
+    if (tg.cells < 1 || tg.cells > 64 || tg.halo < 0 || tg.halo > 8)
+        return fail(SPIC_E_ARG, "tile shape %dx%dx%d (halo %d): a tile holds 1..64 cells, halo 0..8", tg.tx, tg.ty,
+                    tg.tz, tg.halo);
+    size_t need = 0;
+    for (int i = 0; i < nsp; ++i) {
+        if (sp[i].n >= ((int64_t)1 << 31)) return fail(SPIC_E_UNSUPPORTED, "species %d: sort needs n < 2^31", i);
+        need = std::max(need, sort_scratch_bytes(sp[i].n, sp[i].dtype, sp[i].id != nullptr, tg));
+    }
+    for (int i = 0; i < nsp; ++i) {
+        const std::string key = layout_key(g, sp[i]);
+        const std::string slot = "tileoff:" + key;
+        void *toff = nullptr, *scr = nullptr;
+        int rc;
+        if ((rc = reserve(slot.c_str(), (size_t)(tg.ntiles + 1) * 4, &toff))) return rc;
+        if ((rc = reserve("sort", need, &scr))) return rc;
+        SpeciesWork w = work_of(sp[i], nullptr);
+        if ((rc = hip(launch_sort(g, w, tg, scr, (uint32_t *)toff, s), "sort"))) return rc;
+        layouts[key] = Layout{tg, slot};
+    }
+    return SPIC_OK;
 }
 
 int spic_ctx_s::batch_submit(const spic_run *, int32_t, uint64_t *) {

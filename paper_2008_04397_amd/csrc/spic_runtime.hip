@@ -181,9 +181,12 @@ void spic_ctx_s::release_all() {
 // ------------------------------------------------------------------ options
 
 static const char *const kOptionNames[] = {
-    "block",        // threads per block of the fused kernels
+    "block",        // threads per block of the generic kernels
     "grid_cap",     // cap on blocks of the grid-stride kernels
-    "path",         // 0 auto, 1 generic (global gather + global atomics), 2 tiled
+    "path",         // 0 auto (tiled for sorted species), 1 generic only
+    "tile_block",   // threads per block of the tiled fused kernel
+    "tile_x", "tile_y", "tile_z",  // sort tile shape in cells (product <= 64)
+    "halo",         // cells of halo staged around a tile
 };
 
 int64_t spic_ctx_s::opt(const char *k, int64_t dflt) const {
@@ -195,6 +198,7 @@ LaunchCfg spic_ctx_s::launch_cfg() const {
     LaunchCfg c;
     c.block = (int)opt("block", 256);
     c.grid_cap = (int)opt("grid_cap", 1 << 20);
+    c.tile_block = (int)opt("tile_block", 256);
     return c;
 }
 
@@ -255,8 +259,15 @@ int spic_set_option(spic_ctx ctx, const char *key, int64_t value) {
                 return ctx->fail(SPIC_E_ARG, "block must be a multiple of 64 in [64, 1024]");
             if (!strcmp(key, "grid_cap") && (value < 1 || value > (1 << 24)))
                 return ctx->fail(SPIC_E_ARG, "grid_cap must be in [1, 2^24]");
-            if (!strcmp(key, "path") && (value < 0 || value > 2))
-                return ctx->fail(SPIC_E_ARG, "path must be 0, 1 or 2");
+            if (!strcmp(key, "path") && (value < 0 || value > 1))
+                return ctx->fail(SPIC_E_ARG, "path must be 0 (auto) or 1 (generic)");
+            if (!strcmp(key, "tile_block") && (value < 64 || value > 512 || value % 64))
+                return ctx->fail(SPIC_E_ARG, "tile_block must be a multiple of 64 in [64, 512]");
+            if ((!strcmp(key, "tile_x") || !strcmp(key, "tile_y") || !strcmp(key, "tile_z")) &&
+                (value < 1 || value > 64))
+                return ctx->fail(SPIC_E_ARG, "tile sizes must be in [1, 64]");
+            if (!strcmp(key, "halo") && (value < 0 || value > 8))
+                return ctx->fail(SPIC_E_ARG, "halo must be in [0, 8]");
             ctx->options[key] = value;
             return SPIC_OK;
         }

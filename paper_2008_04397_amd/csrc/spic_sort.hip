@@ -1,0 +1,318 @@
+// spic_sort.hip -- counting sort of particles by cell (Sec. III-A and
+// Sec. VI: periodic ordering of particles by their cell restores the
+// locality of the field and moment accesses).
+//
+// Key order.  Cells are grouped in tiles of TX x TY x TZ cells (at most 64
+// cells), tiles in flat (tx, ty, tz) order.  Within a tile the particles are
+// laid out *rank-major*: first the rank-0 particle of every non-empty cell
+// (cells in local order), then the rank-1 particles, and so on.  Consecutive
+// particles therefore sit in different cells, so one wave of the tiled
+// fused kernel deposits into 64 different cells' nodes and its LDS atomics
+// do not collide; the per-tile particle ranges are what the tiled kernel
+// distributes over workgroups.
+//
+// Passes (all on the caller's stream):
+//   1 key:     cell key of every particle; rank within its cell from a
+//              wave-aggregated atomic histogram
+//   2 scan:    exclusive prefix of the per-key counts (three kernels)
+//   3 scatter: particle -> scratch at offset[key] + rank (cell-major)
+//   4 tile:    scratch -> caller arrays, rank-major inside each tile
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "spic_device.h"
+#include "spic_impl.h"
+
+namespace spic {
+
+// ----------------------------------------------------------------- keys
+
+template <typename T>
+__device__ __forceinline__ int sort_locate(T s, T L, T invL, T invd, int n) {
+    T xi;
+    return plocate(s, L, invL, invd, n, xi);
+}
+
+__device__ __forceinline__ uint32_t tile_key(const TileGeom &tg, int i, int j, int k) {
+    const int tx = i / tg.tx, ty = j / tg.ty, tz = k / tg.tz;
+    const int li = i - tx * tg.tx, lj = j - ty * tg.ty, lk = k - tz * tg.tz;
+    const uint32_t tile = (uint32_t)((tx * tg.nty + ty) * tg.ntz + tz);
+    return tile * (uint32_t)tg.cells + (uint32_t)((li * tg.ty + lj) * tg.tz + lk);
+}
+
+// Key of every particle and its rank inside its key.  Lanes holding the
+// same key as their left neighbour form a segment; the segment head adds the
+// segment length to the global count and the other lanes take consecutive
+// ranks.  On (nearly) sorted input this turns ~64 same-address atomics into
+// one or two per wave.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sort_keys(GridT<T> g, TileGeom tg, const T *__restrict__ x, const T *__restrict__ y,
+            const T *__restrict__ z, int64_t n, uint32_t *__restrict__ counts, uint2 *__restrict__ keyrank) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = base + threadIdx.x;
+        const bool valid = p < n;
+        uint32_t key = 0xFFFFFFFFu;
+        if (valid) {
+            const int i = sort_locate(x[p], g.L[0], g.invL[0], g.invd[0], g.nx);
+            const int j = sort_locate(y[p], g.L[1], g.invL[1], g.invd[1], g.ny);
+            const int k = sort_locate(z[p], g.L[2], g.invL[2], g.invd[2], g.nz);
+            key = tile_key(tg, i, j, k);
+        }
+        const uint32_t prev = __shfl_up(key, 1, 64);
+        const bool head = valid && (lane == 0 || prev != key);
+        const uint64_t heads = __ballot(head);
+        const uint64_t validm = __ballot(valid);
+        // start of my segment: highest head at or below my lane
+        const uint64_t below_incl = heads & ((lane == 63) ? ~0ull : ((2ull << lane) - 1));
+        const int start = below_incl ? 63 - __clzll(below_incl) : 0;
+        // end of my segment: next head above me, or end of valid lanes
+        const uint64_t above = (lane == 63) ? 0ull : (heads & ~((2ull << lane) - 1));
+        const int vend = 64 - __clzll(validm);  // one past last valid lane
+        const int end = above ? __ffsll((long long)above) - 1 : vend;
+        uint32_t old = 0;
+        if (head) old = atomicAdd(counts + key, (uint32_t)(end - start));
+        const uint32_t seg_old = __shfl(old, start, 64);
+        if (valid) keyrank[p] = make_uint2(key, seg_old + (uint32_t)(lane - start));
+    }
+}
+
+// ----------------------------------------------------------------- scan
+
+constexpr int SCAN_BLOCK = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_CHUNK = SCAN_BLOCK * SCAN_ITEMS;  // keys per block
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan of one value per thread across the block; returns the
+// exclusive prefix and writes the block total to *total.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh, uint32_t *total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint32_t incl = wave_incl_scan(v);
+    if (lane == 63) sh[wv] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int w = 0; w < nw; ++w) {
+            const uint32_t t = sh[w];
+            sh[w] = acc;
+            acc += t;
+        }
+        sh[nw] = acc;
+    }
+    __syncthreads();
+    const uint32_t r = sh[wv] + incl - v;
+    *total = sh[nw];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(SCAN_BLOCK)
+k_scan_partials(const uint32_t *__restrict__ counts, int64_t nkeys, uint32_t *__restrict__ partial) {
+    __shared__ uint32_t sh[SCAN_BLOCK / 64 + 1];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i)
+        if (base + i < nkeys) s += counts[base + i];
+    uint32_t total;
+    (void)block_excl_scan(s, sh, &total);
+    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+// One block scans the per-chunk totals in place (exclusive).
+__global__ void __launch_bounds__(1024) k_scan_top(uint32_t *__restrict__ partial, int nparts) {
+    __shared__ uint32_t sh[1024 / 64 + 1];
+    uint32_t carry = 0;
+    for (int b = 0; b < nparts; b += blockDim.x) {
+        const int i = b + threadIdx.x;
+        const uint32_t v = i < nparts ? partial[i] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_excl_scan(v, sh, &total);
+        if (i < nparts) partial[i] = carry + ex;
+        carry += total;
+    }
+}
+
+__global__ void __launch_bounds__(SCAN_BLOCK)
+k_scan_apply(const uint32_t *__restrict__ counts, int64_t nkeys, const uint32_t *__restrict__ partial,
+             uint32_t *__restrict__ offsets) {
+    __shared__ uint32_t sh[SCAN_BLOCK / 64 + 1];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        v[i] = (base + i < nkeys) ? counts[base + i] : 0u;
+        s += v[i];
+    }
+    uint32_t total;
+    uint32_t run = partial[blockIdx.x] + block_excl_scan(s, sh, &total);
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        if (base + i < nkeys) offsets[base + i] = run;
+        run += v[i];
+    }
+    // the thread covering the last key writes the total at offsets[nkeys]
+    if (base < nkeys && base + SCAN_ITEMS >= nkeys) offsets[nkeys] = run;
+}
+
+// --------------------------------------------------------------- scatter
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sort_scatter(PartPtrs<T> src, PartPtrs<T> dst, int64_t n, const uint2 *__restrict__ keyrank,
+               const uint32_t *__restrict__ offsets) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const uint2 kr = keyrank[p];
+        const uint32_t d = offsets[kr.x] + kr.y;
+        dst.x[d] = src.x[p]; dst.y[d] = src.y[p]; dst.z[d] = src.z[p];
+        dst.u[d] = src.u[p]; dst.v[d] = src.v[p]; dst.w[d] = src.w[p];
+        dst.q[d] = src.q[p];
+        if (src.id) dst.id[d] = src.id[p];
+    }
+}
+
+// One wave per tile: copy the tile's particles from the cell-major scratch
+// to the caller's arrays in rank-major order.  Lane l owns local cell l.
+// For rank r the active cells are those with count > r; the rank-r block
+// starts after all lower-rank blocks and lists active cells in local order.
+template <typename T>
+__global__ void __launch_bounds__(64)
+k_sort_tile_transpose(PartPtrs<T> src, PartPtrs<T> dst, const uint32_t *__restrict__ offsets, TileGeom tg,
+                      int ntiles) {
+    const int t = blockIdx.x;
+    if (t >= ntiles) return;
+    const int lane = threadIdx.x;
+    const uint32_t key0 = (uint32_t)t * (uint32_t)tg.cells;
+    const uint32_t tile_start = offsets[key0];
+    uint32_t cnt = 0, cbeg = 0;
+    if (lane < tg.cells) {
+        cbeg = offsets[key0 + lane];
+        cnt = offsets[key0 + lane + 1] - cbeg;
+    }
+    uint32_t maxc = cnt;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t o = __shfl_xor(maxc, d, 64);
+        maxc = o > maxc ? o : maxc;
+    }
+    const uint64_t below = (lane == 0) ? 0ull : ((1ull << lane) - 1);
+    uint32_t blk = tile_start;
+    for (uint32_t r = 0; r < maxc; ++r) {
+        const bool act = cnt > r;
+        const uint64_t m = __ballot(act);
+        if (act) {
+            const uint32_t s = cbeg + r;
+            const uint32_t d = blk + (uint32_t)__popcll(m & below);
+            dst.x[d] = src.x[s]; dst.y[d] = src.y[s]; dst.z[d] = src.z[s];
+            dst.u[d] = src.u[s]; dst.v[d] = src.v[s]; dst.w[d] = src.w[s];
+            dst.q[d] = src.q[s];
+            if (src.id) dst.id[d] = src.id[s];
+        }
+        blk += (uint32_t)__popcll(m);
+    }
+}
+
+// Per-tile particle ranges: tile_off[t] = offsets[t * cells].
+__global__ void k_tile_offsets(const uint32_t *__restrict__ offsets, TileGeom tg, int ntiles,
+                               uint32_t *__restrict__ tile_off) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t <= ntiles) tile_off[t] = offsets[(uint32_t)t * (uint32_t)tg.cells];
+}
+
+// ------------------------------------------------------------------ host
+
+TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo) {
+    TileGeom t;
+    t.tx = tx; t.ty = ty; t.tz = tz;
+    t.cells = tx * ty * tz;
+    t.ntx = (g.nx + tx - 1) / tx;
+    t.nty = (g.ny + ty - 1) / ty;
+    t.ntz = (g.nz + tz - 1) / tz;
+    t.ntiles = t.ntx * t.nty * t.ntz;
+    t.halo = halo;
+    t.rx = tx + 2 * halo + 1;
+    t.ry = ty + 2 * halo + 1;
+    t.rz = tz + 2 * halo + 1;
+    return t;
+}
+
+size_t sort_scratch_bytes(int64_t n, int dtype, bool with_id, const TileGeom &tg) {
+    const int64_t nkeys = (int64_t)tg.ntiles * tg.cells;
+    const int64_t nparts = (nkeys + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    const size_t sp = dtype == SPIC_F64 ? 8 : 4;
+    size_t b = 0;
+    b += (size_t)nkeys * 4 + 256;          // counts
+    b += (size_t)(nkeys + 1) * 4 + 256;    // offsets
+    b += (size_t)nparts * 4 + 256;         // partials
+    b += (size_t)n * 8 + 256;              // key/rank
+    b += 7 * ((size_t)n * sp + 256);       // particle copy
+    if (with_id) b += (size_t)n * 8 + 256;
+    return b;
+}
+
+static inline char *carve(char *&cur, size_t bytes) {
+    char *p = cur;
+    cur += (bytes + 255) & ~(size_t)255;
+    return p;
+}
+
+template <typename T>
+static hipError_t sort_t(const spic_grid &g, const SpeciesWork &w, const TileGeom &tg, void *scratch,
+                         uint32_t *tile_off, hipStream_t s) {
+    const int64_t n = w.n;
+    const int64_t nkeys = (int64_t)tg.ntiles * tg.cells;
+    const int nparts = (int)((nkeys + SCAN_CHUNK - 1) / SCAN_CHUNK);
+    char *cur = (char *)scratch;
+    uint32_t *counts = (uint32_t *)carve(cur, (size_t)nkeys * 4);
+    uint32_t *offsets = (uint32_t *)carve(cur, (size_t)(nkeys + 1) * 4);
+    uint32_t *partial = (uint32_t *)carve(cur, (size_t)nparts * 4);
+    uint2 *keyrank = (uint2 *)carve(cur, (size_t)n * 8);
+    PartPtrs<T> src, tmp;
+    src.x = (T *)w.a[0]; src.y = (T *)w.a[1]; src.z = (T *)w.a[2];
+    src.u = (T *)w.a[3]; src.v = (T *)w.a[4]; src.w = (T *)w.a[5]; src.q = (T *)w.a[6];
+    src.id = w.id;
+    tmp.x = (T *)carve(cur, n * sizeof(T)); tmp.y = (T *)carve(cur, n * sizeof(T));
+    tmp.z = (T *)carve(cur, n * sizeof(T)); tmp.u = (T *)carve(cur, n * sizeof(T));
+    tmp.v = (T *)carve(cur, n * sizeof(T)); tmp.w = (T *)carve(cur, n * sizeof(T));
+    tmp.q = (T *)carve(cur, n * sizeof(T));
+    tmp.id = w.id ? (int64_t *)carve(cur, (size_t)n * 8) : nullptr;
+
+    hipError_t e;
+    if ((e = launch_zero32(counts, nkeys, s)) != hipSuccess) return e;
+    const int gp = (int)std::min<int64_t>((n + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL((k_sort_keys<T>), dim3(gp > 0 ? gp : 1), dim3(256), 0, s, make_grid_t<T>(g), tg, src.x,
+                       src.y, src.z, n, counts, keyrank);
+    hipLaunchKernelGGL(k_scan_partials, dim3(nparts), dim3(SCAN_BLOCK), 0, s, counts, nkeys, partial);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, partial, nparts);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nparts), dim3(SCAN_BLOCK), 0, s, counts, nkeys, partial, offsets);
+    hipLaunchKernelGGL((k_sort_scatter<T>), dim3(gp > 0 ? gp : 1), dim3(256), 0, s, src, tmp, n, keyrank, offsets);
+    hipLaunchKernelGGL((k_sort_tile_transpose<T>), dim3(tg.ntiles), dim3(64), 0, s, tmp, src, offsets, tg,
+                       tg.ntiles);
+    hipLaunchKernelGGL(k_tile_offsets, dim3((tg.ntiles + 1 + 255) / 256), dim3(256), 0, s, offsets, tg, tg.ntiles,
+                       tile_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort(const spic_grid &g, const SpeciesWork &w, const TileGeom &tg, void *scratch,
+                       uint32_t *tile_off, hipStream_t s) {
+    if (w.n <= 0) {
+        return launch_zero32(tile_off, tg.ntiles + 1, s);
+    }
+    return w.dtype == SPIC_F64 ? sort_t<double>(g, w, tg, scratch, tile_off, s)
+                               : sort_t<float>(g, w, tg, scratch, tile_off, s);
+}
+
+}  // namespace spic

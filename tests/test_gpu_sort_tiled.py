@@ -1,0 +1,200 @@
+"""GPU tests of the cell sort and of the tiled fused path (the path used once
+a species has been sorted), against the FP64 oracle and the generic path.
+
+The sort only permutes particles (checked by id, bitwise); the tiled path
+must give the oracle's result whatever the particle order, including
+particles that left their tile's LDS region, ragged edge tiles and grids
+smaller than one region (periodic images aliased inside the region).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2008_04397_amd import workloads as W
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def spic():
+    from paper_2008_04397_amd import spic as S
+    S.lib()
+    return S
+
+
+@pytest.fixture
+def ctx(spic):
+    c = spic.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _keys_np(g, st, tile):
+    tx, ty, tz = tile
+    dx, dy, dz = g.d
+    i = np.minimum((np.asarray(st["x"], np.float64) / dx).astype(np.int64), g.nx - 1)
+    j = np.minimum((np.asarray(st["y"], np.float64) / dy).astype(np.int64), g.ny - 1)
+    k = np.minimum((np.asarray(st["z"], np.float64) / dz).astype(np.int64), g.nz - 1)
+    nty, ntz = -(-g.ny // ty), -(-g.nz // tz)
+    tile_id = ((i // tx) * nty + (j // ty)) * ntz + (k // tz)
+    local = ((i % tx) * ty + (j % ty)) * tz + (k % tz)
+    return tile_id, local
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sort_permutes_into_tile_rank_major_order(spic, ctx, dtype):
+    h = W.harris_32x16x4()
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    sp = W.make_species(h, W.SHEET_E)
+    # scramble so the sort has work to do
+    perm = np.random.default_rng(1).permutation(sp["x"].size)
+    sp = {k: v[perm] for k, v in sp.items()}
+    dev = spic.to_device(sp, tdt)
+    _say("case sort %s harris_32x16x4 sheet_e" % dtype)
+    spic.spic_sort(ctx, h.grid, [dev])
+    torch.cuda.synchronize()
+    out = spic.to_host(dev)
+    a, b = P.by_id(out), P.by_id(spic.to_host(spic.to_device(sp, tdt)))
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    tile_id, local = _keys_np(h.grid, out, (4, 4, 4))
+    assert np.all(np.diff(tile_id) >= 0), "tiles not contiguous"
+    # rank-major inside each tile: inside a rank block local cells increase;
+    # a new block starts exactly where the local cell does not increase
+    for t in np.unique(tile_id)[:50]:
+        loc = local[tile_id == t]
+        counts = np.bincount(loc, minlength=64)
+        starts = np.flatnonzero(np.diff(loc) <= 0) + 1
+        blocks = np.split(loc, starts)
+        for r, blk in enumerate(blocks):
+            assert np.array_equal(blk, np.flatnonzero(counts > r)), (t, r)
+
+
+def _oracle_steps(h, f, sps, qoms, nsteps):
+    st = [dict(s) for s in sps]
+    ms = None
+    for _ in range(nsteps):
+        ms = []
+        for s in range(len(st)):
+            st[s], m = O.step(h.grid, h.dt, h.c, h.niter, qoms[s], f, st[s])
+            ms.append(m)
+    return st, ms
+
+
+def _gpu_steps(spic, ctx, h, f, sps, qoms, nsteps, dtype=torch.float64, sort_every=4, check=None):
+    dev_f = spic.to_device(f, dtype)
+    dev = [spic.to_device(s, dtype) for s in sps]
+    moms = spic.moment_buffers(h.grid, len(sps))
+    for step in range(nsteps):
+        prm = spic.make_params(h.dt, h.c, h.niter, sort_every, step)
+        spic.spic_mover(ctx, h.grid, prm, dev_f, dev, qoms, moms)
+        if check:
+            torch.cuda.synchronize()
+            check(step, [spic.to_host(d) for d in dev], [m.cpu().numpy() for m in moms])
+    torch.cuda.synchronize()
+    return [spic.to_host(d) for d in dev], [m.cpu().numpy() for m in moms]
+
+
+def test_tiled_fp64_every_step_matches_oracle(spic, ctx):
+    """32x16x4 cells, 4 species, 10 steps, sorted every 4 steps."""
+    h = W.harris_32x16x4()
+    f = W.make_fields(h)
+    sps = W.make_all_species(h)
+    ora = [dict(s) for s in sps]
+
+    def check(step, states, moms):
+        for s in range(4):
+            ora[s], m = O.step(h.grid, h.dt, h.c, h.niter, h.qoms[s], f, ora[s])
+            P.assert_state(states[s], ora[s], h.grid, P.POS64, P.VEL64)
+            P.assert_moments(moms[s], m, P.MOM64)
+
+    _say("case tiled fp64 harris_32x16x4 sort_every 4")
+    _gpu_steps(spic, ctx, h, f, sps, h.qoms, 10, check=check)
+
+
+def test_tiled_fp32_one_step(spic, ctx):
+    h = W.harris_32x16x4()
+    f32 = {k: v.astype(np.float32) for k, v in W.make_fields(h).items()}
+    sps = [W.round_state(s, np.float32) for s in W.make_all_species(h)]
+    _say("case tiled fp32 one step")
+    st, ms = _gpu_steps(spic, ctx, h, f32, sps, h.qoms, 1, dtype=torch.float32, sort_every=1)
+    f64 = {k: v.astype(np.float64) for k, v in f32.items()}
+    for s in range(4):
+        ora = O.mover(h.grid, h.dt, h.c, h.niter, h.qoms[s], f64, W.upcast(sps[s]))
+        P.assert_state(st[s], ora, h.grid, P.POS32, P.VEL32, vscale=max(P.vmax(ora), h.vths[s]))
+        P.assert_moments(ms[s], O.deposit(h.grid, W.upcast(st[s])), P.MOM32)
+
+
+@pytest.mark.parametrize("tile,halo", [((4, 4, 4), 0), ((2, 4, 8), 1), ((3, 3, 3), 1), ((2, 2, 2), 2),
+                                       ((2, 8, 4), 1), ((4, 4, 2), 1)])
+def test_tile_shapes_and_halo_overflow_match_oracle(spic, ctx, tile, halo):
+    """Fast particles leave small regions (halo 0) -> global fallbacks; tile
+    shapes that do not divide the grid leave ragged edge tiles."""
+    h = W.harris_32x16x4()
+    f = W.make_fields(h)
+    g = h.grid
+    sps = [W.random_particles(g, 20011, 2.0, seed=7), W.make_species(h, W.SHEET_I)]
+    qoms = [-64.0, 1.0]
+    ctx.set_option("tile_x", tile[0]); ctx.set_option("tile_y", tile[1]); ctx.set_option("tile_z", tile[2])
+    ctx.set_option("halo", halo)
+    _say("case tiles %s halo %d" % (tile, halo))
+    st, ms = _gpu_steps(spic, ctx, h, f, sps, qoms, 3, sort_every=2)
+    ora, oms = _oracle_steps(h, f, sps, qoms, 3)
+    for s in range(2):
+        P.assert_state(st[s], ora[s], g, P.POS64, P.VEL64)
+        P.assert_moments(ms[s], oms[s], P.MOM64)
+
+
+@pytest.mark.parametrize("cells", [(5, 3, 2), (2, 2, 2), (9, 7, 5)])
+def test_tiny_and_odd_grids(spic, ctx, cells):
+    """Grids smaller than one LDS region: periodic images alias inside it."""
+    h = W.Harris(W.Grid(*cells, 3.0, 2.0, 1.0), ppc=8)
+    f = W.make_fields(h)
+    sps = [W.make_species(h, s) for s in range(4)]
+    _say("case tiny grid %s" % (cells,))
+    st, ms = _gpu_steps(spic, ctx, h, f, sps, h.qoms, 3, sort_every=1)
+    ora, oms = _oracle_steps(h, f, sps, h.qoms, 3)
+    for s in range(4):
+        P.assert_state(st[s], ora[s], h.grid, P.POS64, P.VEL64)
+        P.assert_moments(ms[s], oms[s], P.MOM64)
+
+
+def test_sorted_and_unsorted_runs_agree(spic, ctx):
+    """Sorting only reorders: the same particles (by id) and the same moments
+    up to summation order."""
+    h = W.harris_32x16x4()
+    f = W.make_fields(h)
+    sps = W.make_all_species(h)
+    a_st, a_m = _gpu_steps(spic, ctx, h, f, sps, h.qoms, 6, sort_every=2)
+    ctx2 = spic.Context(0)
+    b_st, b_m = _gpu_steps(spic, ctx2, h, f, sps, h.qoms, 6, sort_every=0)
+    ctx2.close()
+    for s in range(4):
+        a, b = P.by_id(a_st[s]), P.by_id(b_st[s])
+        for k in ("x", "y", "z", "u", "v", "w"):
+            assert np.array_equal(a[k], b[k]), k
+        P.assert_moments(a_m[s], b_m[s], 1e-14)
+
+
+def test_run_to_run_repeatability(spic, ctx):
+    """Particles are bitwise repeatable; moments agree to rounding (atomics
+    add in a varying order)."""
+    h = W.harris_32x16x4()
+    f = W.make_fields(h)
+    sps = W.make_all_species(h)
+    r1 = _gpu_steps(spic, ctx, h, f, sps, h.qoms, 3, sort_every=1)
+    r2 = _gpu_steps(spic, ctx, h, f, sps, h.qoms, 3, sort_every=1)
+    for s in range(4):
+        a, b = P.by_id(r1[0][s]), P.by_id(r2[0][s])
+        for k in ("x", "y", "z", "u", "v", "w"):
+            assert np.array_equal(a[k], b[k])
+        P.assert_moments(r1[1][s], r2[1][s], 1e-15)
