@@ -9,6 +9,20 @@ FP32-particle / FP64-moment path; the FP64 path is reported beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64] [--no-cpu]
 Prints one JSON line.
+
+Other measured configurations (one JSON line each):
+  --mode ensemble   64 independent Harris boxes of uneven size (16x8x4 ..
+                    128x64x8 cells, ppc 8/27/64, B0 in [0.01, 0.03], mass
+                    ratio 25/64/100), FP32, 50 steps each, one batch
+                    submission (persistent work-list launch per step, hipGraph
+                    replay)
+  --mode streamed   512x256x32 cells x 125 ppc x 4 species (2.1e9 FP32
+                    particles in pinned host memory) streamed through a 16 GB
+                    HBM budget in batches of 2^26, sort every 4 steps, 5 steps
+                    (--fraction f keeps the first f of the x-slabs)
+  --mode serving    Poisson arrivals (20/s) of Harris-box runs (16x8x4 ..
+                    256x128x8 cells, ppc 8..64, 10..200 steps), continuous
+                    batching vs one-at-a-time on the same GPU, p50/p99 latency
 """
 from __future__ import annotations
 
@@ -40,9 +54,9 @@ def algorithmic_bytes(n_particles: int, nodes: int, s_p: int, s_f: int) -> float
     return n_particles * 13 * s_p + 6 * nodes * s_f + 10 * nodes * 8
 
 
-def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: int):
+def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: int, tune: bool = True):
     import torch
-    from paper_2008_04397_amd import spic
+    from paper_2008_04397_amd import autotune, spic
 
     dt = torch.float32 if dtype_name == "f32" else torch.float64
     g = h.grid
@@ -60,6 +74,19 @@ def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: 
     moms = spic.moment_buffers(g, 4, torch.float64)
     log("[bench] inputs resident in HBM after %.1f s" % (time.time() - t0))
     stream = torch.cuda.current_stream()
+    tuned = None
+    if tune and not path:
+        key = autotune.workload_class(dtype_name, g, h.ppc)
+        tuned = autotune.load(key)
+        if tuned is None:
+            tuned = autotune.tune(h, f, species, h.qoms, moms, steps=6, log=log)
+            autotune.store(key, tuned)
+        autotune.apply(ctx, tuned)
+        if sort_every < 0:
+            sort_every = tuned["sort_every"]
+        log("[bench] tuned %s: %s" % (key, tuned))
+    if sort_every < 0:
+        sort_every = 4
 
     def step(k, ev=None):
         prm = spic.make_params(h.dt, h.c, h.niter, sort_every, k)
@@ -100,6 +127,7 @@ def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: 
     step_ms = total_ms / steps
     per_step = launch_ms.sum(axis=1)
     return {
+        "tuned": tuned, "sort_every": sort_every,
         "value": n * steps / (total_ms / 1e3),
         "ms_per_step": step_ms,
         "ms_per_step_mean": float(per_step.mean()),
@@ -138,12 +166,137 @@ def cpu_baseline(h, target_s: float = 12.0):
                       "128x64x32 grid, %d fused steps (mover + FP64 deposit), %.1f s" % (n, steps, el)}
 
 
+def _engine_ctx(budget=0, tuned_key=None):
+    from paper_2008_04397_amd import autotune, spic
+    ctx = spic.Context(0, budget)
+    cfg = autotune.load(tuned_key) if tuned_key else None
+    if cfg:
+        autotune.apply(ctx, cfg)
+    return ctx
+
+
+def bench_ensemble(args):
+    """64 independent boxes, one batch submission, 50 steps each."""
+    import torch
+    from paper_2008_04397_amd import spic
+    boxes = W.ensemble_boxes(64)
+    nsteps = 50
+    ctx = _engine_ctx()
+    runs, total, gbytes = [], 0, 0.0
+    log("[bench] generating 64 boxes")
+    for b, h in enumerate(boxes):
+        f = W.fields_tensors(h, dtype=torch.float32)
+        sps = [W.species_tensors(h, s, dtype=torch.float32) for s in range(4)]
+        moms = spic.moment_buffers(h.grid, 4, torch.float64)
+        runs.append(spic.Run(h.grid, spic.make_params(h.dt, h.c, h.niter, 4, 0), f, sps, h.qoms, moms, nsteps))
+        total += h.n_total
+        gbytes += algorithmic_bytes(h.n_total, h.grid.nodes, 4, 4) + 3 * (6 * h.grid.nodes * 4 + 10 * h.grid.nodes * 8)
+    torch.cuda.synchronize()
+    log("[bench] %d particles in %d boxes; submitting" % (total, len(boxes)))
+    # warm-up: one step of every box (not timed)
+    warm = [spic.Run(r.grid, r.params, r.fields, r.species, r.qoms, r.moments, 1) for r in runs]
+    for t in spic.spic_batch_submit(ctx, warm):
+        spic.spic_wait(ctx, t)
+    t0 = time.perf_counter()
+    tickets = spic.spic_batch_submit(ctx, runs)
+    dev = [spic.spic_wait(ctx, t) for t in tickets]
+    wall = time.perf_counter() - t0
+    ctx.close()
+    ps = total * nsteps
+    achieved = gbytes * nsteps / wall / 1e9
+    return {"metric": METRIC, "mode": "ensemble", "value": ps / wall, "unit": "particle-steps/s", "n_gpus": 1,
+            "steps": nsteps, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "ensemble_64_harris_boxes", "boxes": len(boxes), "particles": total,
+                       "precision": "f32 particles, f64 moments", "sort_every": 4},
+            "wall_s": wall, "max_run_device_s": max(dev),
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None}}
+
+
+def bench_streamed(args):
+    """The 2.1e9-particle box streamed through a 16 GB budget."""
+    import torch
+    from paper_2008_04397_amd import spic
+    h = W.harris_512x256x32()
+    g = h.grid
+    nx_used = max(1, int(round(g.nx * args.fraction)))
+    budget = 16 * (1 << 30)
+    ctx = spic.Context(0, budget)
+    ctx.set_option("batch_particles", 1 << 26)
+    f = W.fields_tensors(h, dtype=torch.float32)
+    species, total = [], 0
+    log("[bench] generating %d x-slabs of 512 into pinned host memory" % nx_used)
+    t0 = time.time()
+    for s in range(4):
+        n = nx_used * g.ny * g.nz * h.ppc
+        host = {k: torch.empty(n, dtype=torch.float32, pin_memory=True) for k in ("x", "y", "z", "u", "v", "w", "q")}
+        step_slabs = 8
+        for i0 in range(0, nx_used, step_slabs):
+            i1 = min(nx_used, i0 + step_slabs)
+            t = W.species_tensors(h, s, i0, i1, dtype=torch.float32)
+            a = i0 * g.ny * g.nz * h.ppc
+            for k in host:
+                host[k][a:a + t[k].numel()].copy_(t[k])
+            del t
+        species.append(host)
+        total += n
+        log("[bench] species %d ready (%.1f s)" % (s, time.time() - t0))
+    moms = spic.moment_buffers(g, 4, torch.float64)
+    nsteps = 5
+    run = spic.Run(g, spic.make_params(h.dt, h.c, h.niter, 4, 0), f, species, h.qoms, moms, nsteps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dev = spic.spic_wait(ctx, spic.spic_batch_submit(ctx, [run])[0])
+    wall = time.perf_counter() - t1
+    ctx.close()
+    link = total * nsteps * (28 + 28) / wall / 1e9
+    return {"metric": METRIC, "mode": "streamed", "value": total * nsteps / wall, "unit": "particle-steps/s",
+            "n_gpus": 1, "steps": nsteps, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "harris_512x256x32_ppc125_4species_streamed", "particles": total,
+                       "fraction_of_x_slabs": nx_used / g.nx, "hbm_budget_bytes": budget, "batch": 1 << 26,
+                       "sort_every": 4},
+            "wall_s": wall, "device_s": dev,
+            "roofline": {"bound": "pcie", "achieved": link, "peak": 2 * 64.0, "unit": "GB/s",
+                         "frac": link / 128.0, "traffic": None,
+                         "note": "host<->device bytes (7 arrays up, 7 back, FP32) per second vs PCIe Gen5 x16 "
+                                 "nominal 64 GB/s per direction"}}
+
+
+def bench_serving(args):
+    """Poisson request stream: continuous batching vs one at a time."""
+    import torch
+    from paper_2008_04397_amd import serving, spic
+    reqs = W.serving_stream(args.requests)
+    res = {}
+    for mode in ("continuous", "serial"):
+        ctx = _engine_ctx(budget=64 * (1 << 30))
+        # warm the engine and the kernels once
+        warm = serving.make_request_run(reqs[0])
+        warm.nsteps = 1
+        spic.spic_wait(ctx, spic.spic_batch_submit(ctx, [warm])[0])
+        log("[bench] serving %d requests (%s)" % (len(reqs), mode))
+        done = serving.serve(ctx, reqs, mode=mode, log=log)
+        ctx.close()
+        res[mode] = serving.summarize(done)
+        log("[bench] %s: %s" % (mode, res[mode]))
+    c = res["continuous"]
+    return {"metric": METRIC, "mode": "serving", "value": c["throughput"], "unit": "particle-steps/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "poisson_20_per_s_harris_runs", "requests": len(reqs),
+                       "precision": "f32 particles, f64 moments", "hbm_budget_bytes": 64 * (1 << 30)},
+            "p50_s": c["p50_s"], "p99_s": c["p99_s"], "continuous": c, "serial": res["serial"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--sort-every", type=int, default=0)
+    ap.add_argument("--sort-every", type=int, default=-1, help="-1: the autotuned cadence")
+    ap.add_argument("--mode", default="main", choices=("main", "ensemble", "streamed", "serving"))
+    ap.add_argument("--fraction", type=float, default=1.0)
+    ap.add_argument("--requests", type=int, default=120)
+    ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--path", type=int, default=0)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -158,14 +311,18 @@ def main():
         sys.exit(1)
     from paper_2008_04397_amd import spic
     spic.lib()  # fail loudly if the HIP library is missing
+    if args.mode != "main":
+        out = {"ensemble": bench_ensemble, "streamed": bench_streamed, "serving": bench_serving}[args.mode](args)
+        print(json.dumps(out), flush=True)
+        return
 
     h = W.harris_128x64x32()
-    r32 = run_gpu(h, "f32", args.steps, args.warmup, args.sort_every, args.path)
+    r32 = run_gpu(h, "f32", args.steps, args.warmup, args.sort_every, args.path, tune=not args.no_tune)
     log("[bench] f32: %.3e particle-steps/s, %.3f ms/step, %.1f%% HBM" %
         (r32["value"], r32["ms_per_step"], 100 * r32["roofline"]["frac"]))
     r64 = None
     if not args.no_fp64:
-        r64 = run_gpu(h, "f64", args.steps, args.warmup, args.sort_every, args.path)
+        r64 = run_gpu(h, "f64", args.steps, args.warmup, args.sort_every, args.path, tune=not args.no_tune)
         log("[bench] f64: %.3e particle-steps/s, %.3f ms/step, %.1f%% HBM" %
             (r64["value"], r64["ms_per_step"], 100 * r64["roofline"]["frac"]))
     cpu = None
@@ -189,14 +346,15 @@ def main():
         "config": {"workload": "harris_128x64x32_ppc64_4species", "cells": [128, 64, 32],
                    "particles": h.n_total, "species": 4, "ppc": 64, "niter_mover": h.niter, "dt": h.dt,
                    "precision": "f32 particles and mover, f64 moment accumulation",
-                   "sort_every": args.sort_every, "path": args.path or "auto"},
+                   "sort_every": r32["sort_every"], "path": args.path or "auto", "tuned": r32["tuned"]},
         "roofline": r32["roofline"],
         "cpu_baseline": cpu,
         "ms_per_step_stats": {k: r32[k] for k in ("ms_per_step_mean", "ms_per_step_std", "ms_per_step_median")},
     }
     if r64 is not None:
         out["fp64"] = {"value": r64["value"], "unit": "particle-steps/s", "dtype": "f64",
-                       "ms_per_step": r64["ms_per_step"], "roofline": r64["roofline"]}
+                       "ms_per_step": r64["ms_per_step"], "roofline": r64["roofline"], "tuned": r64["tuned"],
+                       "sort_every": r64["sort_every"]}
     print(json.dumps(out), flush=True)
 
 

@@ -21,6 +21,7 @@ struct spic_ctx_s {
     };
 
     int device = 0;        // -1: host-only context (validation only)
+    size_t lds_max = 64 * 1024;  // LDS bytes one workgroup may use on the device
     uint64_t budget = 0;   // 0 = unlimited
     uint64_t used = 0;     // bytes of library scratch currently allocated
     std::string err;

@@ -14,13 +14,29 @@ namespace spic {
 __device__ __forceinline__ float dfloor(float x) { return __builtin_floorf(x); }
 __device__ __forceinline__ double dfloor(double x) { return __builtin_floor(x); }
 
-// Periodic wrap into [0, L): r = s - L floor(s/L); a rounding that lands on
-// L (or below 0) is the same point of the box as 0.
+// Periodic wrap into [0, L): a point already inside is returned as is;
+// otherwise r = s - L floor(s/L), and a rounding that lands on L (or below
+// 0) is the same point of the box as 0.
 template <typename T>
 __device__ __forceinline__ T pwrap(T s, T L, T invL) {
-    T r = s - L * dfloor(s * invL);
-    r = (r >= L) ? T(0) : r;
-    return (r < T(0)) ? T(0) : r;
+    T r = s;
+    if (__builtin_expect(!(s >= T(0) && s < L), 0)) {
+        r = s - L * dfloor(s * invL);
+        r = (r >= L) ? T(0) : r;
+        r = (r < T(0)) ? T(0) : r;
+    }
+    return r;
+}
+
+// 1 / d for d >= 1 (the denominator of Eq. 2): the hardware reciprocal in
+// FP32 (1 ulp), a Newton-refined reciprocal in FP64.
+__device__ __forceinline__ float recip_ge1(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double recip_ge1(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = __builtin_fma(-d, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-d, r, 1.0);
+    return __builtin_fma(r, e, r);
 }
 
 // Left node index along one axis and the offset xi in [0,1] inside the cell;
@@ -125,7 +141,7 @@ __device__ __forceinline__ void implicit_move(const GridT<T> &g, const MoveT<T> 
         const T wt = w0 + mv.beta * F[2];
         const T bx = mv.bc * F[3], by = mv.bc * F[4], bz = mv.bc * F[5];
         const T vdb = ut * bx + vt * by + wt * bz;
-        const T inv = T(1) / (T(1) + (bx * bx + by * by + bz * bz));
+        const T inv = recip_ge1(T(1) + (bx * bx + by * by + bz * bz));
         ub = (ut + (vt * bz - wt * by) + vdb * bx) * inv;
         vb = (vt + (wt * bx - ut * bz) + vdb * by) * inv;
         wb = (wt + (ut * by - vt * bx) + vdb * bz) * inv;

@@ -11,9 +11,6 @@
 
 using namespace spic;
 
-namespace spic {
-struct BatchEngine {};
-}
 
 static SpeciesWork work_of(const spic_species &s, const spic_moment_array *m) {
     SpeciesWork w;
@@ -39,7 +36,6 @@ TileGeom spic_ctx_s::tile_geom(const spic_grid &g) const {
                           (int)opt("halo", 1));
 }
 
-static constexpr size_t kMaxLds = 64 * 1024;
 
 int spic_ctx_s::mover(const spic_grid &g, const spic_params &p, const spic_fields &f, spic_species *sp,
                       int32_t nsp, spic_moment_array *mom, hipStream_t s) {
@@ -59,7 +55,7 @@ int spic_ctx_s::mover(const spic_grid &g, const spic_params &p, const spic_field
         const Layout *lay = nullptr;
         if (!generic_only) {
             auto it = layouts.find(layout_key(g, sp[i]));
-            if (it != layouts.end() && tiled_lds_bytes(it->second.tg, w.dtype, w.acc_dtype) <= kMaxLds)
+            if (it != layouts.end() && tiled_lds_bytes(it->second.tg, w.dtype, w.acc_dtype) <= lds_max)
                 lay = &it->second;
         }
         int rc;
@@ -112,15 +108,3 @@ int spic_ctx_s::sort(const spic_grid &g, spic_species *sp, int32_t nsp, hipStrea
     return SPIC_OK;
 }
 
-int spic_ctx_s::batch_submit(const spic_run *, int32_t, uint64_t *) {
-    return fail(SPIC_E_UNSUPPORTED, "batch_submit is not built yet");
-}
-
-int spic_ctx_s::wait(uint64_t, double *) { return fail(SPIC_E_STATE, "unknown ticket"); }
-
-int spic_ctx_s::poll(uint64_t, int32_t *) { return fail(SPIC_E_STATE, "unknown ticket"); }
-
-void spic_ctx_s::shutdown() {}
-
-spic_ctx_s::spic_ctx_s() {}
-spic_ctx_s::~spic_ctx_s() {}

@@ -53,6 +53,7 @@ struct LaunchCfg {
     int block = 256;        // generic kernels
     int grid_cap = 1 << 20;
     int tile_block = 256;   // tiled fused kernel
+    int home_acc = 0;       // tiled kernel: home-cell register accumulation
 };
 
 // Tiles of tx x ty x tz cells (at most 64 cells) cover the grid; ntx.. are
@@ -63,6 +64,7 @@ struct TileGeom {
     int tx, ty, tz, cells;
     int ntx, nty, ntz, ntiles;
     int halo, rx, ry, rz;
+    int ryp, rzp, rnp, pad;  // padded LDS extents (bank spread) and slots rx*ryp*rzp
 };
 
 template <typename T>
@@ -109,6 +111,39 @@ inline FieldPtrs<T> field_ptrs(const spic_fields &f) {
     return r;
 }
 
+// Everything the tiled fused code needs for one species: grid constants in
+// the mover and accumulation precisions, fields, mover constants, particle
+// arrays, moment output, per-tile particle ranges and tile geometry.
+template <typename TP, typename TF, typename TA>
+struct TileJob {
+    GridT<TP> g;
+    GridT<TA> ga;
+    FieldPtrs<TF> f;
+    MoveT<TP> mv;
+    PartPtrs<TP> p;
+    TA *mom;
+    const uint32_t *tile_off;
+    TileGeom tg;
+    int nn, pad;
+};
+
+template <typename TP, typename TF, typename TA>
+inline TileJob<TP, TF, TA> make_tile_job(const spic_grid &g, const spic_params &prm, const spic_fields &f,
+                                         const SpeciesWork &w, const TileGeom &tg, const uint32_t *tile_off) {
+    TileJob<TP, TF, TA> J;
+    J.g = make_grid_t<TP>(g);
+    J.ga = make_grid_t<TA>(g);
+    J.f = field_ptrs<TF>(f);
+    J.mv = make_move<TP>(prm, w.qom);
+    J.p = part_ptrs<TP>(w);
+    J.mom = (TA *)w.mom;
+    J.tile_off = tile_off;
+    J.tg = tg;
+    J.nn = g.nx * g.ny * g.nz;
+    J.pad = 0;
+    return J;
+}
+
 // Zero `count` elements of a float (SPIC_F32), double (SPIC_F64) array.
 hipError_t launch_fill(void *p, int dtype, int64_t count, hipStream_t s);
 // Zero `count` 32-bit words.
@@ -135,5 +170,17 @@ size_t tiled_lds_bytes(const TileGeom &tg, int dtype, int acc_dtype);
 hipError_t launch_fused_tiled(const spic_grid &g, const spic_params &prm, const spic_fields &f,
                               const SpeciesWork &w, const TileGeom &tg, const uint32_t *tile_off,
                               const LaunchCfg &cfg, hipStream_t s);
+
+// Work lists (spic_tiled.hip).  combo: 0 f64/f64/f64, 1 f32/f32/f64,
+// 2 f32/f32/f32, 3 f32/f64/f64, 4 f32/f64/f32 (particles/fields/moments);
+// -1 for an unsupported combination.
+int job_combo(int dtype, int fdtype, int acc_dtype);
+size_t tile_job_bytes(int combo);
+void write_tile_job(int combo, void *dst, const spic_grid &g, const spic_params &prm, const spic_fields &f,
+                    const SpeciesWork &w, const TileGeom &tg, const uint32_t *tile_off);
+int worklist_groups(int combo, bool home, size_t lds, int block, int nitems, int max_groups);
+hipError_t launch_worklist(int combo, bool home, const void *jobs, const uint2 *items, int nitems,
+                           unsigned *counter, size_t lds, int block, int groups, hipStream_t s);
+hipError_t launch_fill_many(void *const *ptrs, const int64_t *counts, int narr, int elem_bytes, hipStream_t s);
 
 }  // namespace spic

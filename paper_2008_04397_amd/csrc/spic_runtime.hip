@@ -187,6 +187,11 @@ static const char *const kOptionNames[] = {
     "tile_block",   // threads per block of the tiled fused kernel
     "tile_x", "tile_y", "tile_z",  // sort tile shape in cells (product <= 64)
     "halo",         // cells of halo staged around a tile
+    "lds_max",      // read only: LDS bytes per workgroup on the device
+    "home_acc",     // tiled kernel: 1 = home-cell register accumulation, 0 = LDS atomics only
+    "graph",        // batch engine: 1 = replay unchanged ticks as a hipGraph
+    "batch_particles",  // batch engine: particles per streamed batch (upper bound)
+    "max_groups",   // batch engine: cap on workgroups of the persistent launch (0 = occupancy)
 };
 
 int64_t spic_ctx_s::opt(const char *k, int64_t dflt) const {
@@ -199,6 +204,7 @@ LaunchCfg spic_ctx_s::launch_cfg() const {
     c.block = (int)opt("block", 256);
     c.grid_cap = (int)opt("grid_cap", 1 << 20);
     c.tile_block = (int)opt("tile_block", 256);
+    c.home_acc = (int)opt("home_acc", 0);
     return c;
 }
 
@@ -232,6 +238,11 @@ int spic_ctx_create(int device, uint64_t hbm_budget_bytes, spic_ctx *out) {
     if (!c) return SPIC_E_HIP;
     c->device = device;
     c->budget = hbm_budget_bytes;
+    if (device >= 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && v > 0)
+            c->lds_max = (size_t)v;
+    }
     *out = c;
     return SPIC_OK;
 }
@@ -268,6 +279,7 @@ int spic_set_option(spic_ctx ctx, const char *key, int64_t value) {
                 return ctx->fail(SPIC_E_ARG, "tile sizes must be in [1, 64]");
             if (!strcmp(key, "halo") && (value < 0 || value > 8))
                 return ctx->fail(SPIC_E_ARG, "halo must be in [0, 8]");
+            if (!strcmp(key, "lds_max")) return ctx->fail(SPIC_E_ARG, "lds_max is read only");
             ctx->options[key] = value;
             return SPIC_OK;
         }
@@ -279,7 +291,7 @@ int spic_get_option(spic_ctx ctx, const char *key, int64_t *value) {
     std::lock_guard<std::mutex> lk(ctx->mu);
     for (const char *k : kOptionNames)
         if (!strcmp(k, key)) {
-            *value = ctx->opt(key, -1);
+            *value = !strcmp(key, "lds_max") ? (int64_t)ctx->lds_max : ctx->opt(key, -1);
             return SPIC_OK;
         }
     return ctx->fail(SPIC_E_ARG, "unknown option '%s'", key);

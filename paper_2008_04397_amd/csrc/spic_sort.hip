@@ -15,8 +15,9 @@
 //   1 key:     cell key of every particle; rank within its cell from a
 //              wave-aggregated atomic histogram
 //   2 scan:    exclusive prefix of the per-key counts (three kernels)
-//   3 scatter: particle -> scratch at offset[key] + rank (cell-major)
-//   4 tile:    scratch -> caller arrays, rank-major inside each tile
+//   3 tables:  per tile and rank, the start of the rank block and the mask
+//              of cells holding a particle of that rank
+//   4 scatter: particle -> scratch at its rank-major slot; copy back
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -170,13 +171,64 @@ k_scan_apply(const uint32_t *__restrict__ counts, int64_t nkeys, const uint32_t 
 
 // --------------------------------------------------------------- scatter
 
+// Rank tables.  Inside tile t the particle of local cell l with rank r goes
+// to  tile_start + base_t[r] + #{l' < l : count_l' > r},  where base_t[r] is
+// the number of the tile's particles of rank < r.  One wave per tile (lane
+// l = local cell l) writes, for each rank r < max count, the entry
+// {base_t[r], mask of cells with count > r} at tab[tab_off[t] + r].
+
+// Max cell count of every tile.
+__global__ void __launch_bounds__(64)
+k_tile_maxc(const uint32_t *__restrict__ offsets, TileGeom tg, uint32_t *__restrict__ maxc) {
+    const int t = blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint32_t key0 = (uint32_t)t * (uint32_t)tg.cells;
+    uint32_t c = 0;
+    if (lane < tg.cells) c = offsets[key0 + lane + 1] - offsets[key0 + lane];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t o = __shfl_xor(c, d, 64);
+        c = o > c ? o : c;
+    }
+    if (lane == 0) maxc[t] = c;
+}
+
+__global__ void __launch_bounds__(64)
+k_tile_table(const uint32_t *__restrict__ offsets, TileGeom tg, const uint32_t *__restrict__ tab_off,
+             uint4 *__restrict__ tab) {
+    const int t = blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint32_t key0 = (uint32_t)t * (uint32_t)tg.cells;
+    uint32_t cnt = 0;
+    if (lane < tg.cells) cnt = offsets[key0 + lane + 1] - offsets[key0 + lane];
+    const uint32_t t0 = tab_off[t], nr = tab_off[t + 1] - t0;
+    uint32_t base = 0;
+    for (uint32_t r0 = 0; r0 < nr; r0 += 64) {
+        // lane j computes the entry of rank r0 + j from a wave-wide ballot per rank
+        uint32_t my_base = 0;
+        uint64_t my_mask = 0;
+        for (int j = 0; j < 64 && r0 + j < nr; ++j) {
+            const uint64_t m = __ballot(cnt > r0 + j);
+            if (lane == j) { my_base = base; my_mask = m; }
+            base += (uint32_t)__popcll(m);
+        }
+        if (r0 + lane < nr) tab[t0 + r0 + lane] = make_uint4(my_base, (uint32_t)my_mask, (uint32_t)(my_mask >> 32), 0u);
+    }
+}
+
+// Scatter every particle straight to its rank-major slot in scratch.
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_sort_scatter(PartPtrs<T> src, PartPtrs<T> dst, int64_t n, const uint2 *__restrict__ keyrank,
-               const uint32_t *__restrict__ offsets) {
+k_sort_scatter_rm(PartPtrs<T> src, PartPtrs<T> dst, int64_t n, const uint2 *__restrict__ keyrank,
+                  const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ tab_off,
+                  const uint4 *__restrict__ tab, int cells) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
         const uint2 kr = keyrank[p];
-        const uint32_t d = offsets[kr.x] + kr.y;
+        const uint32_t t = kr.x / (uint32_t)cells, l = kr.x - t * (uint32_t)cells;
+        const uint4 e = tab[tab_off[t] + kr.y];
+        const uint64_t m = ((uint64_t)e.z << 32) | e.y;
+        const uint64_t below = (l == 0) ? 0ull : (m & ((1ull << l) - 1));
+        const uint32_t d = offsets[t * (uint32_t)cells] + e.x + (uint32_t)__popcll(below);
         dst.x[d] = src.x[p]; dst.y[d] = src.y[p]; dst.z[d] = src.z[p];
         dst.u[d] = src.u[p]; dst.v[d] = src.v[p]; dst.w[d] = src.w[p];
         dst.q[d] = src.q[p];
@@ -184,44 +236,13 @@ k_sort_scatter(PartPtrs<T> src, PartPtrs<T> dst, int64_t n, const uint2 *__restr
     }
 }
 
-// One wave per tile: copy the tile's particles from the cell-major scratch
-// to the caller's arrays in rank-major order.  Lane l owns local cell l.
-// For rank r the active cells are those with count > r; the rank-r block
-// starts after all lower-rank blocks and lists active cells in local order.
 template <typename T>
-__global__ void __launch_bounds__(64)
-k_sort_tile_transpose(PartPtrs<T> src, PartPtrs<T> dst, const uint32_t *__restrict__ offsets, TileGeom tg,
-                      int ntiles) {
-    const int t = blockIdx.x;
-    if (t >= ntiles) return;
-    const int lane = threadIdx.x;
-    const uint32_t key0 = (uint32_t)t * (uint32_t)tg.cells;
-    const uint32_t tile_start = offsets[key0];
-    uint32_t cnt = 0, cbeg = 0;
-    if (lane < tg.cells) {
-        cbeg = offsets[key0 + lane];
-        cnt = offsets[key0 + lane + 1] - cbeg;
-    }
-    uint32_t maxc = cnt;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        const uint32_t o = __shfl_xor(maxc, d, 64);
-        maxc = o > maxc ? o : maxc;
-    }
-    const uint64_t below = (lane == 0) ? 0ull : ((1ull << lane) - 1);
-    uint32_t blk = tile_start;
-    for (uint32_t r = 0; r < maxc; ++r) {
-        const bool act = cnt > r;
-        const uint64_t m = __ballot(act);
-        if (act) {
-            const uint32_t s = cbeg + r;
-            const uint32_t d = blk + (uint32_t)__popcll(m & below);
-            dst.x[d] = src.x[s]; dst.y[d] = src.y[s]; dst.z[d] = src.z[s];
-            dst.u[d] = src.u[s]; dst.v[d] = src.v[s]; dst.w[d] = src.w[s];
-            dst.q[d] = src.q[s];
-            if (src.id) dst.id[d] = src.id[s];
-        }
-        blk += (uint32_t)__popcll(m);
+__global__ void __launch_bounds__(256) k_copy_parts(PartPtrs<T> src, PartPtrs<T> dst, int64_t n) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        dst.x[p] = src.x[p]; dst.y[p] = src.y[p]; dst.z[p] = src.z[p];
+        dst.u[p] = src.u[p]; dst.v[p] = src.v[p]; dst.w[p] = src.w[p];
+        dst.q[p] = src.q[p];
+        if (src.id) dst.id[p] = src.id[p];
     }
 }
 
@@ -246,6 +267,34 @@ TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo) {
     t.rx = tx + 2 * halo + 1;
     t.ry = ty + 2 * halo + 1;
     t.rz = tz + 2 * halo + 1;
+    // Padded LDS extents: choose RYP >= ry, RZP >= rz so that the lower
+    // corners of a full tile's cells (one cell per lane) hit the 16 pairs of
+    // 4-byte banks as evenly as possible, for every corner offset; prefer
+    // the fewest slots among the most even.
+    int best_w = 1 << 30, best_n = 1 << 30, bry = t.ry, brz = t.rz;
+    for (int ryp = t.ry; ryp < t.ry + 9; ++ryp)
+        for (int rzp = t.rz; rzp < t.rz + 9; ++rzp) {
+            const int sx = ryp * rzp, sy = rzp;
+            int worst = 0;
+            for (int c = 0; c < 8; ++c) {
+                int cnt[16] = {0};
+                for (int li = 0; li < tx; ++li)
+                    for (int lj = 0; lj < ty; ++lj)
+                        for (int lk = 0; lk < tz; ++lk) {
+                            const int slot = (li + halo + (c & 1)) * sx + (lj + halo + ((c >> 1) & 1)) * sy +
+                                             (lk + halo + (c >> 2));
+                            worst = std::max(worst, ++cnt[slot & 15]);
+                        }
+            }
+            const int slots = t.rx * sx;
+            if (worst < best_w || (worst == best_w && slots < best_n)) {
+                best_w = worst; best_n = slots; bry = ryp; brz = rzp;
+            }
+        }
+    t.ryp = bry;
+    t.rzp = brz;
+    t.rnp = t.rx * bry * brz;
+    t.pad = 0;
     return t;
 }
 
@@ -258,6 +307,9 @@ size_t sort_scratch_bytes(int64_t n, int dtype, bool with_id, const TileGeom &tg
     b += (size_t)(nkeys + 1) * 4 + 256;    // offsets
     b += (size_t)nparts * 4 + 256;         // partials
     b += (size_t)n * 8 + 256;              // key/rank
+    b += (size_t)(tg.ntiles + 1) * 4 * 2 + 512;   // maxc, tab_off
+    b += ((size_t)n + tg.ntiles) * 16 + 256;      // rank tables (sum of max counts <= n)
+    b += (size_t)((tg.ntiles + SCAN_CHUNK) / SCAN_CHUNK) * 4 + 256;  // partials of the tile scan
     b += 7 * ((size_t)n * sp + 256);       // particle copy
     if (with_id) b += (size_t)n * 8 + 256;
     return b;
@@ -280,6 +332,11 @@ static hipError_t sort_t(const spic_grid &g, const SpeciesWork &w, const TileGeo
     uint32_t *offsets = (uint32_t *)carve(cur, (size_t)(nkeys + 1) * 4);
     uint32_t *partial = (uint32_t *)carve(cur, (size_t)nparts * 4);
     uint2 *keyrank = (uint2 *)carve(cur, (size_t)n * 8);
+    uint32_t *maxc = (uint32_t *)carve(cur, (size_t)(tg.ntiles + 1) * 4);
+    uint32_t *tab_off = (uint32_t *)carve(cur, (size_t)(tg.ntiles + 1) * 4);
+    uint4 *tab = (uint4 *)carve(cur, ((size_t)n + tg.ntiles) * 16);
+    const int tparts = (int)((tg.ntiles + SCAN_CHUNK) / SCAN_CHUNK);
+    uint32_t *tpartial = (uint32_t *)carve(cur, (size_t)tparts * 4);
     PartPtrs<T> src, tmp;
     src.x = (T *)w.a[0]; src.y = (T *)w.a[1]; src.z = (T *)w.a[2];
     src.u = (T *)w.a[3]; src.v = (T *)w.a[4]; src.w = (T *)w.a[5]; src.q = (T *)w.a[6];
@@ -298,9 +355,16 @@ static hipError_t sort_t(const spic_grid &g, const SpeciesWork &w, const TileGeo
     hipLaunchKernelGGL(k_scan_partials, dim3(nparts), dim3(SCAN_BLOCK), 0, s, counts, nkeys, partial);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, partial, nparts);
     hipLaunchKernelGGL(k_scan_apply, dim3(nparts), dim3(SCAN_BLOCK), 0, s, counts, nkeys, partial, offsets);
-    hipLaunchKernelGGL((k_sort_scatter<T>), dim3(gp > 0 ? gp : 1), dim3(256), 0, s, src, tmp, n, keyrank, offsets);
-    hipLaunchKernelGGL((k_sort_tile_transpose<T>), dim3(tg.ntiles), dim3(64), 0, s, tmp, src, offsets, tg,
-                       tg.ntiles);
+    // rank tables: max count per tile, exclusive scan of the max counts, fill
+    hipLaunchKernelGGL(k_tile_maxc, dim3(tg.ntiles), dim3(64), 0, s, offsets, tg, maxc);
+    hipLaunchKernelGGL(k_scan_partials, dim3(tparts), dim3(SCAN_BLOCK), 0, s, maxc, (int64_t)tg.ntiles, tpartial);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tpartial, tparts);
+    hipLaunchKernelGGL(k_scan_apply, dim3(tparts), dim3(SCAN_BLOCK), 0, s, maxc, (int64_t)tg.ntiles, tpartial,
+                       tab_off);
+    hipLaunchKernelGGL(k_tile_table, dim3(tg.ntiles), dim3(64), 0, s, offsets, tg, tab_off, tab);
+    hipLaunchKernelGGL((k_sort_scatter_rm<T>), dim3(gp > 0 ? gp : 1), dim3(256), 0, s, src, tmp, n, keyrank,
+                       offsets, tab_off, tab, tg.cells);
+    hipLaunchKernelGGL((k_copy_parts<T>), dim3(gp > 0 ? gp : 1), dim3(256), 0, s, tmp, src, n);
     hipLaunchKernelGGL(k_tile_offsets, dim3((tg.ntiles + 1 + 255) / 256), dim3(256), 0, s, offsets, tg, tg.ntiles,
                        tile_off);
     return hipGetLastError();

@@ -6,18 +6,27 @@
 // nodes) in LDS, moves every particle of the tile's range (Eq. 1, Eq. 2,
 // Eq. 5) gathering E and B from LDS (Eq. 3, Eq. 4), and deposits the ten
 // moments of the moved particle (Sec. II moment equation; Sec. III-B:
-// fused, from the new position) into an FP64 region accumulator in LDS.
-// The region accumulator is then added to the global moments with
-// coalesced global atomics (neighbouring tiles' regions overlap).
+// fused, from the new position).  The region's moments are then added to
+// the global moments with coalesced global atomics (neighbouring tiles'
+// regions overlap).
+//
+// Deposit.  Rank-major order inside a tile (spic_sort.hip) gives every
+// thread a run of particles from one cell, and every lane of a wave a
+// different cell.  A thread keeps the 80 sums (8 corners x 10 moments) of
+// its "home" cell -- the cell of the first particle it deposits -- in
+// registers of the accumulation type; only particles that have drifted into
+// another cell go to the region accumulator in LDS with atomics, and a
+// thread adds its register sums to the region once at the end of the tile.
+//
+// LDS layout.  Region slots are (di*RYP + dj)*RZP + dk with padded extents
+// RYP >= ry, RZP >= rz chosen on the host so that the nodes of a wave's 64
+// cells fall evenly on the LDS banks.  Fields are node-major (6 values per
+// slot), moments component-major ([10][slots]).
 //
 // Particles whose cell lies outside the region (they drifted farther than
 // the halo since the last sort) take the global path for that gather or
 // deposit, so the result does not depend on the particle order; the order
-// only decides how much work stays in LDS.
-//
-// Rank-major order inside a tile puts consecutive particles -- the lanes of
-// a wave -- in different cells, so the LDS atomics of one instruction hit
-// different nodes.
+// only decides how much work stays in LDS and registers.
 //
 // Tiles are mapped to workgroups so that the 8 XCDs each take a contiguous
 // slab of tiles: workgroup b runs on XCD b % 8, and gets tile
@@ -30,18 +39,18 @@
 
 namespace spic {
 
-constexpr int MSTRIDE = 11;  // doubles per node in the LDS moment region (odd: spreads banks)
-
 template <typename TP>
 struct LdsFieldNode {
     TP v[6];
 };
 
-// Region-relative cell of a point; returns false when the cell's +1 corners
-// leave the region.  `o*` is the region origin cell (periodic, in [0, n)).
+// Location of a point relative to the region.  Returns true when the
+// point's cell (with its +1 corners) lies inside the region; `slot` is the
+// LDS slot of the cell's lower corner.  When it returns false the global
+// cell is in c (base and wrap offsets), otherwise only c.f* are set.
 template <typename T>
-__device__ __forceinline__ bool region_cell(const GridT<T> &g, const TileGeom &tg, int ox, int oy, int oz,
-                                            T x, T y, T z, int &rb, Cell<T> &c) {
+__device__ __forceinline__ bool region_locate(const GridT<T> &g, const TileGeom &tg, int ox, int oy, int oz, T x,
+                                              T y, T z, int &slot, Cell<T> &c) {
     const int i = plocate(x, g.L[0], g.invL[0], g.invd[0], g.nx, c.fx);
     const int j = plocate(y, g.L[1], g.invL[1], g.invd[1], g.ny, c.fy);
     const int k = plocate(z, g.L[2], g.invL[2], g.invd[2], g.nz, c.fz);
@@ -49,13 +58,16 @@ __device__ __forceinline__ bool region_cell(const GridT<T> &g, const TileGeom &t
     di += (di < 0) ? g.nx : 0;
     dj += (dj < 0) ? g.ny : 0;
     dk += (dk < 0) ? g.nz : 0;
-    const int nyz = g.ny * g.nz;
-    c.base = i * nyz + j * g.nz + k;
-    c.ox = (i == g.nx - 1) ? -(g.nx - 1) * nyz : nyz;
-    c.oy = (j == g.ny - 1) ? -(g.ny - 1) * g.nz : g.nz;
-    c.oz = (k == g.nz - 1) ? -(g.nz - 1) : 1;
-    rb = (di * tg.ry + dj) * tg.rz + dk;
-    return di < tg.rx - 1 && dj < tg.ry - 1 && dk < tg.rz - 1;
+    slot = (di * tg.ryp + dj) * tg.rzp + dk;
+    const bool in = di < tg.rx - 1 && dj < tg.ry - 1 && dk < tg.rz - 1;
+    if (!in) {
+        const int nyz = g.ny * g.nz;
+        c.base = i * nyz + j * g.nz + k;
+        c.ox = (i == g.nx - 1) ? -(g.nx - 1) * nyz : nyz;
+        c.oy = (j == g.ny - 1) ? -(g.ny - 1) * g.nz : g.nz;
+        c.oz = (k == g.nz - 1) ? -(g.nz - 1) : 1;
+    }
+    return in;
 }
 
 template <typename TP>
@@ -63,7 +75,7 @@ __device__ __forceinline__ void gather_lds(const LdsFieldNode<TP> *__restrict__ 
                                            const Cell<TP> &c, TP out[6]) {
     TP w[8];
     pweights(c.fx, c.fy, c.fz, w);
-    const int sx = tg.ry * tg.rz, sy = tg.rz;
+    const int sx = tg.ryp * tg.rzp, sy = tg.rzp;
     const int nd[8] = {rb, rb + sx, rb + sy, rb + sx + sy, rb + 1, rb + sx + 1, rb + sy + 1, rb + sx + sy + 1};
 #pragma unroll
     for (int m = 0; m < 6; ++m) out[m] = TP(0);
@@ -75,47 +87,78 @@ __device__ __forceinline__ void gather_lds(const LdsFieldNode<TP> *__restrict__ 
     }
 }
 
-template <typename TP, typename TF, typename TA>
-__global__ void __launch_bounds__(512)
-k_fused_tiled(GridT<TP> g, GridT<TA> ga, FieldPtrs<TF> f, MoveT<TP> mv, PartPtrs<TP> p, TA *__restrict__ mom,
-              int nn, const uint32_t *__restrict__ tile_off, TileGeom tg, int chunk) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int b = blockIdx.x;
-    const int t = (b & 7) * chunk + (b >> 3);
-    if (t >= tg.ntiles) return;
-    const int RN = tg.rx * tg.ry * tg.rz;
-    LdsFieldNode<TP> *fl = (LdsFieldNode<TP> *)smem;
-    TA *ml = (TA *)(smem + ((RN * sizeof(LdsFieldNode<TP>) + 15) & ~(size_t)15));
+// Global node of a region node's logical coordinates.
+__device__ __forceinline__ int region_node(int nx, int ny, int nz, int ox, int oy, int oz, int ri, int rj, int rk) {
+    const int gi = (ox + ri) % nx, gj = (oy + rj) % ny, gk = (oz + rk) % nz;
+    return (gi * ny + gj) * nz + gk;
+}
 
+// One tile of one species: stage the region, move and deposit the tile's
+// particles, flush the region's moments.  Called by the per-species tiled
+// kernel and by the work-list kernel of the batch engine; `t` is uniform
+// across the workgroup.
+template <typename TP, typename TF, typename TA, bool HOME>
+__device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, unsigned char *smem) {
+    const GridT<TP> &g = J.g;
+    const TileGeom &tg = J.tg;
+    const FieldPtrs<TF> &f = J.f;
+    const PartPtrs<TP> &p = J.p;
+    TA *__restrict__ mom = J.mom;
+    const int nn = J.nn;
+    const uint32_t beg = J.tile_off[t], end = J.tile_off[t + 1];
+    if (beg == end) return;  // uniform: no particle in this tile
+
+    const int RNP = tg.rnp;
+    LdsFieldNode<TP> *fl = (LdsFieldNode<TP> *)smem;
+    TA *ml = (TA *)(smem + ((RNP * sizeof(LdsFieldNode<TP>) + 15) & ~(size_t)15));
     const int tzi = t % tg.ntz, tyi = (t / tg.ntz) % tg.nty, txi = t / (tg.ntz * tg.nty);
     int ox = (txi * tg.tx - tg.halo) % g.nx; ox += ox < 0 ? g.nx : 0;
     int oy = (tyi * tg.ty - tg.halo) % g.ny; oy += oy < 0 ? g.ny : 0;
     int oz = (tzi * tg.tz - tg.halo) % g.nz; oz += oz < 0 ? g.nz : 0;
+    const int RL = tg.rx * tg.ry * tg.rz;  // logical region nodes
     const int rzy = tg.ry * tg.rz;
+    const int sx = tg.ryp * tg.rzp, sy = tg.rzp;
 
     // stage the region's node fields, zero the region's moments
-    for (int r = threadIdx.x; r < RN; r += blockDim.x) {
+    for (int r = threadIdx.x; r < RL; r += blockDim.x) {
         const int ri = r / rzy, rj = (r / tg.rz) % tg.ry, rk = r % tg.rz;
-        const int gi = (ox + ri) % g.nx, gj = (oy + rj) % g.ny, gk = (oz + rk) % g.nz;
-        const int gn = (gi * g.ny + gj) * g.nz + gk;
+        const int gn = region_node(g.nx, g.ny, g.nz, ox, oy, oz, ri, rj, rk);
         LdsFieldNode<TP> fn;
 #pragma unroll
         for (int m = 0; m < 6; ++m) fn.v[m] = (TP)f.f[m][gn];
-        fl[r] = fn;
+        fl[ri * sx + rj * sy + rk] = fn;
     }
-    for (int q = threadIdx.x; q < RN * MSTRIDE; q += blockDim.x) ml[q] = TA(0);
+    if (mom)
+        for (int q = threadIdx.x; q < 10 * RNP; q += blockDim.x) ml[q] = TA(0);
     __syncthreads();
 
-    const uint32_t beg = tile_off[t], end = tile_off[t + 1];
-    for (uint32_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
-        TP xn = p.x[i], yn = p.y[i], zn = p.z[i];
-        TP un = p.u[i], vn = p.v[i], wn = p.w[i];
+    const int coff[8] = {0, sx, sy, sx + sy, 1, sx + 1, sy + 1, sx + sy + 1};
+    TA acc[HOME ? 80 : 1];
+#pragma unroll
+    for (int q = 0; q < (HOME ? 80 : 1); ++q) acc[q] = TA(0);
+    int home = -1;
+
+    const uint32_t stride = blockDim.x;
+    uint32_t i = beg + threadIdx.x;
+    TP nx_ = 0, ny_ = 0, nz_ = 0, nu_ = 0, nv_ = 0, nw_ = 0, nq_ = 0;
+    if (i < end) {
+        nx_ = p.x[i]; ny_ = p.y[i]; nz_ = p.z[i];
+        nu_ = p.u[i]; nv_ = p.v[i]; nw_ = p.w[i]; nq_ = p.q[i];
+    }
+    for (; i < end; i += stride) {
+        TP xn = nx_, yn = ny_, zn = nz_, un = nu_, vn = nv_, wn = nw_;
+        const TP qp = nq_;
+        const uint32_t inext = i + stride;
+        if (inext < end) {  // prefetch the next particle while this one is moved
+            nx_ = p.x[inext]; ny_ = p.y[inext]; nz_ = p.z[inext];
+            nu_ = p.u[inext]; nv_ = p.v[inext]; nw_ = p.w[inext]; nq_ = p.q[inext];
+        }
         implicit_move(
-            g, mv,
+            g, J.mv,
             [&](TP px, TP py, TP pz, TP F[6]) {
                 int rb;
                 Cell<TP> c;
-                if (region_cell(g, tg, ox, oy, oz, px, py, pz, rb, c)) {
+                if (region_locate(g, tg, ox, oy, oz, px, py, pz, rb, c)) {
                     gather_lds(fl, tg, rb, c, F);
                 } else {
                     gather_cell_global(f, c, F);
@@ -127,68 +170,130 @@ k_fused_tiled(GridT<TP> g, GridT<TA> ga, FieldPtrs<TF> f, MoveT<TP> mv, PartPtrs
         if (!mom) continue;
 
         // deposit of the new state in the accumulation precision
-        const TA qa = (TA)p.q[i];
+        const TA qa = (TA)qp;
         const TA ua = (TA)un, va = (TA)vn, wa = (TA)wn;
         int rb;
         Cell<TA> c;
-        const bool in = region_cell(ga, tg, ox, oy, oz, (TA)xn, (TA)yn, (TA)zn, rb, c);
+        const bool in = region_locate(J.ga, tg, ox, oy, oz, (TA)xn, (TA)yn, (TA)zn, rb, c);
         TA wt8[8];
         pweights(c.fx, c.fy, c.fz, wt8);
         const TA val[10] = {TA(1), ua, va, wa, ua * ua, ua * va, ua * wa, va * va, va * wa, wa * wa};
-        if (in) {
-            const int sx = tg.ry * tg.rz, sy = tg.rz;
-            const int nd[8] = {rb, rb + sx, rb + sy, rb + sx + sy, rb + 1, rb + sx + 1, rb + sy + 1,
-                               rb + sx + sy + 1};
+        if (HOME && in && home < 0) home = rb;
+        if (HOME && in && rb == home) {
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const TA qw = qa * wt8[k];
-                TA *dst = ml + nd[k] * MSTRIDE;
 #pragma unroll
-                for (int m = 0; m < 10; ++m) atomicAdd(dst + m, qw * val[m]);
+                for (int m = 0; m < 10; ++m) acc[(k * 10 + m) % (HOME ? 80 : 1)] += qw * val[m];
             }
-        } else {
+        } else if (in) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const TA qw = qa * wt8[k];
+                TA *dst = ml + rb + coff[k];
+#pragma unroll
+                for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, qw * val[m]);
+            }
+        } else {  // rare: the particle left the region
             int nd[8];
             pnodes(c, nd);
-#pragma unroll
+#pragma unroll 1
             for (int k = 0; k < 8; ++k) {
                 const TA qw = qa * wt8[k];
-#pragma unroll
-                for (int m = 0; m < 10; ++m) atomicAdd(mom + (size_t)m * nn + nd[k], qw * val[m]);
+                TA *dst = mom + nd[k];
+#pragma unroll 1
+                for (int m = 0; m < 10; ++m) atomicAdd(dst + (size_t)m * nn, qw * val[m]);
             }
         }
     }
     if (!mom) return;
+    if (HOME && home >= 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            TA *dst = ml + home + coff[k];
+#pragma unroll
+            for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, acc[(k * 10 + m) % (HOME ? 80 : 1)]);
+        }
+    }
     __syncthreads();
     // flush: region accumulator -> global moments (skip exact zeros: halo
     // nodes no particle reached)
-    for (int q = threadIdx.x; q < RN * 10; q += blockDim.x) {
-        const int m = q / RN, r = q - m * RN;
-        const TA val = ml[r * MSTRIDE + m];
-        if (val != TA(0)) {
-            const int ri = r / rzy, rj = (r / tg.rz) % tg.ry, rk = r % tg.rz;
-            const int gi = (ox + ri) % g.nx, gj = (oy + rj) % g.ny, gk = (oz + rk) % g.nz;
-            atomicAdd(mom + (size_t)m * nn + (gi * g.ny + gj) * g.nz + gk, val);
-        }
+    for (int q = threadIdx.x; q < RL * 10; q += blockDim.x) {
+        const int m = q / RL, r = q - m * RL;
+        const int ri = r / rzy, rj = (r / tg.rz) % tg.ry, rk = r % tg.rz;
+        const TA val = ml[m * RNP + ri * sx + rj * sy + rk];
+        if (val != TA(0))
+            atomicAdd(mom + (size_t)m * nn + region_node(g.nx, g.ny, g.nz, ox, oy, oz, ri, rj, rk), val);
+    }
+}
+
+// HOME: deposit into per-thread home-cell registers (80 sums) and LDS for
+// drifted particles; else every deposit is an LDS atomic, which needs far
+// fewer registers and so runs twice as many waves per SIMD.
+template <typename TP, typename TF, typename TA, bool HOME>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HOME ? 2 : 4)))
+k_fused_tiled(TileJob<TP, TF, TA> J, int chunk) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int b = blockIdx.x;
+    const int t = (b & 7) * chunk + (b >> 3);
+    if (t >= J.tg.ntiles) return;
+    tile_body<TP, TF, TA, HOME>(J, t, smem);
+}
+
+// Persistent work-list kernel: workgroups take (job, tile) items from an
+// atomic counter until the list is drained; every workgroup exits once the
+// counter passes nitems.  The counter must be zero at launch.
+template <typename TP, typename TF, typename TA, bool HOME>
+__global__ void __launch_bounds__(512)
+k_worklist(const TileJob<TP, TF, TA> *__restrict__ jobs, const uint2 *__restrict__ items, int nitems,
+           unsigned *__restrict__ counter) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int cur;
+    for (;;) {
+        __syncthreads();  // the previous item's LDS use is over before `cur` changes
+        if (threadIdx.x == 0) cur = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(cur);
+        if (it >= nitems) break;
+        const uint2 item = items[it];
+        const TileJob<TP, TF, TA> J = jobs[item.x];
+        tile_body<TP, TF, TA, HOME>(J, (int)item.y, smem);
     }
 }
 
 size_t tiled_lds_bytes(const TileGeom &tg, int dtype, int acc_dtype) {
-    const size_t RN = (size_t)tg.rx * tg.ry * tg.rz;
-    const size_t fsz = RN * 6 * (dtype == SPIC_F64 ? 8 : 4);
-    const size_t msz = RN * MSTRIDE * (acc_dtype == SPIC_F64 ? 8 : 4);
+    const size_t fsz = (size_t)tg.rnp * 6 * (dtype == SPIC_F64 ? 8 : 4);
+    const size_t msz = (size_t)tg.rnp * 10 * (acc_dtype == SPIC_F64 ? 8 : 4);
     return ((fsz + 15) & ~(size_t)15) + msz;
+}
+
+// Dynamic LDS above 64 KiB must be allowed per kernel once.
+template <typename K>
+static void allow_lds(K kernel, size_t bytes) {
+    static size_t allowed = 64 * 1024;
+    if (bytes > allowed) {
+        if (hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
+            hipSuccess)
+            allowed = bytes;
+    }
 }
 
 template <typename TP, typename TF, typename TA>
 static void tiled_t(const spic_grid &g, const spic_params &prm, const spic_fields &f, const SpeciesWork &w,
                     const TileGeom &tg, const uint32_t *tile_off, const LaunchCfg &cfg, hipStream_t s) {
-    const int nn = g.nx * g.ny * g.nz;
     const int chunk = (tg.ntiles + 7) / 8;
     const size_t lds = tiled_lds_bytes(tg, sizeof(TP) == 8 ? SPIC_F64 : SPIC_F32,
                                        sizeof(TA) == 8 ? SPIC_F64 : SPIC_F32);
-    hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA>), dim3(8 * chunk), dim3(cfg.tile_block), lds, s,
-                       make_grid_t<TP>(g), make_grid_t<TA>(g), field_ptrs<TF>(f), make_move<TP>(prm, w.qom),
-                       part_ptrs<TP>(w), (TA *)w.mom, nn, tile_off, tg, chunk);
+    const auto job = make_tile_job<TP, TF, TA>(g, prm, f, w, tg, tile_off);
+    if (cfg.home_acc) {
+        allow_lds(k_fused_tiled<TP, TF, TA, true>, lds);
+        hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, true>), dim3(8 * chunk), dim3(cfg.tile_block), lds, s, job,
+                           chunk);
+    } else {
+        allow_lds(k_fused_tiled<TP, TF, TA, false>, lds);
+        hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, false>), dim3(8 * chunk), dim3(cfg.tile_block), lds, s, job,
+                           chunk);
+    }
 }
 
 hipError_t launch_fused_tiled(const spic_grid &g, const spic_params &prm, const spic_fields &f,
@@ -206,6 +311,121 @@ hipError_t launch_fused_tiled(const spic_grid &g, const spic_params &prm, const 
         if (f64acc) tiled_t<float, double, double>(g, prm, f, w, tg, tile_off, cfg, s);
         else tiled_t<float, double, float>(g, prm, f, w, tg, tile_off, cfg, s);
     }
+    return hipGetLastError();
+}
+
+}  // namespace spic
+
+// ------------------------------------------------------------ work lists
+//
+// The batch engine drives the persistent work-list kernel over tiles of
+// many (run, species) jobs of one precision combination per launch.
+
+namespace spic {
+
+int job_combo(int dtype, int fdtype, int acc_dtype) {
+    if (dtype == SPIC_F64) return (fdtype == SPIC_F64 && acc_dtype == SPIC_F64) ? 0 : -1;
+    if (fdtype == SPIC_F32) return acc_dtype == SPIC_F64 ? 1 : 2;
+    return acc_dtype == SPIC_F64 ? 3 : 4;
+}
+
+size_t tile_job_bytes(int combo) {
+    switch (combo) {
+        case 0: return sizeof(TileJob<double, double, double>);
+        case 1: return sizeof(TileJob<float, float, double>);
+        case 2: return sizeof(TileJob<float, float, float>);
+        case 3: return sizeof(TileJob<float, double, double>);
+        default: return sizeof(TileJob<float, double, float>);
+    }
+}
+
+void write_tile_job(int combo, void *dst, const spic_grid &g, const spic_params &prm, const spic_fields &f,
+                    const SpeciesWork &w, const TileGeom &tg, const uint32_t *tile_off) {
+    switch (combo) {
+        case 0: *(TileJob<double, double, double> *)dst = make_tile_job<double, double, double>(g, prm, f, w, tg, tile_off); break;
+        case 1: *(TileJob<float, float, double> *)dst = make_tile_job<float, float, double>(g, prm, f, w, tg, tile_off); break;
+        case 2: *(TileJob<float, float, float> *)dst = make_tile_job<float, float, float>(g, prm, f, w, tg, tile_off); break;
+        case 3: *(TileJob<float, double, double> *)dst = make_tile_job<float, double, double>(g, prm, f, w, tg, tile_off); break;
+        default: *(TileJob<float, double, float> *)dst = make_tile_job<float, double, float>(g, prm, f, w, tg, tile_off); break;
+    }
+}
+
+// Workgroups of the persistent launch: resident workgroups per CU times
+// CUs, capped by the item count (and by max_groups when > 0).  Also allows
+// the LDS size; call before any stream capture.
+template <typename TP, typename TF, typename TA, bool HOME>
+static int worklist_groups_t(size_t lds, int block, int nitems, int max_groups) {
+    auto k = k_worklist<TP, TF, TA, HOME>;
+    allow_lds(k, lds);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    int groups = per_cu * ncu;
+    if (groups > nitems) groups = nitems;
+    if (max_groups > 0 && groups > max_groups) groups = max_groups;
+    return groups < 1 ? 1 : groups;
+}
+
+int worklist_groups(int combo, bool home, size_t lds, int block, int nitems, int max_groups) {
+#define SPIC_WG(TP, TF, TA)                                                                     \
+    return home ? worklist_groups_t<TP, TF, TA, true>(lds, block, nitems, max_groups)          \
+                : worklist_groups_t<TP, TF, TA, false>(lds, block, nitems, max_groups)
+    switch (combo) {
+        case 0: SPIC_WG(double, double, double);
+        case 1: SPIC_WG(float, float, double);
+        case 2: SPIC_WG(float, float, float);
+        case 3: SPIC_WG(float, double, double);
+        default: SPIC_WG(float, double, float);
+    }
+#undef SPIC_WG
+}
+
+template <typename TP, typename TF, typename TA, bool HOME>
+static hipError_t worklist_t(const void *jobs, const uint2 *items, int nitems, unsigned *counter, size_t lds,
+                             int block, int groups, hipStream_t s) {
+    hipLaunchKernelGGL((k_worklist<TP, TF, TA, HOME>), dim3(groups), dim3(block), lds, s,
+                       (const TileJob<TP, TF, TA> *)jobs, items, nitems, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_worklist(int combo, bool home, const void *jobs, const uint2 *items, int nitems,
+                           unsigned *counter, size_t lds, int block, int groups, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+#define SPIC_WL(TP, TF, TA)                                                                                  \
+    return home ? worklist_t<TP, TF, TA, true>(jobs, items, nitems, counter, lds, block, groups, s)         \
+                : worklist_t<TP, TF, TA, false>(jobs, items, nitems, counter, lds, block, groups, s)
+    switch (combo) {
+        case 0: SPIC_WL(double, double, double);
+        case 1: SPIC_WL(float, float, double);
+        case 2: SPIC_WL(float, float, float);
+        case 3: SPIC_WL(float, double, double);
+        default: SPIC_WL(float, double, float);
+    }
+#undef SPIC_WL
+}
+
+// Zero many arrays in one launch: array a has counts[a] elements of
+// elem_bytes (4 or 8) bytes.
+__global__ void k_fill_many(void *const *__restrict__ ptrs, const int64_t *__restrict__ counts, int narr,
+                            int elem_bytes) {
+    const int a = blockIdx.y;
+    if (a >= narr) return;
+    const int64_t n = counts[a];
+    if (elem_bytes == 8) {
+        double *p = (double *)ptrs[a];
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+            p[i] = 0.0;
+    } else {
+        float *p = (float *)ptrs[a];
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+            p[i] = 0.0f;
+    }
+}
+
+hipError_t launch_fill_many(void *const *ptrs, const int64_t *counts, int narr, int elem_bytes, hipStream_t s) {
+    if (narr <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_many, dim3(64, narr), dim3(256), 0, s, ptrs, counts, narr, elem_bytes);
     return hipGetLastError();
 }
 

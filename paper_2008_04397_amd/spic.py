@@ -251,12 +251,6 @@ def spic_sort(ctx: Context, grid, species: Sequence[dict], stream=None, raw: boo
     return st if raw else ctx.check(st)
 
 
-def spic_wait(ctx: Context, ticket: int) -> float:
-    secs = C.c_double()
-    ctx.check(lib().spic_wait(ctx.handle, int(ticket), C.byref(secs)))
-    return secs.value
-
-
 def spic_poll(ctx: Context, ticket: int) -> bool:
     done = C.c_int32()
     ctx.check(lib().spic_poll(ctx.handle, int(ticket), C.byref(done)))
@@ -285,3 +279,81 @@ def moment_buffers(grid, nsp: int, dtype=None, device="cuda"):
     import torch
     dtype = dtype or torch.float64
     return [torch.zeros((10, grid.nx * grid.ny * grid.nz), dtype=dtype, device=device) for _ in range(nsp)]
+
+
+# ----------------------------------------------------------- batch engine
+
+class Run:
+    """One multi-step run for spic_batch_submit.
+
+    species: list of dicts of tensors (device tensors, or pinned host tensors
+    for host-resident species); qoms: charge-to-mass ratio per species;
+    moments: list of device tensors [10, nodes] or None.
+    """
+
+    def __init__(self, grid, params, fields, species, qoms, moments=None, nsteps=1):
+        self.grid, self.params, self.fields = grid, params, fields
+        self.species, self.qoms, self.moments, self.nsteps = list(species), list(qoms), moments, int(nsteps)
+
+    def _host(self, s):
+        x = s["x"]
+        return (not hasattr(x, "is_cuda")) or (not x.is_cuda)
+
+    def to_c(self):
+        sps = [make_species(s, q, host_resident=self._host(s)) for s, q in zip(self.species, self.qoms)]
+        sp_arr = _arr(spic_species, sps)
+        mom_arr = _arr(spic_moment_array, [make_moments(m) for m in self.moments]) if self.moments is not None else None
+        r = spic_run()
+        r.grid = make_grid(self.grid)
+        r.params = self.params
+        r.fields = make_fields(self.fields)
+        r.species = C.cast(sp_arr, C.POINTER(spic_species))
+        r.moments = C.cast(mom_arr, C.POINTER(spic_moment_array)) if mom_arr is not None else None
+        r.nspecies = len(self.species)
+        r.nsteps = self.nsteps
+        return r, (sp_arr, mom_arr)
+
+
+def spic_batch_submit(ctx: Context, runs: Sequence[Run], raw: bool = False):
+    """Submit runs; returns their tickets.  The runs' tensors are kept
+    referenced by the context until their ticket has been waited on."""
+    cs, keep = [], []
+    for r in runs:
+        c, k = r.to_c()
+        cs.append(c)
+        keep.append(k)
+    arr = _arr(spic_run, cs)
+    tickets = (C.c_uint64 * max(1, len(runs)))()
+    st = lib().spic_batch_submit(ctx.handle, arr, len(runs), tickets)
+    if raw and st != SPIC_OK:
+        return st
+    ctx.check(st)
+    if not hasattr(ctx, "_inflight"):
+        ctx._inflight = {}
+    out = []
+    for i, r in enumerate(runs):
+        ctx._inflight[int(tickets[i])] = r
+        out.append(int(tickets[i]))
+    return out
+
+
+def spic_wait(ctx: Context, ticket: int) -> float:
+    """Block until the ticket's run is done; returns its device seconds and
+    releases the run's tensors."""
+    secs = C.c_double()
+    st = lib().spic_wait(ctx.handle, int(ticket), C.byref(secs))
+    getattr(ctx, "_inflight", {}).pop(int(ticket), None)
+    ctx.check(st)
+    return secs.value
+
+
+def pinned_like(arrs: Dict[str, np.ndarray], dtype) -> Dict[str, "object"]:
+    """Copy numpy arrays into pinned (page-locked) host tensors."""
+    import torch
+    out = {}
+    for k, v in arrs.items():
+        t = torch.from_numpy(np.ascontiguousarray(v))
+        if t.is_floating_point():
+            t = t.to(dtype)
+        out[k] = t.pin_memory()
+    return out

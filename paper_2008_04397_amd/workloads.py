@@ -342,3 +342,64 @@ def serving_stream(n_req: int = 1000, rate: float = 20.0, seed: int = 5,
         g = Grid(nx, max(2, nx // 2), nz)
         reqs.append(Request(k, t, Harris(g, ppc=ppc, seed=seed * 100000 + k), steps))
     return reqs
+
+
+# ---------------------------------------------------------------------------
+# Device-side generator for workloads that are never compared with the
+# oracle (serving streams, the 2.1e9-particle streamed box): the same recipe
+# as species_slab (lattice positions, Maxwellian velocities, density in q),
+# drawn with torch's seeded generator on the GPU, so inputs of millions of
+# particles are produced in milliseconds.  Values differ from species_slab's.
+# ---------------------------------------------------------------------------
+
+def species_tensors(h: Harris, s: int, i0: int = 0, i1: Optional[int] = None, device="cuda", dtype=None,
+                    seed_offset: int = 0):
+    import torch
+    dtype = dtype or torch.float32
+    g = h.grid
+    i1 = g.nx if i1 is None else i1
+    dx, dy, dz = g.d
+    ppc = h.ppc
+    m = _lattice_side(ppc)
+    gen = torch.Generator(device=device)
+    gen.manual_seed((h.seed * 1_000_003 + s * 10_007 + i0 * 101 + seed_offset) & 0x7FFFFFFFFFFFFFFF)
+    nxs = i1 - i0
+    ncell = nxs * g.ny * g.nz
+    n = ncell * ppc
+    cell = torch.arange(ncell, device=device, dtype=torch.int64).repeat_interleave(ppc)
+    k = cell % g.nz
+    j = (cell // g.nz) % g.ny
+    i = cell // (g.nz * g.ny) + i0
+    if m:
+        a = torch.arange(ppc, device=device, dtype=torch.int64).repeat(ncell)
+        fa = ((a // (m * m)) + 0.5) / m
+        fb = (((a // m) % m) + 0.5) / m
+        fc = ((a % m) + 0.5) / m
+    else:
+        fa = torch.rand(n, generator=gen, device=device, dtype=torch.float64)
+        fb = torch.rand(n, generator=gen, device=device, dtype=torch.float64)
+        fc = torch.rand(n, generator=gen, device=device, dtype=torch.float64)
+    x = (i.double() + fa) * dx
+    y = (j.double() + fb) * dy
+    z = (k.double() + fc) * dz
+    vth = h.vths[s]
+    u = torch.randn(n, generator=gen, device=device, dtype=torch.float32) * vth
+    v = torch.randn(n, generator=gen, device=device, dtype=torch.float32) * vth
+    w = torch.randn(n, generator=gen, device=device, dtype=torch.float32) * vth
+    if s in (SHEET_E, SHEET_I) and h.drift_z != 0.0:
+        w = w + (h.drift_z if s == SHEET_I else -h.drift_z)
+    if s in (SHEET_E, SHEET_I):
+        dens = 1.0 / torch.cosh((y - 0.5 * g.Ly) / h.delta) ** 2
+    else:
+        dens = torch.full_like(y, h.n_bg)
+    q = math.copysign(1.0, h.qoms[s]) * dens * (dx * dy * dz / ppc)
+    out = {"x": x.to(dtype), "y": y.to(dtype), "z": z.to(dtype), "u": u.to(dtype), "v": v.to(dtype),
+           "w": w.to(dtype), "q": q.to(dtype)}
+    return out
+
+
+def fields_tensors(h: Harris, device="cuda", dtype=None):
+    """make_fields (numpy, seeded) moved to the device: fields are small."""
+    import torch
+    dtype = dtype or torch.float32
+    return {k: torch.from_numpy(v).to(device=device, dtype=dtype) for k, v in make_fields(h).items()}

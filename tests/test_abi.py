@@ -121,3 +121,55 @@ def test_python_binding_refuses_to_run_without_the_library(monkeypatch, tmp_path
     monkeypatch.setattr(spic, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         spic.lib()
+
+
+def test_batch_submit_validates_on_the_host(hctx):
+    """spic_batch_submit checks every run before anything is queued; a valid
+    set reaches the host-only stop, an invalid one names the run."""
+    a = _HostArrays()
+    g = W.Grid(8, 8, 8)
+
+    def runs(mut=None):
+        r = spic.spic_run()
+        r.grid = spic.make_grid(g)
+        r.params = spic.make_params(0.25, 1.0, 3, 4, 0)
+        r.fields = spic.make_fields(a.f)
+        sp = spic._arr(spic.spic_species, [spic.make_species(a.sp, -64.0, host_resident=True)])
+        mom = spic._arr(spic.spic_moment_array, [spic.make_moments(a.m)])
+        r.species = C.cast(sp, C.POINTER(spic.spic_species))
+        r.moments = C.cast(mom, C.POINTER(spic.spic_moment_array))
+        r.nspecies = 1
+        r.nsteps = 5
+        if mut:
+            mut(r)
+        return spic._arr(spic.spic_run, [r]), (sp, mom)
+
+    t = (C.c_uint64 * 1)()
+    arr, keep = runs()
+    assert spic.lib().spic_batch_submit(hctx.handle, arr, 1, t) == spic.SPIC_E_STATE
+    arr, keep = runs(lambda r: setattr(r, "nsteps", -1))
+    assert spic.lib().spic_batch_submit(hctx.handle, arr, 1, t) == spic.SPIC_E_ARG
+    arr, keep = runs(lambda r: setattr(r.params, "niter_mover", 0))
+    assert spic.lib().spic_batch_submit(hctx.handle, arr, 1, t) == spic.SPIC_E_ARG
+    assert "run 0" in spic.lib().spic_last_error(hctx.handle).decode()
+    assert spic.lib().spic_batch_submit(hctx.handle, arr, 1, None) == spic.SPIC_E_ARG
+    assert spic.lib().spic_wait(hctx.handle, 1, None) == spic.SPIC_E_STATE
+
+
+def test_autotune_cache_roundtrip(tmp_path, monkeypatch):
+    from paper_2008_04397_amd import autotune
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "tuned.json"))
+    key = autotune.workload_class("f32", W.Grid(128, 64, 32), 64)
+    assert key == "f32/cells262144/ppc64"
+    assert autotune.load(key) is None
+    autotune.store(key, dict(autotune.DEFAULT))
+    assert autotune.load(key) == autotune.DEFAULT
+    assert len(list(autotune.candidates(quick=True))) == 12
+
+
+def test_serving_summary_statistics():
+    from paper_2008_04397_amd import serving
+    done = [serving.Done(i, float(i), float(i), float(i) + 0.1 * (i + 1), 1000, 10, 0.05) for i in range(100)]
+    s = serving.summarize(done)
+    assert abs(s["p50_s"] - 5.05) < 0.06 and abs(s["p99_s"] - 9.9) < 0.02
+    assert s["particle_steps"] == 100 * 1000 * 10

@@ -1,0 +1,184 @@
+"""GPU tests of spic_batch_submit: many runs stepped together by the
+persistent work-list kernel, continuous admission under an HBM budget,
+host-resident runs, streamed runs (particle batching through two device
+slots), hipGraph replay -- each result against the oracle or against the
+same run executed alone."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2008_04397_amd import workloads as W
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def spic():
+    from paper_2008_04397_amd import spic as S
+    S.lib()
+    return S
+
+
+def _boxes():
+    """Three small boxes of different shape, ppc and mass ratio."""
+    return [W.Harris(W.Grid(16, 8, 4), ppc=8, qom_e=-25.0, B0=0.02, seed=11),
+            W.Harris(W.Grid(12, 6, 8), ppc=27, qom_e=-64.0, B0=0.015, seed=12),
+            W.Harris(W.Grid(8, 8, 4), ppc=10, qom_e=-100.0, B0=0.03, seed=13)]
+
+
+def _run_of(spic, h, nsteps, dtype=torch.float64, host=False, sort_every=2):
+    f = spic.to_device(W.make_fields(h), dtype)
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    sps = [W.make_species(h, s, dtype=npdt) for s in range(4)]
+    if host:
+        dev = [spic.pinned_like(s, dtype) for s in sps]
+    else:
+        dev = [spic.to_device(s, dtype) for s in sps]
+    moms = spic.moment_buffers(h.grid, 4)
+    prm = spic.make_params(h.dt, h.c, h.niter, sort_every, 0)
+    return spic.Run(h.grid, prm, f, dev, h.qoms, moms, nsteps), sps
+
+
+def _oracle(h, sps, nsteps):
+    f = W.make_fields(h)
+    return O.run(h, f, [W.upcast(s) for s in sps], nsteps)
+
+
+def _host(run):
+    return [spic_to_host(s) for s in run.species]
+
+
+def spic_to_host(s):
+    return {k: v.detach().cpu().numpy() for k, v in s.items()}
+
+
+def test_resident_runs_together_match_oracle(spic):
+    ctx = spic.Context(0)
+    boxes = _boxes()
+    runs, inputs = zip(*[_run_of(spic, h, 4) for h in boxes])
+    _say("case batch resident 3 boxes x 4 steps")
+    tickets = spic.spic_batch_submit(ctx, runs)
+    for t in tickets:
+        assert spic.spic_wait(ctx, t) >= 0.0
+    for h, run, sps in zip(boxes, runs, inputs):
+        st, ms = _oracle(h, sps, 4)
+        got = _host(run)
+        for s in range(4):
+            P.assert_state(got[s], st[s], h.grid, P.POS64, P.VEL64)
+            P.assert_moments(run.moments[s].cpu().numpy(), ms[s], P.MOM64)
+    ctx.close()
+
+
+def test_each_run_alone_equals_the_mix(spic):
+    """Continuous batching must not change results: every run submitted
+    alone gives the same particles (bitwise, by id) and moments as in the
+    mix, where runs of different lengths overlap."""
+    boxes = _boxes()
+    steps = [3, 6, 2]
+    ctx = spic.Context(0)
+    alone = []
+    for h, n in zip(boxes, steps):
+        run, _ = _run_of(spic, h, n)
+        spic.spic_wait(ctx, spic.spic_batch_submit(ctx, [run])[0])
+        alone.append(run)
+    mixed = [_run_of(spic, h, n)[0] for h, n in zip(boxes, steps)]
+    tickets = spic.spic_batch_submit(ctx, mixed[:1])
+    tickets += spic.spic_batch_submit(ctx, mixed[1:])   # arrives while the first runs
+    for t in tickets:
+        spic.spic_wait(ctx, t)
+    for a, b, h in zip(alone, mixed, boxes):
+        for s in range(4):
+            x, y = P.by_id(spic_to_host(a.species[s])), P.by_id(spic_to_host(b.species[s]))
+            for k in ("x", "y", "z", "u", "v", "w"):
+                assert np.array_equal(x[k], y[k])
+            P.assert_moments(b.moments[s].cpu().numpy(), a.moments[s].cpu().numpy(), 1e-14)
+    ctx.close()
+
+
+def test_admission_under_a_small_budget(spic):
+    """Host-resident runs whose total footprint exceeds the budget are
+    admitted a few at a time as others retire; all complete correctly."""
+    boxes = _boxes() * 2
+    one = max(sum(W.make_species(h, s)["x"].size for s in range(4)) * (7 * 8 + 8) for h in boxes)
+    ctx = spic.Context(0, hbm_budget_bytes=int(2.5 * one) + (1 << 20))
+    made = [_run_of(spic, h, 3, host=True) for h in boxes]
+    runs = [m[0] for m in made]
+    _say("case batch admission budget %d bytes" % int(2.5 * one))
+    tickets = spic.spic_batch_submit(ctx, runs)
+    for t in tickets:
+        spic.spic_wait(ctx, t)
+    for (run, sps), h in zip(made, boxes):
+        st, ms = _oracle(h, sps, 3)
+        got = _host(run)
+        for s in range(4):
+            P.assert_state(got[s], st[s], h.grid, P.POS64, P.VEL64)
+            P.assert_moments(run.moments[s].cpu().numpy(), ms[s], P.MOM64)
+    ctx.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_streamed_run_equals_resident_run(spic, dtype):
+    """A budget of a few MB forces the 32x16x4 box through batches of a few
+    thousand particles; the result equals the resident run's."""
+    h = W.harris_32x16x4()
+    ctx_r = spic.Context(0)
+    res, _ = _run_of(spic, h, 3, dtype=dtype, sort_every=2)
+    spic.spic_wait(ctx_r, spic.spic_batch_submit(ctx_r, [res])[0])
+    ctx_s = spic.Context(0, hbm_budget_bytes=3 << 20)
+    ctx_s.set_option("batch_particles", 8192)
+    stm, _ = _run_of(spic, h, 3, dtype=dtype, host=True, sort_every=2)
+    _say("case streamed %s budget 3 MiB" % dtype)
+    secs = spic.spic_wait(ctx_s, spic.spic_batch_submit(ctx_s, [stm])[0])
+    assert secs > 0
+    for s in range(4):
+        a, b = P.by_id(spic_to_host(res.species[s])), P.by_id(spic_to_host(stm.species[s]))
+        for k in ("x", "y", "z", "u", "v", "w"):
+            assert np.array_equal(a[k], b[k]), k
+        tol = 1e-13 if dtype == torch.float64 else 1e-12
+        P.assert_moments(stm.moments[s].cpu().numpy(), res.moments[s].cpu().numpy(), tol)
+    ctx_r.close()
+    ctx_s.close()
+
+
+def test_graph_replay_matches_plain_launches(spic):
+    boxes = _boxes()
+    out = []
+    for graph in (1, 0):
+        ctx = spic.Context(0)
+        ctx.set_option("graph", graph)
+        runs = [_run_of(spic, h, 5, sort_every=3)[0] for h in boxes]
+        for t in spic.spic_batch_submit(ctx, runs):
+            spic.spic_wait(ctx, t)
+        out.append(runs)
+        ctx.close()
+    for a, b in zip(*out):
+        for s in range(4):
+            x, y = P.by_id(spic_to_host(a.species[s])), P.by_id(spic_to_host(b.species[s]))
+            for k in ("x", "y", "z", "u", "v", "w"):
+                assert np.array_equal(x[k], y[k])
+            P.assert_moments(a.moments[s].cpu().numpy(), b.moments[s].cpu().numpy(), 1e-14)
+
+
+def test_zero_step_run_and_errors(spic):
+    ctx = spic.Context(0)
+    h = _boxes()[0]
+    run, sps = _run_of(spic, h, 0, host=True)
+    spic.spic_wait(ctx, spic.spic_batch_submit(ctx, [run])[0])
+    got = _host(run)
+    for s in range(4):
+        for k in ("x", "u"):
+            np.testing.assert_array_equal(got[s][k], sps[s][k])
+    assert spic.lib().spic_poll(ctx.handle, 987654, (spic.C.c_int32 * 1)()) == spic.SPIC_E_STATE
+    ctx.close()
+    tiny = spic.Context(0, hbm_budget_bytes=4096)
+    run, _ = _run_of(spic, h, 1, host=True)
+    assert spic.spic_batch_submit(tiny, [run], raw=True) == spic.SPIC_E_BUDGET
+    tiny.close()
