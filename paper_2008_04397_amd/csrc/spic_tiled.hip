@@ -87,10 +87,30 @@ __device__ __forceinline__ void gather_lds(const LdsFieldNode<TP> *__restrict__ 
     }
 }
 
-// Global node of a region node's logical coordinates.
-__device__ __forceinline__ int region_node(int nx, int ny, int nz, int ox, int oy, int oz, int ri, int rj, int rk) {
-    const int gi = (ox + ri) % nx, gj = (oy + rj) % ny, gk = (oz + rk) % nz;
-    return (gi * ny + gj) * nz + gk;
+// Periodic index o + r with 0 <= o < n, r >= 0: subtract n while needed
+// (once, unless the region is wider than the grid).
+__device__ __forceinline__ int pwrap_index(int v, int n) {
+    while (v >= n) v -= n;
+    return v;
+}
+
+// Logical region node r -> (ri, rj, rk), its padded LDS slot and its global
+// node.
+struct RegionNode {
+    int slot, gnode;
+};
+
+__device__ __forceinline__ RegionNode region_node(const TileGeom &tg, int nx, int ny, int nz, int ox, int oy, int oz,
+                                                  int r) {
+    const int rzy = tg.ry * tg.rz;
+    const int ri = r / rzy;
+    const int rem = r - ri * rzy;
+    const int rj = rem / tg.rz;
+    const int rk = rem - rj * tg.rz;
+    RegionNode n;
+    n.slot = (ri * tg.ryp + rj) * tg.rzp + rk;
+    n.gnode = (pwrap_index(ox + ri, nx) * ny + pwrap_index(oy + rj, ny)) * nz + pwrap_index(oz + rk, nz);
+    return n;
 }
 
 // One tile of one species: stage the region, move and deposit the tile's
@@ -116,17 +136,15 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
     int oy = (tyi * tg.ty - tg.halo) % g.ny; oy += oy < 0 ? g.ny : 0;
     int oz = (tzi * tg.tz - tg.halo) % g.nz; oz += oz < 0 ? g.nz : 0;
     const int RL = tg.rx * tg.ry * tg.rz;  // logical region nodes
-    const int rzy = tg.ry * tg.rz;
     const int sx = tg.ryp * tg.rzp, sy = tg.rzp;
 
     // stage the region's node fields, zero the region's moments
     for (int r = threadIdx.x; r < RL; r += blockDim.x) {
-        const int ri = r / rzy, rj = (r / tg.rz) % tg.ry, rk = r % tg.rz;
-        const int gn = region_node(g.nx, g.ny, g.nz, ox, oy, oz, ri, rj, rk);
+        const RegionNode rn = region_node(tg, g.nx, g.ny, g.nz, ox, oy, oz, r);
         LdsFieldNode<TP> fn;
 #pragma unroll
-        for (int m = 0; m < 6; ++m) fn.v[m] = (TP)f.f[m][gn];
-        fl[ri * sx + rj * sy + rk] = fn;
+        for (int m = 0; m < 6; ++m) fn.v[m] = (TP)f.f[m][rn.gnode];
+        fl[rn.slot] = fn;
     }
     if (mom)
         for (int q = threadIdx.x; q < 10 * RNP; q += blockDim.x) ml[q] = TA(0);
@@ -217,13 +235,15 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
     }
     __syncthreads();
     // flush: region accumulator -> global moments (skip exact zeros: halo
-    // nodes no particle reached)
-    for (int q = threadIdx.x; q < RL * 10; q += blockDim.x) {
-        const int m = q / RL, r = q - m * RL;
-        const int ri = r / rzy, rj = (r / tg.rz) % tg.ry, rk = r % tg.rz;
-        const TA val = ml[m * RNP + ri * sx + rj * sy + rk];
-        if (val != TA(0))
-            atomicAdd(mom + (size_t)m * nn + region_node(g.nx, g.ny, g.nz, ox, oy, oz, ri, rj, rk), val);
+    // nodes no particle reached); consecutive threads take consecutive region
+    // nodes, so each moment's atomics are coalesced along z
+    for (int r = threadIdx.x; r < RL; r += blockDim.x) {
+        const RegionNode rn = region_node(tg, g.nx, g.ny, g.nz, ox, oy, oz, r);
+#pragma unroll
+        for (int m = 0; m < 10; ++m) {
+            const TA val = ml[m * RNP + rn.slot];
+            if (val != TA(0)) atomicAdd(mom + (size_t)m * nn + rn.gnode, val);
+        }
     }
 }
 
