@@ -1,5 +1,6 @@
 """Autotuner for the fused tiled path: picks the threads per workgroup, the
-deposit variant (home-cell registers or LDS atomics), the halo and the sort
+kernel variant (LDS atomics, + field corners in registers, home-cell
+register accumulation), the halo and the sort
 cadence by timing short runs of the actual workload, and caches the choice
 per (dtype, workload class) in a JSON file next to this module.
 
@@ -18,7 +19,7 @@ from typing import Dict, Iterable, Optional, Sequence
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 
-DEFAULT = {"tile_block": 256, "home_acc": 0, "halo": 1, "tile_x": 4, "tile_y": 4, "tile_z": 4, "sort_every": 4}
+DEFAULT = {"tile_block": 256, "tile_variant": 0, "halo": 1, "tile_x": 4, "tile_y": 4, "tile_z": 4, "sort_every": 4}
 
 
 def workload_class(dtype_name: str, grid, ppc: int) -> str:
@@ -56,12 +57,12 @@ def apply(ctx, cfg: Dict[str, int]):
 
 def candidates(quick: bool = True) -> Iterable[Dict[str, int]]:
     blocks = (256, 512)
-    homes = (0, 1)
+    variants = (0, 1, 2)
     cadences = (2, 4, 8) if quick else (1, 2, 4, 8, 16)
     halos = (1,) if quick else (1, 2)
-    for blk, home, se, halo in itertools.product(blocks, homes, cadences, halos):
+    for blk, var, se, halo in itertools.product(blocks, variants, cadences, halos):
         c = dict(DEFAULT)
-        c.update(tile_block=blk, home_acc=home, sort_every=se, halo=halo)
+        c.update(tile_block=blk, tile_variant=var, sort_every=se, halo=halo)
         yield c
 
 

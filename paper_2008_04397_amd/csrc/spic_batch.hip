@@ -137,7 +137,7 @@ struct BatchEngine {
     std::vector<uint64_t> graph_key;
 
     // tuning, read from the ctx options when the engine starts
-    int tile_block = 256, home_acc = 0, use_graph = 1, max_groups = 0;
+    int tile_block = 256, variant = 0, use_graph = 1, max_groups = 0;
     int64_t batch_particles = (int64_t)1 << 26;
     LaunchCfg lcfg;
 
@@ -493,7 +493,7 @@ struct BatchEngine {
         // 3. the step itself (captured as a graph when enabled); launch sizes
         // are settled before the capture starts
         std::map<int, int> groups;
-        for (auto &kv : combos) groups[kv.first] = worklist_groups(kv.first, home_acc != 0, kv.second.lds, tile_block,
+        for (auto &kv : combos) groups[kv.first] = worklist_groups(kv.first, variant, kv.second.lds, tile_block,
                                                                  (int)kv.second.items.size(), max_groups);
         bool capturing = false;
         if (use_graph && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) capturing = true;
@@ -506,7 +506,7 @@ struct BatchEngine {
         int ci = 0;
         for (auto &kv : combos) {
             if (e != hipSuccess) break;
-            e = launch_worklist(kv.first, home_acc != 0, d + co[kv.first].first,
+            e = launch_worklist(kv.first, variant, d + co[kv.first].first,
                                 (const uint2 *)(d + co[kv.first].second), (int)kv.second.items.size(),
                                 (unsigned *)(d + o_ctr) + (ci++ % 8), kv.second.lds, tile_block, groups[kv.first], cs);
         }
@@ -772,7 +772,7 @@ int spic_ctx_s::batch_submit(const spic_run *runs, int32_t nruns, uint64_t *tick
     if (!batch) {
         batch.reset(new BatchEngine(this));
         batch->tile_block = (int)opt("tile_block", 256);
-        batch->home_acc = (int)opt("home_acc", 0);
+        batch->variant = (int)opt("tile_variant", 0);
         batch->use_graph = (int)opt("graph", 1);
         batch->batch_particles = opt("batch_particles", (int64_t)1 << 26);
         batch->max_groups = (int)opt("max_groups", 0);

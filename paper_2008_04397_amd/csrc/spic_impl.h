@@ -53,7 +53,7 @@ struct LaunchCfg {
     int block = 256;        // generic kernels
     int grid_cap = 1 << 20;
     int tile_block = 256;   // tiled fused kernel
-    int home_acc = 0;       // tiled kernel: home-cell register accumulation
+    int variant = 0;        // tiled kernel variant (see spic_tiled.hip)
 };
 
 // Tiles of tx x ty x tz cells (at most 64 cells) cover the grid; ntx.. are
@@ -178,8 +178,8 @@ int job_combo(int dtype, int fdtype, int acc_dtype);
 size_t tile_job_bytes(int combo);
 void write_tile_job(int combo, void *dst, const spic_grid &g, const spic_params &prm, const spic_fields &f,
                     const SpeciesWork &w, const TileGeom &tg, const uint32_t *tile_off);
-int worklist_groups(int combo, bool home, size_t lds, int block, int nitems, int max_groups);
-hipError_t launch_worklist(int combo, bool home, const void *jobs, const uint2 *items, int nitems,
+int worklist_groups(int combo, int variant, size_t lds, int block, int nitems, int max_groups);
+hipError_t launch_worklist(int combo, int variant, const void *jobs, const uint2 *items, int nitems,
                            unsigned *counter, size_t lds, int block, int groups, hipStream_t s);
 hipError_t launch_fill_many(void *const *ptrs, const int64_t *counts, int narr, int elem_bytes, hipStream_t s);
 

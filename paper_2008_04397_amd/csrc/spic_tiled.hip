@@ -117,8 +117,10 @@ __device__ __forceinline__ RegionNode region_node(const TileGeom &tg, int nx, in
 // particles, flush the region's moments.  Called by the per-species tiled
 // kernel and by the work-list kernel of the batch engine; `t` is uniform
 // across the workgroup.
-template <typename TP, typename TF, typename TA, bool HOME>
+template <typename TP, typename TF, typename TA, int VAR>
 __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, unsigned char *smem) {
+    constexpr bool HOME = VAR == 2;   // home-cell register accumulation
+    constexpr bool CACHE = VAR == 1;  // field corners of the last cell in registers
     const GridT<TP> &g = J.g;
     const TileGeom &tg = J.tg;
     const FieldPtrs<TF> &f = J.f;
@@ -155,6 +157,8 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
 #pragma unroll
     for (int q = 0; q < (HOME ? 80 : 1); ++q) acc[q] = TA(0);
     int home = -1;
+    LdsFieldNode<TP> corner[CACHE ? 8 : 1];  // field corners of the cell `cached`
+    int cached = -1;
 
     const uint32_t stride = blockDim.x;
     uint32_t i = beg + threadIdx.x;
@@ -177,7 +181,27 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
                 int rb;
                 Cell<TP> c;
                 if (region_locate(g, tg, ox, oy, oz, px, py, pz, rb, c)) {
-                    gather_lds(fl, tg, rb, c, F);
+                    if (!CACHE) {
+                        gather_lds(fl, tg, rb, c, F);
+                    } else {
+                        // the corners of the last LDS cell stay in registers:
+                        // a thread's particles share their sort cell
+                        if (rb != cached) {
+                            const int nd[8] = {rb, rb + sx, rb + sy, rb + sx + sy, rb + 1, rb + sx + 1, rb + sy + 1,
+                                               rb + sx + sy + 1};
+#pragma unroll
+                            for (int k = 0; k < 8; ++k) corner[k] = fl[nd[k]];
+                            cached = rb;
+                        }
+                        TP w[8];
+                        pweights(c.fx, c.fy, c.fz, w);
+#pragma unroll
+                        for (int m = 0; m < 6; ++m) F[m] = TP(0);
+#pragma unroll
+                        for (int k = 0; k < 8; ++k)
+#pragma unroll
+                            for (int m = 0; m < 6; ++m) F[m] += w[k] * corner[k].v[m];
+                    }
                 } else {
                     gather_cell_global(f, c, F);
                 }
@@ -247,24 +271,32 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
     }
 }
 
-// HOME: deposit into per-thread home-cell registers (80 sums) and LDS for
-// drifted particles; else every deposit is an LDS atomic, which needs far
-// fewer registers and so runs twice as many waves per SIMD.
-template <typename TP, typename TF, typename TA, bool HOME>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(HOME ? 2 : 4)))
+// Variants (register budget -> waves per SIMD):
+//   0  every deposit is an LDS atomic; <= 128 VGPRs, 4 waves/SIMD
+//   1  as 0, and the 48 field corners of the last cell stay in registers,
+//      so gathers in a thread's cell skip LDS; <= 168 VGPRs, 3 waves/SIMD
+//   2  home-cell register accumulation of the deposit (80 sums) with LDS
+//      atomics for drifted particles; <= 256 VGPRs, 2 waves/SIMD
+template <int VAR>
+struct VariantWaves {
+    static constexpr int value = VAR == 0 ? 4 : (VAR == 1 ? 3 : 2);
+};
+
+template <typename TP, typename TF, typename TA, int VAR>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VariantWaves<VAR>::value)))
 k_fused_tiled(TileJob<TP, TF, TA> J, int chunk) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int b = blockIdx.x;
     const int t = (b & 7) * chunk + (b >> 3);
     if (t >= J.tg.ntiles) return;
-    tile_body<TP, TF, TA, HOME>(J, t, smem);
+    tile_body<TP, TF, TA, VAR>(J, t, smem);
 }
 
 // Persistent work-list kernel: workgroups take (job, tile) items from an
 // atomic counter until the list is drained; every workgroup exits once the
 // counter passes nitems.  The counter must be zero at launch.
-template <typename TP, typename TF, typename TA, bool HOME>
-__global__ void __launch_bounds__(512)
+template <typename TP, typename TF, typename TA, int VAR>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VariantWaves<VAR>::value)))
 k_worklist(const TileJob<TP, TF, TA> *__restrict__ jobs, const uint2 *__restrict__ items, int nitems,
            unsigned *__restrict__ counter) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -277,7 +309,7 @@ k_worklist(const TileJob<TP, TF, TA> *__restrict__ jobs, const uint2 *__restrict
         if (it >= nitems) break;
         const uint2 item = items[it];
         const TileJob<TP, TF, TA> J = jobs[item.x];
-        tile_body<TP, TF, TA, HOME>(J, (int)item.y, smem);
+        tile_body<TP, TF, TA, VAR>(J, (int)item.y, smem);
     }
 }
 
@@ -305,14 +337,21 @@ static void tiled_t(const spic_grid &g, const spic_params &prm, const spic_field
     const size_t lds = tiled_lds_bytes(tg, sizeof(TP) == 8 ? SPIC_F64 : SPIC_F32,
                                        sizeof(TA) == 8 ? SPIC_F64 : SPIC_F32);
     const auto job = make_tile_job<TP, TF, TA>(g, prm, f, w, tg, tile_off);
-    if (cfg.home_acc) {
-        allow_lds(k_fused_tiled<TP, TF, TA, true>, lds);
-        hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, true>), dim3(8 * chunk), dim3(cfg.tile_block), lds, s, job,
-                           chunk);
-    } else {
-        allow_lds(k_fused_tiled<TP, TF, TA, false>, lds);
-        hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, false>), dim3(8 * chunk), dim3(cfg.tile_block), lds, s, job,
-                           chunk);
+    switch (cfg.variant) {
+        case 1:
+            allow_lds(k_fused_tiled<TP, TF, TA, 1>, lds);
+            hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, 1>), dim3(8 * chunk), dim3(cfg.tile_block), lds, s, job,
+                               chunk);
+            break;
+        case 2:
+            allow_lds(k_fused_tiled<TP, TF, TA, 2>, lds);
+            hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, 2>), dim3(8 * chunk), dim3(cfg.tile_block), lds, s, job,
+                               chunk);
+            break;
+        default:
+            allow_lds(k_fused_tiled<TP, TF, TA, 0>, lds);
+            hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, 0>), dim3(8 * chunk), dim3(cfg.tile_block), lds, s, job,
+                               chunk);
     }
 }
 
@@ -373,9 +412,9 @@ void write_tile_job(int combo, void *dst, const spic_grid &g, const spic_params 
 // Workgroups of the persistent launch: resident workgroups per CU times
 // CUs, capped by the item count (and by max_groups when > 0).  Also allows
 // the LDS size; call before any stream capture.
-template <typename TP, typename TF, typename TA, bool HOME>
+template <typename TP, typename TF, typename TA, int VAR>
 static int worklist_groups_t(size_t lds, int block, int nitems, int max_groups) {
-    auto k = k_worklist<TP, TF, TA, HOME>;
+    auto k = k_worklist<TP, TF, TA, VAR>;
     allow_lds(k, lds);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, lds) != hipSuccess || per_cu < 1) per_cu = 1;
@@ -387,10 +426,11 @@ static int worklist_groups_t(size_t lds, int block, int nitems, int max_groups) 
     return groups < 1 ? 1 : groups;
 }
 
-int worklist_groups(int combo, bool home, size_t lds, int block, int nitems, int max_groups) {
-#define SPIC_WG(TP, TF, TA)                                                                     \
-    return home ? worklist_groups_t<TP, TF, TA, true>(lds, block, nitems, max_groups)          \
-                : worklist_groups_t<TP, TF, TA, false>(lds, block, nitems, max_groups)
+int worklist_groups(int combo, int variant, size_t lds, int block, int nitems, int max_groups) {
+#define SPIC_WG(TP, TF, TA)                                                                           \
+    return variant == 2 ? worklist_groups_t<TP, TF, TA, 2>(lds, block, nitems, max_groups)           \
+           : variant == 1 ? worklist_groups_t<TP, TF, TA, 1>(lds, block, nitems, max_groups)         \
+                          : worklist_groups_t<TP, TF, TA, 0>(lds, block, nitems, max_groups)
     switch (combo) {
         case 0: SPIC_WG(double, double, double);
         case 1: SPIC_WG(float, float, double);
@@ -401,20 +441,21 @@ int worklist_groups(int combo, bool home, size_t lds, int block, int nitems, int
 #undef SPIC_WG
 }
 
-template <typename TP, typename TF, typename TA, bool HOME>
+template <typename TP, typename TF, typename TA, int VAR>
 static hipError_t worklist_t(const void *jobs, const uint2 *items, int nitems, unsigned *counter, size_t lds,
                              int block, int groups, hipStream_t s) {
-    hipLaunchKernelGGL((k_worklist<TP, TF, TA, HOME>), dim3(groups), dim3(block), lds, s,
+    hipLaunchKernelGGL((k_worklist<TP, TF, TA, VAR>), dim3(groups), dim3(block), lds, s,
                        (const TileJob<TP, TF, TA> *)jobs, items, nitems, counter);
     return hipGetLastError();
 }
 
-hipError_t launch_worklist(int combo, bool home, const void *jobs, const uint2 *items, int nitems,
+hipError_t launch_worklist(int combo, int variant, const void *jobs, const uint2 *items, int nitems,
                            unsigned *counter, size_t lds, int block, int groups, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
 #define SPIC_WL(TP, TF, TA)                                                                                  \
-    return home ? worklist_t<TP, TF, TA, true>(jobs, items, nitems, counter, lds, block, groups, s)         \
-                : worklist_t<TP, TF, TA, false>(jobs, items, nitems, counter, lds, block, groups, s)
+    return variant == 2 ? worklist_t<TP, TF, TA, 2>(jobs, items, nitems, counter, lds, block, groups, s)    \
+           : variant == 1 ? worklist_t<TP, TF, TA, 1>(jobs, items, nitems, counter, lds, block, groups, s)  \
+                          : worklist_t<TP, TF, TA, 0>(jobs, items, nitems, counter, lds, block, groups, s)
     switch (combo) {
         case 0: SPIC_WL(double, double, double);
         case 1: SPIC_WL(float, float, double);

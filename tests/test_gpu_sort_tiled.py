@@ -104,11 +104,11 @@ def _gpu_steps(spic, ctx, h, f, sps, qoms, nsteps, dtype=torch.float64, sort_eve
     return [spic.to_host(d) for d in dev], [m.cpu().numpy() for m in moms]
 
 
-@pytest.mark.parametrize("home_acc", [0, 1])
-def test_tiled_fp64_every_step_matches_oracle(spic, ctx, home_acc):
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_tiled_fp64_every_step_matches_oracle(spic, ctx, variant):
     """32x16x4 cells, 4 species, 10 steps, sorted every 4 steps; with and
     without home-cell register accumulation of the deposit."""
-    ctx.set_option("home_acc", home_acc)
+    ctx.set_option("tile_variant", variant)
     h = W.harris_32x16x4()
     f = W.make_fields(h)
     sps = W.make_all_species(h)
@@ -124,9 +124,9 @@ def test_tiled_fp64_every_step_matches_oracle(spic, ctx, home_acc):
     _gpu_steps(spic, ctx, h, f, sps, h.qoms, 10, check=check)
 
 
-@pytest.mark.parametrize("home_acc", [0, 1])
-def test_tiled_fp32_one_step(spic, ctx, home_acc):
-    ctx.set_option("home_acc", home_acc)
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_tiled_fp32_one_step(spic, ctx, variant):
+    ctx.set_option("tile_variant", variant)
     h = W.harris_32x16x4()
     f32 = {k: v.astype(np.float32) for k, v in W.make_fields(h).items()}
     sps = [W.round_state(s, np.float32) for s in W.make_all_species(h)]
@@ -139,10 +139,10 @@ def test_tiled_fp32_one_step(spic, ctx, home_acc):
         P.assert_moments(ms[s], O.deposit(h.grid, W.upcast(st[s])), P.MOM32)
 
 
-@pytest.mark.parametrize("tile,halo,home_acc", [((4, 4, 4), 0, 0), ((4, 4, 4), 0, 1), ((2, 4, 8), 1, 0),
-                                                ((3, 3, 3), 1, 1), ((2, 2, 2), 2, 0), ((2, 8, 4), 1, 1),
-                                                ((4, 4, 2), 1, 0)])
-def test_tile_shapes_and_halo_overflow_match_oracle(spic, ctx, tile, halo, home_acc):
+@pytest.mark.parametrize("tile,halo,variant", [((4, 4, 4), 0, 0), ((4, 4, 4), 0, 2), ((2, 4, 8), 1, 1),
+                                               ((3, 3, 3), 1, 2), ((2, 2, 2), 2, 0), ((2, 8, 4), 1, 2),
+                                               ((4, 4, 2), 1, 1)])
+def test_tile_shapes_and_halo_overflow_match_oracle(spic, ctx, tile, halo, variant):
     """Fast particles leave small regions (halo 0) -> global fallbacks; tile
     shapes that do not divide the grid leave ragged edge tiles."""
     h = W.harris_32x16x4()
@@ -152,8 +152,8 @@ def test_tile_shapes_and_halo_overflow_match_oracle(spic, ctx, tile, halo, home_
     qoms = [-64.0, 1.0]
     ctx.set_option("tile_x", tile[0]); ctx.set_option("tile_y", tile[1]); ctx.set_option("tile_z", tile[2])
     ctx.set_option("halo", halo)
-    ctx.set_option("home_acc", home_acc)
-    _say("case tiles %s halo %d home_acc %d" % (tile, halo, home_acc))
+    ctx.set_option("tile_variant", variant)
+    _say("case tiles %s halo %d variant %d" % (tile, halo, variant))
     st, ms = _gpu_steps(spic, ctx, h, f, sps, qoms, 3, sort_every=2)
     ora, oms = _oracle_steps(h, f, sps, qoms, 3)
     for s in range(2):
