@@ -54,7 +54,8 @@ def algorithmic_bytes(n_particles: int, nodes: int, s_p: int, s_f: int) -> float
     return n_particles * 13 * s_p + 6 * nodes * s_f + 10 * nodes * 8
 
 
-def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: int, tune: bool = True):
+def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: int, tune: bool = True,
+            variant: int = -1):
     import torch
     from paper_2008_04397_amd import autotune, spic
 
@@ -87,6 +88,8 @@ def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: 
         log("[bench] tuned %s: %s" % (key, tuned))
     if sort_every < 0:
         sort_every = 4
+    if variant >= 0:
+        ctx.set_option("tile_variant", variant)
 
     def step(k, ev=None):
         prm = spic.make_params(h.dt, h.c, h.niter, sort_every, k)
@@ -304,6 +307,7 @@ def main():
     ap.add_argument("--fraction", type=float, default=1.0)
     ap.add_argument("--requests", type=int, default=120)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--variant", type=int, default=-1, help="tiled kernel variant (-1: autotuned)")
     ap.add_argument("--path", type=int, default=0)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -324,12 +328,14 @@ def main():
         return
 
     h = W.harris_128x64x32()
-    r32 = run_gpu(h, "f32", args.steps, args.warmup, args.sort_every, args.path, tune=not args.no_tune)
+    r32 = run_gpu(h, "f32", args.steps, args.warmup, args.sort_every, args.path, tune=not args.no_tune,
+                  variant=args.variant)
     log("[bench] f32: %.3e particle-steps/s, %.3f ms/step, %.1f%% HBM" %
         (r32["value"], r32["ms_per_step"], 100 * r32["roofline"]["frac"]))
     r64 = None
     if not args.no_fp64:
-        r64 = run_gpu(h, "f64", args.steps, args.warmup, args.sort_every, args.path, tune=not args.no_tune)
+        r64 = run_gpu(h, "f64", args.steps, args.warmup, args.sort_every, args.path, tune=not args.no_tune,
+                      variant=args.variant)
         log("[bench] f64: %.3e particle-steps/s, %.3f ms/step, %.1f%% HBM" %
             (r64["value"], r64["ms_per_step"], 100 * r64["roofline"]["frac"]))
     cpu = None

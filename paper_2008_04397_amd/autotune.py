@@ -57,7 +57,7 @@ def apply(ctx, cfg: Dict[str, int]):
 
 def candidates(quick: bool = True) -> Iterable[Dict[str, int]]:
     blocks = (256, 512)
-    variants = (0, 1, 2)
+    variants = (0, 1, 2, 3)
     cadences = (2, 4, 8) if quick else (1, 2, 4, 8, 16)
     halos = (1,) if quick else (1, 2)
     for blk, var, se, halo in itertools.product(blocks, variants, cadences, halos):

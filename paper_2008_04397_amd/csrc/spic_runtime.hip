@@ -188,7 +188,8 @@ static const char *const kOptionNames[] = {
     "tile_x", "tile_y", "tile_z",  // sort tile shape in cells (product <= 64)
     "halo",         // cells of halo staged around a tile
     "lds_max",      // read only: LDS bytes per workgroup on the device
-    "tile_variant", // tiled kernel: 0 LDS atomics, 1 + field corners in registers, 2 home-cell registers
+    "tile_variant", // tiled kernel: 0 LDS atomics, 1 + field corners in registers, 2 home-cell registers,
+                    // 3 LDS atomics with lane-rotated corners
     "graph",        // batch engine: 1 = replay unchanged ticks as a hipGraph
     "batch_particles",  // batch engine: particles per streamed batch (upper bound)
     "max_groups",   // batch engine: cap on workgroups of the persistent launch (0 = occupancy)
@@ -277,8 +278,8 @@ int spic_set_option(spic_ctx ctx, const char *key, int64_t value) {
             if ((!strcmp(key, "tile_x") || !strcmp(key, "tile_y") || !strcmp(key, "tile_z")) &&
                 (value < 1 || value > 64))
                 return ctx->fail(SPIC_E_ARG, "tile sizes must be in [1, 64]");
-            if (!strcmp(key, "tile_variant") && (value < 0 || value > 2))
-                return ctx->fail(SPIC_E_ARG, "tile_variant must be 0, 1 or 2");
+            if (!strcmp(key, "tile_variant") && (value < 0 || value > 3))
+                return ctx->fail(SPIC_E_ARG, "tile_variant must be 0, 1, 2 or 3");
             if (!strcmp(key, "halo") && (value < 0 || value > 8))
                 return ctx->fail(SPIC_E_ARG, "halo must be in [0, 8]");
             if (!strcmp(key, "lds_max")) return ctx->fail(SPIC_E_ARG, "lds_max is read only");

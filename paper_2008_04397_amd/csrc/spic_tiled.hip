@@ -50,10 +50,15 @@ struct LdsFieldNode {
 // cell is in c (base and wrap offsets), otherwise only c.f* are set.
 template <typename T>
 __device__ __forceinline__ bool region_locate(const GridT<T> &g, const TileGeom &tg, int ox, int oy, int oz, T x,
-                                              T y, T z, int &slot, Cell<T> &c) {
+                                              T y, T z, int &slot, Cell<T> &c, int *ijk = nullptr) {
     const int i = plocate(x, g.L[0], g.invL[0], g.invd[0], g.nx, c.fx);
     const int j = plocate(y, g.L[1], g.invL[1], g.invd[1], g.ny, c.fy);
     const int k = plocate(z, g.L[2], g.invL[2], g.invd[2], g.nz, c.fz);
+    if (ijk) {
+        ijk[0] = i;
+        ijk[1] = j;
+        ijk[2] = k;
+    }
     int di = i - ox, dj = j - oy, dk = k - oz;
     di += (di < 0) ? g.nx : 0;
     dj += (dj < 0) ? g.ny : 0;
@@ -121,6 +126,7 @@ template <typename TP, typename TF, typename TA, int VAR>
 __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, unsigned char *smem) {
     constexpr bool HOME = VAR == 2;   // home-cell register accumulation
     constexpr bool CACHE = VAR == 1;  // field corners of the last cell in registers
+    constexpr bool ROTATE = VAR == 3; // lane-rotated corner order of the LDS deposit
     const GridT<TP> &g = J.g;
     const TileGeom &tg = J.tg;
     const FieldPtrs<TF> &f = J.f;
@@ -170,6 +176,11 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
     for (; i < end; i += stride) {
         TP xn = nx_, yn = ny_, zn = nz_, un = nu_, vn = nv_, wn = nw_;
         const TP qp = nq_;
+        // the cell located by the first gather of this particle; later
+        // gathers inside it reuse it (same result as locating again)
+        int c_ijk[3] = {-1, 0, 0}, c_rb = 0;
+        bool c_in = false;
+        Cell<TP> c_cell;
         const uint32_t inext = i + stride;
         if (inext < end) {  // prefetch the next particle while this one is moved
             nx_ = p.x[inext]; ny_ = p.y[inext]; nz_ = p.z[inext];
@@ -180,7 +191,29 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
             [&](TP px, TP py, TP pz, TP F[6]) {
                 int rb;
                 Cell<TP> c;
-                if (region_locate(g, tg, ox, oy, oz, px, py, pz, rb, c)) {
+                bool in;
+                const TP tx = px * g.invd[0] - (TP)c_ijk[0];
+                const TP ty = py * g.invd[1] - (TP)c_ijk[1];
+                const TP tz = pz * g.invd[2] - (TP)c_ijk[2];
+                if (c_ijk[0] >= 0 && px >= TP(0) && px < g.L[0] && py >= TP(0) && py < g.L[1] && pz >= TP(0) &&
+                    pz < g.L[2] && tx >= TP(0) && tx < TP(1) && ty >= TP(0) && ty < TP(1) && tz >= TP(0) &&
+                    tz < TP(1)) {
+                    c = c_cell;
+                    c.fx = tx;
+                    c.fy = ty;
+                    c.fz = tz;
+                    rb = c_rb;
+                    in = c_in;
+                } else {
+                    in = region_locate(g, tg, ox, oy, oz, px, py, pz, rb, c, c_ijk);
+                    if (in) {  // the global cell is needed only outside the region
+                        c.base = 0; c.ox = 0; c.oy = 0; c.oz = 0;
+                    }
+                    c_cell = c;
+                    c_rb = rb;
+                    c_in = in;
+                }
+                if (in) {
                     if (!CACHE) {
                         gather_lds(fl, tg, rb, c, F);
                     } else {
@@ -227,6 +260,21 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
                 const TA qw = qa * wt8[k];
 #pragma unroll
                 for (int m = 0; m < 10; ++m) acc[(k * 10 + m) % (HOME ? 80 : 1)] += qw * val[m];
+            }
+        } else if (in && ROTATE) {
+            // instruction k of lane l deposits corner k ^ (l & 7): lanes that
+            // share a cell (particles that drifted into a neighbour's cell)
+            // then hit different nodes in the same instruction
+            const int s = threadIdx.x & 7;
+            const TA gx = TA(1) - c.fx, gy = TA(1) - c.fy, gz = TA(1) - c.fz;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int cc = k ^ s;
+                const TA wx = (cc & 1) ? c.fx : gx, wy = (cc & 2) ? c.fy : gy, wz = (cc & 4) ? c.fz : gz;
+                const TA qw = qa * (wx * wy * wz);
+                TA *dst = ml + rb + ((cc & 1) ? sx : 0) + ((cc & 2) ? sy : 0) + ((cc & 4) ? 1 : 0);
+#pragma unroll
+                for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, qw * val[m]);
             }
         } else if (in) {
 #pragma unroll
@@ -277,9 +325,10 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
 //      so gathers in a thread's cell skip LDS; <= 168 VGPRs, 3 waves/SIMD
 //   2  home-cell register accumulation of the deposit (80 sums) with LDS
 //      atomics for drifted particles; <= 256 VGPRs, 2 waves/SIMD
+//   3  as 0, with a lane-rotated corner order in the LDS deposit
 template <int VAR>
 struct VariantWaves {
-    static constexpr int value = VAR == 0 ? 4 : (VAR == 1 ? 3 : 2);
+    static constexpr int value = (VAR == 0 || VAR == 3) ? 4 : (VAR == 1 ? 3 : 2);
 };
 
 template <typename TP, typename TF, typename TA, int VAR>
@@ -346,6 +395,11 @@ static void tiled_t(const spic_grid &g, const spic_params &prm, const spic_field
         case 2:
             allow_lds(k_fused_tiled<TP, TF, TA, 2>, lds);
             hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, 2>), dim3(8 * chunk), dim3(cfg.tile_block), lds, s, job,
+                               chunk);
+            break;
+        case 3:
+            allow_lds(k_fused_tiled<TP, TF, TA, 3>, lds);
+            hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, 3>), dim3(8 * chunk), dim3(cfg.tile_block), lds, s, job,
                                chunk);
             break;
         default:
@@ -428,7 +482,8 @@ static int worklist_groups_t(size_t lds, int block, int nitems, int max_groups) 
 
 int worklist_groups(int combo, int variant, size_t lds, int block, int nitems, int max_groups) {
 #define SPIC_WG(TP, TF, TA)                                                                           \
-    return variant == 2 ? worklist_groups_t<TP, TF, TA, 2>(lds, block, nitems, max_groups)           \
+    return variant == 3 ? worklist_groups_t<TP, TF, TA, 3>(lds, block, nitems, max_groups)           \
+           : variant == 2 ? worklist_groups_t<TP, TF, TA, 2>(lds, block, nitems, max_groups)         \
            : variant == 1 ? worklist_groups_t<TP, TF, TA, 1>(lds, block, nitems, max_groups)         \
                           : worklist_groups_t<TP, TF, TA, 0>(lds, block, nitems, max_groups)
     switch (combo) {
@@ -453,7 +508,8 @@ hipError_t launch_worklist(int combo, int variant, const void *jobs, const uint2
                            unsigned *counter, size_t lds, int block, int groups, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
 #define SPIC_WL(TP, TF, TA)                                                                                  \
-    return variant == 2 ? worklist_t<TP, TF, TA, 2>(jobs, items, nitems, counter, lds, block, groups, s)    \
+    return variant == 3 ? worklist_t<TP, TF, TA, 3>(jobs, items, nitems, counter, lds, block, groups, s)    \
+           : variant == 2 ? worklist_t<TP, TF, TA, 2>(jobs, items, nitems, counter, lds, block, groups, s)  \
            : variant == 1 ? worklist_t<TP, TF, TA, 1>(jobs, items, nitems, counter, lds, block, groups, s)  \
                           : worklist_t<TP, TF, TA, 0>(jobs, items, nitems, counter, lds, block, groups, s)
     switch (combo) {

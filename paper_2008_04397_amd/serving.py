@@ -57,8 +57,10 @@ def make_request_run(req: W.Request, dtype=None, sort_every: int = 4, device="cu
 
 
 def serve(ctx: "spic.Context", requests: Sequence[W.Request], mode: str = "continuous",
-          dtype=None, sort_every: int = 4, time_scale: float = 1.0, log=None) -> List[Done]:
-    """Replay the arrival trace (arrival times multiplied by time_scale)."""
+          dtype=None, sort_every: int = 4, time_scale: float = 1.0, log=None, keep=None) -> List[Done]:
+    """Replay the arrival trace (arrival times multiplied by time_scale).
+    When `keep` is a dict, keep[rid] receives each request's finished run
+    (its species and moments hold the results)."""
     import torch
     assert mode in ("continuous", "serial")
     order = sorted(requests, key=lambda r: r.arrival)
@@ -89,6 +91,8 @@ def serve(ctx: "spic.Context", requests: Sequence[W.Request], mode: str = "conti
                 poll_all(block=True)
         tk = spic.spic_batch_submit(ctx, [run])[0]
         inflight[tk] = (req, arrival, now())
+        if keep is not None:
+            keep[req.rid] = run
         if log and k % 20 == 0:
             log("[serve %s] request %d/%d submitted at %.2f s, %d in flight" % (mode, k, len(order), now(),
                                                                               len(inflight)))

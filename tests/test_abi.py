@@ -164,7 +164,7 @@ def test_autotune_cache_roundtrip(tmp_path, monkeypatch):
     assert autotune.load(key) is None
     autotune.store(key, dict(autotune.DEFAULT))
     assert autotune.load(key) == autotune.DEFAULT
-    assert len(list(autotune.candidates(quick=True))) == 18
+    assert len(list(autotune.candidates(quick=True))) == 24
 
 
 def test_serving_summary_statistics():

@@ -1,0 +1,60 @@
+"""Serving: a Poisson stream of small Harris-box runs through the batch
+engine with continuous batching; every request's result must equal the
+same request run alone (particles bitwise by position in the sorted order
+of ids is not available here -- the inputs carry no ids -- so particles are
+compared as sorted multisets per component, moments within 1e-12)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2008_04397_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _stream():
+    return W.serving_stream(8, rate=40.0, seed=9, max_nx=32, steps_range=(3, 9))
+
+
+def test_each_request_alone_equals_continuous_mix():
+    from paper_2008_04397_amd import serving, spic
+    reqs = _stream()
+    ctx = spic.Context(0, hbm_budget_bytes=256 << 20)
+    mixed = {}
+    _say("case serving continuous 8 requests")
+    done = serving.serve(ctx, reqs, mode="continuous", keep=mixed)
+    assert len(done) == len(reqs)
+    s = serving.summarize(done)
+    assert s["p99_s"] >= s["p50_s"] > 0
+    for req in reqs:
+        alone = serving.make_request_run(req)
+        spic.spic_wait(ctx, spic.spic_batch_submit(ctx, [alone])[0])
+        mix = mixed[req.rid]
+        for sa, sb in zip(alone.species, mix.species):
+            for k in ("x", "y", "z", "u", "v", "w"):
+                a = np.sort(sa[k].numpy())
+                b = np.sort(sb[k].numpy())
+                assert np.array_equal(a, b), (req.rid, k)
+        for ma, mb in zip(alone.moments, mix.moments):
+            a, b = ma.cpu().numpy(), mb.cpu().numpy()
+            for c in range(10):
+                nb = np.linalg.norm(a[c])
+                assert np.linalg.norm(a[c] - b[c]) <= 1e-12 * max(nb, 1e-300)
+    ctx.close()
+
+
+def test_serial_baseline_runs_one_at_a_time():
+    from paper_2008_04397_amd import serving, spic
+    reqs = _stream()[:4]
+    ctx = spic.Context(0)
+    done = serving.serve(ctx, reqs, mode="serial")
+    ctx.close()
+    done.sort(key=lambda d: d.submit)
+    for a, b in zip(done, done[1:]):
+        assert b.submit >= a.complete - 1e-3

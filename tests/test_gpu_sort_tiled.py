@@ -104,7 +104,7 @@ def _gpu_steps(spic, ctx, h, f, sps, qoms, nsteps, dtype=torch.float64, sort_eve
     return [spic.to_host(d) for d in dev], [m.cpu().numpy() for m in moms]
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_tiled_fp64_every_step_matches_oracle(spic, ctx, variant):
     """32x16x4 cells, 4 species, 10 steps, sorted every 4 steps; with and
     without home-cell register accumulation of the deposit."""
@@ -124,7 +124,7 @@ def test_tiled_fp64_every_step_matches_oracle(spic, ctx, variant):
     _gpu_steps(spic, ctx, h, f, sps, h.qoms, 10, check=check)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_tiled_fp32_one_step(spic, ctx, variant):
     ctx.set_option("tile_variant", variant)
     h = W.harris_32x16x4()
@@ -140,8 +140,8 @@ def test_tiled_fp32_one_step(spic, ctx, variant):
 
 
 @pytest.mark.parametrize("tile,halo,variant", [((4, 4, 4), 0, 0), ((4, 4, 4), 0, 2), ((2, 4, 8), 1, 1),
-                                               ((3, 3, 3), 1, 2), ((2, 2, 2), 2, 0), ((2, 8, 4), 1, 2),
-                                               ((4, 4, 2), 1, 1)])
+                                               ((3, 3, 3), 1, 2), ((2, 2, 2), 2, 3), ((2, 8, 4), 1, 2),
+                                               ((4, 4, 2), 1, 1), ((4, 4, 4), 1, 3)])
 def test_tile_shapes_and_halo_overflow_match_oracle(spic, ctx, tile, halo, variant):
     """Fast particles leave small regions (halo 0) -> global fallbacks; tile
     shapes that do not divide the grid leave ragged edge tiles."""
