@@ -164,8 +164,24 @@ const char *spic_status_str(int status);
 /* SPIC_ABI_VERSION of the library. */
 int spic_version(void);
 
-/* Tuning knobs (block size, kernel path, sort tile shape), keyed by name;
- * see the implementation for the list.  Unknown keys return SPIC_E_ARG. */
+/* Tuning knobs, keyed by name; none changes results beyond rounding order.
+ * Out-of-range values and unknown keys return SPIC_E_ARG.
+ *   block          threads per block of the unsorted-path kernels (64..1024, x64)
+ *   grid_cap       cap on blocks of grid-stride kernels
+ *   path           0 = tiled kernel for sorted species, 1 = unsorted path only
+ *   tile_block     threads per block of the tiled kernel (64..512, x64)
+ *   tile_x/y/z     sort tile shape in cells (product <= 64)
+ *   halo           cells of halo staged around a tile in LDS (0..8)
+ *   lds_max        read only: LDS bytes a workgroup may use on the device
+ *   tile_variant   tiled-kernel variant (0..3; see spic_tiled.hip)
+ *   fixed_geo      1 = kernels compiled for 4x4x4 tiles with halo 1 are used
+ *                  when that tiling is in effect
+ *   graph          batch engine: replay unchanged ticks as a hipGraph (0/1)
+ *   batch_particles  batch engine: particles per streamed batch
+ *   max_groups     batch engine: cap on workgroups of the persistent launch
+ *   tick_items     batch engine: a tick steps the runs with the least
+ *                  remaining work until it holds this many (run, species,
+ *                  tile) items (default 4096; 0 = every active run) */
 int spic_set_option(spic_ctx ctx, const char *key, int64_t value);
 int spic_get_option(spic_ctx ctx, const char *key, int64_t *value);
 
@@ -201,14 +217,18 @@ int spic_sort(spic_ctx ctx, const spic_grid *grid, spic_species *sp, int32_t nsp
 
 /* ---------------------------------------------------------------- batches */
 
-/* Submit nruns independent multi-step runs (Sec. III-B, particle batching):
- * runs whose species are device resident are executed together, step by
- * step, in one launch per step over all their (run, species, tile) work
- * items; runs with host_resident species are streamed through HBM in
+/* Submit nruns independent multi-step runs (Sec. III-B, particle batching).
+ * Queued runs are admitted, in submission order, as soon as their HBM
+ * footprint fits the ctx's budget (host_resident species are uploaded on
+ * admission and copied back on completion).  Each tick advances admitted
+ * runs by one step -- those with the least remaining work first, until the
+ * tick holds `tick_items` (run, species, tile) items -- in one launch per
+ * precision combination.  A host_resident run larger than the budget, or
+ * with a species of 4 GiB or more per array, is streamed through HBM in
  * batches on two streams (copy of the next batch overlapping the kernel on
- * the current one) within the ctx's budget.  Work runs on the ctx's own
- * streams; tickets_out[i] identifies run i.  The caller's arrays must stay
- * valid until the ticket completes.
+ * the current one).  Device-resident species need n * element size < 4 GiB.
+ * Work runs on the ctx's own streams; tickets_out[i] identifies run i.  The
+ * caller's arrays must stay valid until the ticket completes.
  * Errors: SPIC_E_ARG, SPIC_E_BUDGET (a run cannot fit even when streamed),
  * SPIC_E_UNSUPPORTED, SPIC_E_HIP. */
 int spic_batch_submit(spic_ctx ctx, const spic_run *runs, int32_t nruns, uint64_t *tickets_out);

@@ -108,6 +108,18 @@ struct RunState {
     int status = SPIC_OK;
     std::string err;
     double secs = 0;
+
+    // particle-steps still to do, and (job, tile) items of one tick
+    double remaining_work() const {
+        double n = 0;
+        for (auto &sl : sp) n += (double)sl.user.n;
+        return n * (double)(nsteps - done_steps);
+    }
+    int64_t tick_items() const {
+        int64_t k = 0;
+        for (auto &sl : sp) k += sl.user.n > 0 ? tg.ntiles : 0;
+        return k;
+    }
 };
 
 struct BatchEngine {
@@ -137,7 +149,8 @@ struct BatchEngine {
     std::vector<uint64_t> graph_key;
 
     // tuning, read from the ctx options when the engine starts
-    int tile_block = 256, variant = 0, use_graph = 1, max_groups = 0;
+    int tile_block = 256, variant = 0, use_graph = 1, max_groups = 0, fixed_geo = 1;
+    int64_t tick_items = 4096;  // 0: every active run steps at every tick
     int64_t batch_particles = (int64_t)1 << 26;
     LaunchCfg lcfg;
 
@@ -199,10 +212,16 @@ struct BatchEngine {
                 const int acc = R.moments ? R.moments[s].acc_dtype : SPIC_F64;
                 sl.combo = job_combo(sl.user.dtype, R.fields.dtype, acc);
                 if (sl.combo < 0) return ctx->fail(SPIC_E_UNSUPPORTED, "run %d species %d: dtype combination", r, s);
-                if (sl.user.n >= ((int64_t)1 << 31) && !sl.user.host_resident)
-                    return ctx->fail(SPIC_E_UNSUPPORTED, "run %d species %d: resident runs need n < 2^31", r, s);
+                if (tiled_lds_bytes(st->tg, sl.user.dtype, acc, 0, tile_block) > ctx->lds_max)
+                    return ctx->fail(SPIC_E_UNSUPPORTED,
+                                     "run %d species %d: the tile region (tile_x/y/z, halo) does not fit in LDS", r, s);
+                const bool big = !tiled_fits(sl.user.n, sl.user.dtype);
+                if (big && !sl.user.host_resident)
+                    return ctx->fail(SPIC_E_UNSUPPORTED,
+                                     "run %d species %d: device-resident species need n * element size < 4 GiB", r, s);
                 if (sl.user.host_resident) {
                     st->host = true;
+                    st->streamed = st->streamed || big;  // streamed in batches that fit
                     fp += species_bytes(sl.user.n, sl.user.dtype, sl.user.id != nullptr);
                 }
                 fp += (size_t)(st->tg.ntiles + 1) * 4 + 256;
@@ -210,7 +229,7 @@ struct BatchEngine {
             }
             if (R.moments) st->mom.assign(R.moments, R.moments + R.nspecies);
             st->footprint = fp;
-            if (ctx->budget && st->host && fp > ctx->budget) {
+            if ((ctx->budget && st->host && fp > ctx->budget) || st->streamed) {
                 st->streamed = true;
                 // a streamed run needs two batch slots, the batch sort scratch and its tile ranges
                 int64_t nb = batch_particles;
@@ -406,7 +425,8 @@ struct BatchEngine {
                     continue;
                 }
                 ensure_sort_scratch(sort_scratch_bytes(sl.dev.n, sl.dev.dtype, sl.dev.id != nullptr, r.tg));
-                hipError_t e = launch_sort(r.grid, work_of(sl.dev, nullptr), r.tg, sort_scr, sl.tile_off, cs);
+                hipError_t e = launch_sort(r.grid, work_of(sl.dev, nullptr), r.tg, sort_scr, sl.tile_off,
+                                           r.done_steps > 0, cs);
                 if (e != hipSuccess) fail_run(r, e, "sort");
             }
             sorted_now = true;
@@ -424,7 +444,8 @@ struct BatchEngine {
         struct Combo {
             std::vector<unsigned char> jobs;
             std::vector<uint2> items;
-            size_t lds = 0;
+            size_t lds = 0, lds0 = 0;  // LDS with the configured variant, with variant 0
+            int var = 0;
         };
         std::map<int, Combo> combos;
         std::vector<void *> mptr[2];
@@ -441,7 +462,8 @@ struct BatchEngine {
                     mcnt[which].push_back(10 * nn);
                 }
                 if (sl.dev.n == 0) continue;
-                Combo &c = combos[sl.combo];
+                // launch key: precision combination, +8 for the compile-time default tiling
+                Combo &c = combos[sl.combo + (fixed_geo && geo_is_default(r.tg) ? 8 : 0)];
                 const size_t jb = tile_job_bytes(sl.combo);
                 const uint32_t jidx = (uint32_t)(c.jobs.size() / jb);
                 c.jobs.resize(c.jobs.size() + jb);
@@ -449,15 +471,17 @@ struct BatchEngine {
                 write_tile_job(sl.combo, c.jobs.data() + jidx * jb, r.grid, prm, r.fields, work_of(sl.dev, m), r.tg,
                                sl.tile_off);
                 for (int t = 0; t < r.tg.ntiles; ++t) c.items.push_back(make_uint2(jidx, (uint32_t)t));
-                c.lds = std::max(c.lds, tiled_lds_bytes(r.tg, sl.dev.dtype, m ? m->acc_dtype : SPIC_F64));
+                const int acc = m ? m->acc_dtype : SPIC_F64;
+                c.lds = std::max(c.lds, tiled_lds_bytes(r.tg, sl.dev.dtype, acc, variant, tile_block));
+                c.lds0 = std::max(c.lds0, tiled_lds_bytes(r.tg, sl.dev.dtype, acc, 0, tile_block));
             }
         }
-        // layout of the device table: [ptrs f64][cnt f64][ptrs f32][cnt f32][counters x8] then per combo jobs, items
+        // layout of the device table: [ptrs f64][cnt f64][ptrs f32][cnt f32][counters x16] then per launch key jobs, items
         size_t off = 0;
         auto reserve = [&](size_t b) { size_t o = off; off += (b + 255) & ~(size_t)255; return o; };
         const size_t o_p0 = reserve(mptr[0].size() * 8), o_c0 = reserve(mcnt[0].size() * 8);
         const size_t o_p1 = reserve(mptr[1].size() * 8), o_c1 = reserve(mcnt[1].size() * 8);
-        const size_t o_ctr = reserve(8 * 4);
+        const size_t o_ctr = reserve(16 * 4);
         std::map<int, std::pair<size_t, size_t>> co;
         for (auto &kv : combos) {
             const size_t oj = reserve(kv.second.jobs.size());
@@ -493,8 +517,14 @@ struct BatchEngine {
         // 3. the step itself (captured as a graph when enabled); launch sizes
         // are settled before the capture starts
         std::map<int, int> groups;
-        for (auto &kv : combos) groups[kv.first] = worklist_groups(kv.first, variant, kv.second.lds, tile_block,
-                                                                 (int)kv.second.items.size(), max_groups);
+        for (auto &kv : combos) {
+            // a variant whose extra LDS does not fit falls back to variant 0
+            Combo &c = kv.second;
+            c.var = c.lds <= ctx->lds_max ? variant : 0;
+            if (c.var != variant) c.lds = c.lds0;
+            groups[kv.first] = worklist_groups(kv.first & 7, kv.first >= 8, c.var, c.lds, tile_block,
+                                               (int)c.items.size(), max_groups);
+        }
         bool capturing = false;
         if (use_graph && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) capturing = true;
         hipError_t e = hipSuccess;
@@ -502,13 +532,13 @@ struct BatchEngine {
             e = launch_fill_many((void *const *)(d + o_p0), (const int64_t *)(d + o_c0), (int)mptr[0].size(), 8, cs);
         if (e == hipSuccess && !mptr[1].empty())
             e = launch_fill_many((void *const *)(d + o_p1), (const int64_t *)(d + o_c1), (int)mptr[1].size(), 4, cs);
-        if (e == hipSuccess) e = launch_zero32(d + o_ctr, 8, cs);
+        if (e == hipSuccess) e = launch_zero32(d + o_ctr, 16, cs);
         int ci = 0;
         for (auto &kv : combos) {
             if (e != hipSuccess) break;
-            e = launch_worklist(kv.first, variant, d + co[kv.first].first,
+            e = launch_worklist(kv.first & 7, kv.first >= 8, kv.second.var, d + co[kv.first].first,
                                 (const uint2 *)(d + co[kv.first].second), (int)kv.second.items.size(),
-                                (unsigned *)(d + o_ctr) + (ci++ % 8), kv.second.lds, tile_block, groups[kv.first], cs);
+                                (unsigned *)(d + o_ctr) + ci++, kv.second.lds, tile_block, groups[kv.first], cs);
         }
         if (capturing) {
             hipGraph_t g = nullptr;
@@ -582,6 +612,30 @@ struct BatchEngine {
     // Streamed run: batches of at most nb particles through two slots.
     void stream_run(RunState &r);
 
+    // The runs the next tick steps: shortest remaining work first, until the
+    // tick holds tick_items (job, tile) items -- enough to fill the GPU -- so
+    // that short requests finish first instead of being slowed down by every
+    // long run they share the GPU with.  Returned in ticket order, so an
+    // unchanged set replays its graph.
+    std::vector<std::shared_ptr<RunState>> pick(const std::vector<std::shared_ptr<RunState>> &all) const {
+        if (tick_items <= 0 || all.size() <= 1) return all;
+        std::vector<std::shared_ptr<RunState>> v(all), out;
+        std::stable_sort(v.begin(), v.end(), [](const std::shared_ptr<RunState> &a,
+                                                const std::shared_ptr<RunState> &b) {
+            return a->remaining_work() < b->remaining_work();
+        });
+        int64_t items = 0;
+        for (auto &r : v) {
+            if (!out.empty() && items >= tick_items) break;
+            out.push_back(r);
+            items += r->tick_items();
+        }
+        std::sort(out.begin(), out.end(), [](const std::shared_ptr<RunState> &a, const std::shared_ptr<RunState> &b) {
+            return a->ticket < b->ticket;
+        });
+        return out;
+    }
+
     void loop() {
         (void)hipSetDevice(device);
         for (;;) {
@@ -633,7 +687,7 @@ struct BatchEngine {
                     }
                     it = queued.erase(it);
                 }
-                act = active;
+                act = pick(active);
             }
             if (streamed) {
                 stream_run(*streamed);
@@ -723,9 +777,12 @@ void BatchEngine::stream_run(RunState &r) {
                     (void)hipStreamWaitEvent(cs, loaded[k], 0);
                     uint32_t *toff = (uint32_t *)tiles + bidx * (r.tg.ntiles + 1);
                     SpeciesWork w = work_of(dv, m);
-                    if (sort_due && (e = launch_sort(r.grid, w, r.tg, sort_scr, toff, cs)) != hipSuccess)
+                    if (sort_due && (e = launch_sort(r.grid, w, r.tg, sort_scr, toff, step > 0, cs)) != hipSuccess)
                         fail_run(r, e, "batch sort");
-                    if ((e = launch_fused_tiled(r.grid, prm, r.fields, w, r.tg, toff, lcfg, cs)) != hipSuccess)
+                    LaunchCfg bcfg = lcfg;  // variant 0 when the configured one's LDS does not fit
+                    if (tiled_lds_bytes(r.tg, w.dtype, w.acc_dtype, bcfg.variant, bcfg.tile_block) > ctx->lds_max)
+                        bcfg.variant = 0;
+                    if ((e = launch_fused_tiled(r.grid, prm, r.fields, w, r.tg, toff, bcfg, cs)) != hipSuccess)
                         fail_run(r, e, "batch kernel");
                     (void)hipEventRecord(computed[k], cs);
                     // download slot -> batch
@@ -773,9 +830,11 @@ int spic_ctx_s::batch_submit(const spic_run *runs, int32_t nruns, uint64_t *tick
         batch.reset(new BatchEngine(this));
         batch->tile_block = (int)opt("tile_block", 256);
         batch->variant = (int)opt("tile_variant", 0);
+        batch->fixed_geo = (int)opt("fixed_geo", 1);
         batch->use_graph = (int)opt("graph", 1);
         batch->batch_particles = opt("batch_particles", (int64_t)1 << 26);
         batch->max_groups = (int)opt("max_groups", 0);
+        batch->tick_items = opt("tick_items", 4096);
         batch->lcfg = launch_cfg();
         int rc = batch->start();
         if (rc) {

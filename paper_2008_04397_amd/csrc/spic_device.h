@@ -41,9 +41,18 @@ __device__ __forceinline__ double recip_ge1(double d) {
 
 // Left node index along one axis and the offset xi in [0,1] inside the cell;
 // the two non-zero linear weights (Eq. 3) are 1 - xi and xi.
+// s * invd, rounded on its own: never fused with a neighbouring add, so
+// every kernel that locates a point (and the tiled kernel's same-cell
+// shortcut) obtains the same in-cell offset bit for bit.
+template <typename T>
+__device__ __forceinline__ T cell_coord(T s, T invd) {
+#pragma clang fp contract(off)
+    return s * invd;
+}
+
 template <typename T>
 __device__ __forceinline__ int plocate(T s, T L, T invL, T invd, int n, T &xi) {
-    T t = pwrap(s, L, invL) * invd;
+    T t = cell_coord(pwrap(s, L, invL), invd);
     int i = (int)t;                 // t >= 0
     i = (i > n - 1) ? n - 1 : i;
     xi = t - (T)i;

@@ -53,16 +53,23 @@ int spic_ctx_s::mover(const spic_grid &g, const spic_params &p, const spic_field
             if (rc) return rc;
         }
         const Layout *lay = nullptr;
+        LaunchCfg tcfg = cfg;
         if (!generic_only) {
             auto it = layouts.find(layout_key(g, sp[i]));
-            if (it != layouts.end() && tiled_lds_bytes(it->second.tg, w.dtype, w.acc_dtype) <= lds_max)
-                lay = &it->second;
+            if (it != layouts.end() && tiled_fits(w.n, w.dtype)) {
+                // a variant whose extra LDS does not fit falls back to variant 0,
+                // a region that does not fit at all to the unsorted path
+                if (tiled_lds_bytes(it->second.tg, w.dtype, w.acc_dtype, tcfg.variant, tcfg.tile_block) > lds_max)
+                    tcfg.variant = 0;
+                if (tiled_lds_bytes(it->second.tg, w.dtype, w.acc_dtype, tcfg.variant, tcfg.tile_block) <= lds_max)
+                    lay = &it->second;
+            }
         }
         int rc;
         if (lay) {
             void *toff = nullptr;
             if ((rc = reserve(lay->slot.c_str(), (size_t)(lay->tg.ntiles + 1) * 4, &toff))) return rc;
-            rc = hip(launch_fused_tiled(g, p, f, w, lay->tg, (const uint32_t *)toff, cfg, s), "fused mover (tiled)");
+            rc = hip(launch_fused_tiled(g, p, f, w, lay->tg, (const uint32_t *)toff, tcfg, s), "fused mover (tiled)");
         } else {
             rc = hip(launch_fused_generic(g, p, f, w, cfg, s), "fused mover");
         }
@@ -102,7 +109,9 @@ int spic_ctx_s::sort(const spic_grid &g, spic_species *sp, int32_t nsp, hipStrea
         if ((rc = reserve(slot.c_str(), (size_t)(tg.ntiles + 1) * 4, &toff))) return rc;
         if ((rc = reserve("sort", need, &scr))) return rc;
         SpeciesWork w = work_of(sp[i], nullptr);
-        if ((rc = hip(launch_sort(g, w, tg, scr, (uint32_t *)toff, s), "sort"))) return rc;
+        auto it = layouts.find(key);
+        const bool prev = it != layouts.end() && same_tiling(it->second.tg, tg);
+        if ((rc = hip(launch_sort(g, w, tg, scr, (uint32_t *)toff, prev, s), "sort"))) return rc;
         layouts[key] = Layout{tg, slot};
     }
     return SPIC_OK;

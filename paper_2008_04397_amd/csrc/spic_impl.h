@@ -54,6 +54,7 @@ struct LaunchCfg {
     int grid_cap = 1 << 20;
     int tile_block = 256;   // tiled fused kernel
     int variant = 0;        // tiled kernel variant (see spic_tiled.hip)
+    int fixed_geo = 1;      // compile-time region geometry for the default tiling
 };
 
 // Tiles of tx x ty x tz cells (at most 64 cells) cover the grid; ntx.. are
@@ -66,6 +67,74 @@ struct TileGeom {
     int halo, rx, ry, rz;
     int ryp, rzp, rnp, pad;  // padded LDS extents (bank spread) and slots rx*ryp*rzp
 };
+
+// Padded LDS extents RYP >= ry, RZP >= rz of a region: the lower corners of
+// a full tile's cells (one cell per lane) should hit the 16 pairs of 4-byte
+// banks as evenly as possible, for every corner offset; among the most even
+// paddings the one with the fewest slots wins.  constexpr so that kernels
+// specialised for one tiling use the same layout as the host.
+struct RegionPadding {
+    int ryp, rzp;
+};
+
+constexpr RegionPadding region_padding(int tx, int ty, int tz, int halo) {
+    const int rx = tx + 2 * halo + 1, ry = ty + 2 * halo + 1, rz = tz + 2 * halo + 1;
+    int best_w = 1 << 30, best_n = 1 << 30, bry = ry, brz = rz;
+    for (int ryp = ry; ryp < ry + 9; ++ryp)
+        for (int rzp = rz; rzp < rz + 9; ++rzp) {
+            const int sx = ryp * rzp, sy = rzp;
+            int worst = 0;
+            for (int c = 0; c < 8; ++c) {
+                int cnt[16] = {};
+                for (int li = 0; li < tx; ++li)
+                    for (int lj = 0; lj < ty; ++lj)
+                        for (int lk = 0; lk < tz; ++lk) {
+                            const int slot = (li + halo + (c & 1)) * sx + (lj + halo + ((c >> 1) & 1)) * sy +
+                                             (lk + halo + (c >> 2));
+                            const int v = ++cnt[slot & 15];
+                            worst = v > worst ? v : worst;
+                        }
+            }
+            const int slots = rx * sx;
+            if (worst < best_w || (worst == best_w && slots < best_n)) {
+                best_w = worst;
+                best_n = slots;
+                bry = ryp;
+                brz = rzp;
+            }
+        }
+    return RegionPadding{bry, brz};
+}
+
+// Region geometry known at compile time (the default tiling): LDS offsets of
+// corners and moment components fold into instruction immediates.
+struct GeoRuntime {
+    static constexpr bool fixed = false;
+    static constexpr int tx = 0, ty = 0, tz = 0, halo = 0, rx = 0, ry = 0, rz = 0, ryp = 0, rzp = 0, rnp = 0;
+};
+
+template <int TX, int TY, int TZ, int HALO>
+struct GeoFixed {
+    static constexpr bool fixed = true;
+    static constexpr int tx = TX, ty = TY, tz = TZ, halo = HALO;
+    static constexpr int rx = TX + 2 * HALO + 1, ry = TY + 2 * HALO + 1, rz = TZ + 2 * HALO + 1;
+    static constexpr int ryp = region_padding(TX, TY, TZ, HALO).ryp;
+    static constexpr int rzp = region_padding(TX, TY, TZ, HALO).rzp;
+    static constexpr int rnp = rx * ryp * rzp;
+};
+
+using GeoDefault = GeoFixed<4, 4, 4, 1>;
+
+// The tiled kernels address particle arrays with 32-bit byte offsets.
+inline bool tiled_fits(int64_t n, int dtype) {
+    return n >= 0 && (uint64_t)n * (dtype == SPIC_F64 ? 8u : 4u) < ((uint64_t)1 << 32);
+}
+
+inline bool geo_is_default(const TileGeom &t) {
+    return t.tx == GeoDefault::tx && t.ty == GeoDefault::ty && t.tz == GeoDefault::tz &&
+           t.halo == GeoDefault::halo && t.ryp == GeoDefault::ryp && t.rzp == GeoDefault::rzp &&
+           t.rnp == GeoDefault::rnp;
+}
 
 template <typename T>
 inline GridT<T> make_grid_t(const spic_grid &g) {
@@ -161,25 +230,35 @@ hipError_t launch_deposit_generic(const spic_grid &g, const SpeciesWork &w, cons
 // Sort (spic_sort.hip).
 TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo);
 size_t sort_scratch_bytes(int64_t n, int dtype, bool with_id, const TileGeom &tg);
+// prev: tile_off already holds the per-tile ranges of the particles'
+// current order (an earlier sort with the same tiles and n); the key pass
+// then walks tiles in that order, which keeps the scatter's writes local.
 hipError_t launch_sort(const spic_grid &g, const SpeciesWork &w, const TileGeom &tg, void *scratch,
-                       uint32_t *tile_off, hipStream_t s);
+                       uint32_t *tile_off, bool prev, hipStream_t s);
+inline bool same_tiling(const TileGeom &a, const TileGeom &b) {
+    return a.tx == b.tx && a.ty == b.ty && a.tz == b.tz && a.halo == b.halo && a.ntiles == b.ntiles &&
+           a.ntx == b.ntx && a.nty == b.nty && a.ntz == b.ntz;
+}
 
 // Tiled fused path (spic_tiled.hip): one workgroup per tile of a sorted
 // species, fields and moments of the tile region staged in LDS.
-size_t tiled_lds_bytes(const TileGeom &tg, int dtype, int acc_dtype);
+// LDS bytes of one workgroup of the tiled kernel (variant and block size
+// matter: variant 2 adds per-wave queues).
+size_t tiled_lds_bytes(const TileGeom &tg, int dtype, int acc_dtype, int variant, int block);
 hipError_t launch_fused_tiled(const spic_grid &g, const spic_params &prm, const spic_fields &f,
                               const SpeciesWork &w, const TileGeom &tg, const uint32_t *tile_off,
                               const LaunchCfg &cfg, hipStream_t s);
 
 // Work lists (spic_tiled.hip).  combo: 0 f64/f64/f64, 1 f32/f32/f64,
 // 2 f32/f32/f32, 3 f32/f64/f64, 4 f32/f64/f32 (particles/fields/moments);
-// -1 for an unsupported combination.
+// -1 for an unsupported combination.  fixed: every job of the launch uses
+// the default tiling (GeoDefault) and the kernel compiled for it.
 int job_combo(int dtype, int fdtype, int acc_dtype);
 size_t tile_job_bytes(int combo);
 void write_tile_job(int combo, void *dst, const spic_grid &g, const spic_params &prm, const spic_fields &f,
                     const SpeciesWork &w, const TileGeom &tg, const uint32_t *tile_off);
-int worklist_groups(int combo, int variant, size_t lds, int block, int nitems, int max_groups);
-hipError_t launch_worklist(int combo, int variant, const void *jobs, const uint2 *items, int nitems,
+int worklist_groups(int combo, bool fixed, int variant, size_t lds, int block, int nitems, int max_groups);
+hipError_t launch_worklist(int combo, bool fixed, int variant, const void *jobs, const uint2 *items, int nitems,
                            unsigned *counter, size_t lds, int block, int groups, hipStream_t s);
 hipError_t launch_fill_many(void *const *ptrs, const int64_t *counts, int narr, int elem_bytes, hipStream_t s);
 

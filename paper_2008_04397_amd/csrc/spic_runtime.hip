@@ -190,9 +190,11 @@ static const char *const kOptionNames[] = {
     "lds_max",      // read only: LDS bytes per workgroup on the device
     "tile_variant", // tiled kernel: 0 LDS atomics, 1 + field corners in registers, 2 home-cell registers,
                     // 3 LDS atomics with lane-rotated corners
+    "fixed_geo",    // tiled kernel: 1 = compile-time region geometry for 4x4x4 tiles, halo 1
     "graph",        // batch engine: 1 = replay unchanged ticks as a hipGraph
     "batch_particles",  // batch engine: particles per streamed batch (upper bound)
     "max_groups",   // batch engine: cap on workgroups of the persistent launch (0 = occupancy)
+    "tick_items",   // batch engine: (job, tile) items per tick, shortest runs first (0 = all runs)
 };
 
 int64_t spic_ctx_s::opt(const char *k, int64_t dflt) const {
@@ -206,6 +208,7 @@ LaunchCfg spic_ctx_s::launch_cfg() const {
     c.grid_cap = (int)opt("grid_cap", 1 << 20);
     c.tile_block = (int)opt("tile_block", 256);
     c.variant = (int)opt("tile_variant", 0);
+    c.fixed_geo = (int)opt("fixed_geo", 1);
     return c;
 }
 
@@ -280,6 +283,12 @@ int spic_set_option(spic_ctx ctx, const char *key, int64_t value) {
                 return ctx->fail(SPIC_E_ARG, "tile sizes must be in [1, 64]");
             if (!strcmp(key, "tile_variant") && (value < 0 || value > 3))
                 return ctx->fail(SPIC_E_ARG, "tile_variant must be 0, 1, 2 or 3");
+            if (!strcmp(key, "batch_particles") && (value < 1024 || value > ((int64_t)1 << 29)))
+                return ctx->fail(SPIC_E_ARG, "batch_particles must be in [1024, 2^29]");
+            if (!strcmp(key, "tick_items") && (value < 0 || value > ((int64_t)1 << 30)))
+                return ctx->fail(SPIC_E_ARG, "tick_items must be in [0, 2^30]");
+            if (!strcmp(key, "fixed_geo") && (value < 0 || value > 1))
+                return ctx->fail(SPIC_E_ARG, "fixed_geo must be 0 or 1");
             if (!strcmp(key, "halo") && (value < 0 || value > 8))
                 return ctx->fail(SPIC_E_ARG, "halo must be in [0, 8]");
             if (!strcmp(key, "lds_max")) return ctx->fail(SPIC_E_ARG, "lds_max is read only");

@@ -80,6 +80,30 @@ k_sort_keys(GridT<T> g, TileGeom tg, const T *__restrict__ x, const T *__restric
     }
 }
 
+// Keys and ranks of particles that are still in the tile layout of an
+// earlier sort with the same tiles (prev_off = that sort's per-tile ranges,
+// a partition of [0, n)).  One workgroup walks one tile's range in order, so
+// a cell's ranks follow the earlier order up to the few waves in flight, and
+// the scatter writes nearly contiguous runs instead of one scattered value
+// per lane.  Correct for any partition of [0, n): only locality depends on
+// the particles still being near their earlier tiles.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sort_keys_tiled(GridT<T> g, TileGeom tg, const T *__restrict__ x, const T *__restrict__ y,
+                  const T *__restrict__ z, const uint32_t *__restrict__ prev_off, uint32_t *__restrict__ counts,
+                  uint2 *__restrict__ keyrank) {
+    for (int t = blockIdx.x; t < tg.ntiles; t += gridDim.x) {
+        const uint32_t b = prev_off[t], e = prev_off[t + 1];
+        for (uint32_t p = b + threadIdx.x; p < e; p += blockDim.x) {
+            const int i = sort_locate(x[p], g.L[0], g.invL[0], g.invd[0], g.nx);
+            const int j = sort_locate(y[p], g.L[1], g.invL[1], g.invd[1], g.ny);
+            const int k = sort_locate(z[p], g.L[2], g.invL[2], g.invd[2], g.nz);
+            const uint32_t key = tile_key(tg, i, j, k);
+            keyrank[p] = make_uint2(key, atomicAdd(counts + key, 1u));
+        }
+    }
+}
+
 // ----------------------------------------------------------------- scan
 
 constexpr int SCAN_BLOCK = 256;
@@ -267,30 +291,8 @@ TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo) {
     t.rx = tx + 2 * halo + 1;
     t.ry = ty + 2 * halo + 1;
     t.rz = tz + 2 * halo + 1;
-    // Padded LDS extents: choose RYP >= ry, RZP >= rz so that the lower
-    // corners of a full tile's cells (one cell per lane) hit the 16 pairs of
-    // 4-byte banks as evenly as possible, for every corner offset; prefer
-    // the fewest slots among the most even.
-    int best_w = 1 << 30, best_n = 1 << 30, bry = t.ry, brz = t.rz;
-    for (int ryp = t.ry; ryp < t.ry + 9; ++ryp)
-        for (int rzp = t.rz; rzp < t.rz + 9; ++rzp) {
-            const int sx = ryp * rzp, sy = rzp;
-            int worst = 0;
-            for (int c = 0; c < 8; ++c) {
-                int cnt[16] = {0};
-                for (int li = 0; li < tx; ++li)
-                    for (int lj = 0; lj < ty; ++lj)
-                        for (int lk = 0; lk < tz; ++lk) {
-                            const int slot = (li + halo + (c & 1)) * sx + (lj + halo + ((c >> 1) & 1)) * sy +
-                                             (lk + halo + (c >> 2));
-                            worst = std::max(worst, ++cnt[slot & 15]);
-                        }
-            }
-            const int slots = t.rx * sx;
-            if (worst < best_w || (worst == best_w && slots < best_n)) {
-                best_w = worst; best_n = slots; bry = ryp; brz = rzp;
-            }
-        }
+    const RegionPadding pad = region_padding(tx, ty, tz, halo);
+    const int bry = pad.ryp, brz = pad.rzp;
     t.ryp = bry;
     t.rzp = brz;
     t.rnp = t.rx * bry * brz;
@@ -323,7 +325,7 @@ static inline char *carve(char *&cur, size_t bytes) {
 
 template <typename T>
 static hipError_t sort_t(const spic_grid &g, const SpeciesWork &w, const TileGeom &tg, void *scratch,
-                         uint32_t *tile_off, hipStream_t s) {
+                         uint32_t *tile_off, bool prev, hipStream_t s) {
     const int64_t n = w.n;
     const int64_t nkeys = (int64_t)tg.ntiles * tg.cells;
     const int nparts = (int)((nkeys + SCAN_CHUNK - 1) / SCAN_CHUNK);
@@ -350,8 +352,12 @@ static hipError_t sort_t(const spic_grid &g, const SpeciesWork &w, const TileGeo
     hipError_t e;
     if ((e = launch_zero32(counts, nkeys, s)) != hipSuccess) return e;
     const int gp = (int)std::min<int64_t>((n + 255) / 256, 1 << 16);
-    hipLaunchKernelGGL((k_sort_keys<T>), dim3(gp > 0 ? gp : 1), dim3(256), 0, s, make_grid_t<T>(g), tg, src.x,
-                       src.y, src.z, n, counts, keyrank);
+    if (prev)  // tile_off still holds the ranges of the current order
+        hipLaunchKernelGGL((k_sort_keys_tiled<T>), dim3(std::min(tg.ntiles, 1 << 16)), dim3(256), 0, s,
+                           make_grid_t<T>(g), tg, src.x, src.y, src.z, (const uint32_t *)tile_off, counts, keyrank);
+    else
+        hipLaunchKernelGGL((k_sort_keys<T>), dim3(gp > 0 ? gp : 1), dim3(256), 0, s, make_grid_t<T>(g), tg, src.x,
+                           src.y, src.z, n, counts, keyrank);
     hipLaunchKernelGGL(k_scan_partials, dim3(nparts), dim3(SCAN_BLOCK), 0, s, counts, nkeys, partial);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, partial, nparts);
     hipLaunchKernelGGL(k_scan_apply, dim3(nparts), dim3(SCAN_BLOCK), 0, s, counts, nkeys, partial, offsets);
@@ -371,12 +377,12 @@ static hipError_t sort_t(const spic_grid &g, const SpeciesWork &w, const TileGeo
 }
 
 hipError_t launch_sort(const spic_grid &g, const SpeciesWork &w, const TileGeom &tg, void *scratch,
-                       uint32_t *tile_off, hipStream_t s) {
+                       uint32_t *tile_off, bool prev, hipStream_t s) {
     if (w.n <= 0) {
         return launch_zero32(tile_off, tg.ntiles + 1, s);
     }
-    return w.dtype == SPIC_F64 ? sort_t<double>(g, w, tg, scratch, tile_off, s)
-                               : sort_t<float>(g, w, tg, scratch, tile_off, s);
+    return w.dtype == SPIC_F64 ? sort_t<double>(g, w, tg, scratch, tile_off, prev, s)
+                               : sort_t<float>(g, w, tg, scratch, tile_off, prev, s);
 }
 
 }  // namespace spic

@@ -92,6 +92,20 @@ __device__ __forceinline__ void gather_lds(const LdsFieldNode<TP> *__restrict__ 
     }
 }
 
+// Element i of a particle array through a 32-bit byte offset from the
+// array base (the host sends only species with n * sizeof(T) < 2^32 here):
+// a uniform 64-bit base plus one 32-bit offset per lane, shared by all
+// seven arrays.
+template <typename T>
+__device__ __forceinline__ T ld32(const T *base, uint32_t byte_off) {
+    return *(const T *)((const char *)base + byte_off);
+}
+
+template <typename T>
+__device__ __forceinline__ void st32(T *base, uint32_t byte_off, T v) {
+    *(T *)((char *)base + byte_off) = v;
+}
+
 // Periodic index o + r with 0 <= o < n, r >= 0: subtract n while needed
 // (once, unless the region is wider than the grid).
 __device__ __forceinline__ int pwrap_index(int v, int n) {
@@ -118,17 +132,98 @@ __device__ __forceinline__ RegionNode region_node(const TileGeom &tg, int nx, in
     return n;
 }
 
+// Ten moments of one moved particle into the region accumulator with LDS
+// atomics, or into the global moments when its cell left the region.
+template <typename TA, class GEO>
+__device__ __forceinline__ void deposit_one(const GridT<TA> &ga, const TileGeom &tg, int ox, int oy, int oz,
+                                            TA *__restrict__ ml, TA *__restrict__ mom, int nn, TA x, TA y, TA z,
+                                            TA qa, TA ua, TA va, TA wa, bool rotate) {
+    const int RNP = tg.rnp, sx = tg.ryp * tg.rzp, sy = tg.rzp;
+    int rb;
+    Cell<TA> c;
+    const bool in = region_locate(ga, tg, ox, oy, oz, x, y, z, rb, c);
+    const TA val[10] = {TA(1), ua, va, wa, ua * ua, ua * va, ua * wa, va * va, va * wa, wa * wa};
+    if (in && rotate) {
+        // instruction k of lane l deposits corner k ^ (l & 7): lanes that
+        // share a cell then hit different nodes in the same instruction
+        const int s = threadIdx.x & 7;
+        const TA gx = TA(1) - c.fx, gy = TA(1) - c.fy, gz = TA(1) - c.fz;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int cc = k ^ s;
+            const TA wx = (cc & 1) ? c.fx : gx, wy = (cc & 2) ? c.fy : gy, wz = (cc & 4) ? c.fz : gz;
+            const TA qw = qa * (wx * wy * wz);
+            TA *dst = ml + rb + ((cc & 1) ? sx : 0) + ((cc & 2) ? sy : 0) + ((cc & 4) ? 1 : 0);
+#pragma unroll
+            for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, qw * val[m]);
+        }
+        return;
+    }
+    TA wt8[8];
+    pweights(c.fx, c.fy, c.fz, wt8);
+    if (in) {
+        const int coff[8] = {0, sx, sy, sx + sy, 1, sx + 1, sy + 1, sx + sy + 1};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const TA qw = qa * wt8[k];
+            TA *dst = ml + rb + coff[k];
+#pragma unroll
+            for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, qw * val[m]);
+        }
+    } else {  // rare: the particle left the region
+        int nd[8];
+        pnodes(c, nd);
+#pragma unroll 1
+        for (int k = 0; k < 8; ++k) {
+            const TA qw = qa * wt8[k];
+            TA *dst = mom + nd[k];
+#pragma unroll 1
+            for (int m = 0; m < 10; ++m) atomicAdd(dst + (size_t)m * nn, qw * val[m]);
+        }
+    }
+}
+
+// Orders one wave's LDS accesses across lanes (a wave's LDS operations are
+// processed in issue order; this keeps the compiler from reordering them).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One moved particle waiting in a wave's queue (variant 2).
+template <typename TP>
+struct QueuedParticle {
+    TP x, y, z, u, v, w, q, pad;
+};
+
+// Records per wave queue: at most 63 wait between drains, and one
+// iteration adds at most 64.
+constexpr int kQueueCap = 128;
+
+// LDS bytes of the per-wave queues of variant 2 (0 for the others).
+inline size_t queue_lds_bytes(int variant, int block, int dtype) {
+    if (variant != 2) return 0;
+    return (size_t)(block / 64) * kQueueCap * 8 * (dtype == SPIC_F64 ? 8 : 4);
+}
+
 // One tile of one species: stage the region, move and deposit the tile's
 // particles, flush the region's moments.  Called by the per-species tiled
 // kernel and by the work-list kernel of the batch engine; `t` is uniform
-// across the workgroup.
-template <typename TP, typename TF, typename TA, int VAR>
+// across the workgroup.  The particle loop is uniform per wave (lanes past
+// the end of the range idle), so wave-wide votes are safe inside it.
+template <typename TP, typename TF, typename TA, int VAR, class GEO>
 __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, unsigned char *smem) {
-    constexpr bool HOME = VAR == 2;   // home-cell register accumulation
+    constexpr bool HOME = VAR == 2;   // home-cell registers + queue of drifted particles
     constexpr bool CACHE = VAR == 1;  // field corners of the last cell in registers
     constexpr bool ROTATE = VAR == 3; // lane-rotated corner order of the LDS deposit
     const GridT<TP> &g = J.g;
-    const TileGeom &tg = J.tg;
+    TileGeom tg = J.tg;
+    if constexpr (GEO::fixed) {  // the host launches this only for a matching tiling
+        tg.tx = GEO::tx; tg.ty = GEO::ty; tg.tz = GEO::tz; tg.halo = GEO::halo;
+        tg.rx = GEO::rx; tg.ry = GEO::ry; tg.rz = GEO::rz;
+        tg.ryp = GEO::ryp; tg.rzp = GEO::rzp; tg.rnp = GEO::rnp;
+    }
     const FieldPtrs<TF> &f = J.f;
     const PartPtrs<TP> &p = J.p;
     TA *__restrict__ mom = J.mom;
@@ -137,8 +232,9 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
     if (beg == end) return;  // uniform: no particle in this tile
 
     const int RNP = tg.rnp;
+    const size_t fbytes = (RNP * sizeof(LdsFieldNode<TP>) + 15) & ~(size_t)15;
     LdsFieldNode<TP> *fl = (LdsFieldNode<TP> *)smem;
-    TA *ml = (TA *)(smem + ((RNP * sizeof(LdsFieldNode<TP>) + 15) & ~(size_t)15));
+    TA *ml = (TA *)(smem + fbytes);
     const int tzi = t % tg.ntz, tyi = (t / tg.ntz) % tg.nty, txi = t / (tg.ntz * tg.nty);
     int ox = (txi * tg.tx - tg.halo) % g.nx; ox += ox < 0 ? g.nx : 0;
     int oy = (tyi * tg.ty - tg.halo) % g.ny; oy += oy < 0 ? g.ny : 0;
@@ -165,144 +261,165 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
     int home = -1;
     LdsFieldNode<TP> corner[CACHE ? 8 : 1];  // field corners of the cell `cached`
     int cached = -1;
+    // variant 2: this wave's queue of drifted particles, a stack of qn records
+    QueuedParticle<TP> *queue = nullptr;
+    int qn = 0;  // uniform across the wave
+    if constexpr (HOME)
+        queue = (QueuedParticle<TP> *)(smem + fbytes + (((size_t)10 * RNP * sizeof(TA) + 15) & ~(size_t)15)) +
+                (threadIdx.x >> 6) * kQueueCap;
+    const int lane = threadIdx.x & 63;
 
     const uint32_t stride = blockDim.x;
+    constexpr uint32_t ES = sizeof(TP);
     uint32_t i = beg + threadIdx.x;
     TP nx_ = 0, ny_ = 0, nz_ = 0, nu_ = 0, nv_ = 0, nw_ = 0, nq_ = 0;
     if (i < end) {
-        nx_ = p.x[i]; ny_ = p.y[i]; nz_ = p.z[i];
-        nu_ = p.u[i]; nv_ = p.v[i]; nw_ = p.w[i]; nq_ = p.q[i];
+        const uint32_t o = i * ES;
+        nx_ = ld32(p.x, o); ny_ = ld32(p.y, o); nz_ = ld32(p.z, o);
+        nu_ = ld32(p.u, o); nv_ = ld32(p.v, o); nw_ = ld32(p.w, o); nq_ = ld32(p.q, o);
     }
-    for (; i < end; i += stride) {
+    // uniform per wave: the first index of this wave's lane 0
+    for (uint32_t i0 = beg + (threadIdx.x & ~63u); i0 < end; i0 += stride, i += stride) {
+        const bool valid = i < end;
         TP xn = nx_, yn = ny_, zn = nz_, un = nu_, vn = nv_, wn = nw_;
         const TP qp = nq_;
-        // the cell located by the first gather of this particle; later
-        // gathers inside it reuse it (same result as locating again)
-        int c_ijk[3] = {-1, 0, 0}, c_rb = 0;
-        bool c_in = false;
-        Cell<TP> c_cell;
         const uint32_t inext = i + stride;
         if (inext < end) {  // prefetch the next particle while this one is moved
-            nx_ = p.x[inext]; ny_ = p.y[inext]; nz_ = p.z[inext];
-            nu_ = p.u[inext]; nv_ = p.v[inext]; nw_ = p.w[inext]; nq_ = p.q[inext];
+            const uint32_t o = inext * ES;
+            nx_ = ld32(p.x, o); ny_ = ld32(p.y, o); nz_ = ld32(p.z, o);
+            nu_ = ld32(p.u, o); nv_ = ld32(p.v, o); nw_ = ld32(p.w, o); nq_ = ld32(p.q, o);
         }
-        implicit_move(
-            g, J.mv,
-            [&](TP px, TP py, TP pz, TP F[6]) {
-                int rb;
-                Cell<TP> c;
-                bool in;
-                const TP tx = px * g.invd[0] - (TP)c_ijk[0];
-                const TP ty = py * g.invd[1] - (TP)c_ijk[1];
-                const TP tz = pz * g.invd[2] - (TP)c_ijk[2];
-                if (c_ijk[0] >= 0 && px >= TP(0) && px < g.L[0] && py >= TP(0) && py < g.L[1] && pz >= TP(0) &&
-                    pz < g.L[2] && tx >= TP(0) && tx < TP(1) && ty >= TP(0) && ty < TP(1) && tz >= TP(0) &&
-                    tz < TP(1)) {
-                    c = c_cell;
-                    c.fx = tx;
-                    c.fy = ty;
-                    c.fz = tz;
-                    rb = c_rb;
-                    in = c_in;
-                } else {
-                    in = region_locate(g, tg, ox, oy, oz, px, py, pz, rb, c, c_ijk);
-                    if (in) {  // the global cell is needed only outside the region
-                        c.base = 0; c.ox = 0; c.oy = 0; c.oz = 0;
-                    }
-                    c_cell = c;
-                    c_rb = rb;
-                    c_in = in;
-                }
-                if (in) {
-                    if (!CACHE) {
-                        gather_lds(fl, tg, rb, c, F);
+        bool enq = false;
+        if (valid) {
+            // the cell located by the first gather of this particle; later
+            // gathers inside it reuse it (same result as locating again)
+            int c_ijk[3] = {-1, 0, 0}, c_rb = 0;
+            bool c_in = false;
+            Cell<TP> c_cell;
+            implicit_move(
+                g, J.mv,
+                [&](TP px, TP py, TP pz, TP F[6]) {
+                    int rb;
+                    Cell<TP> c;
+                    bool in;
+                    const TP tx = cell_coord(px, g.invd[0]) - (TP)c_ijk[0];
+                    const TP ty = cell_coord(py, g.invd[1]) - (TP)c_ijk[1];
+                    const TP tz = cell_coord(pz, g.invd[2]) - (TP)c_ijk[2];
+                    if (c_ijk[0] >= 0 && px >= TP(0) && px < g.L[0] && py >= TP(0) && py < g.L[1] &&
+                        pz >= TP(0) && pz < g.L[2] && tx >= TP(0) && tx < TP(1) && ty >= TP(0) && ty < TP(1) &&
+                        tz >= TP(0) && tz < TP(1)) {
+                        c = c_cell;
+                        c.fx = tx;
+                        c.fy = ty;
+                        c.fz = tz;
+                        rb = c_rb;
+                        in = c_in;
                     } else {
-                        // the corners of the last LDS cell stay in registers:
-                        // a thread's particles share their sort cell
-                        if (rb != cached) {
-                            const int nd[8] = {rb, rb + sx, rb + sy, rb + sx + sy, rb + 1, rb + sx + 1, rb + sy + 1,
-                                               rb + sx + sy + 1};
-#pragma unroll
-                            for (int k = 0; k < 8; ++k) corner[k] = fl[nd[k]];
-                            cached = rb;
+                        in = region_locate(g, tg, ox, oy, oz, px, py, pz, rb, c, c_ijk);
+                        if (in) {  // the global cell is needed only outside the region
+                            c.base = 0; c.ox = 0; c.oy = 0; c.oz = 0;
                         }
-                        TP w[8];
-                        pweights(c.fx, c.fy, c.fz, w);
+                        c_cell = c;
+                        c_rb = rb;
+                        c_in = in;
+                    }
+                    if (in) {
+                        if (!CACHE) {
+                            gather_lds(fl, tg, rb, c, F);
+                        } else {
+                            // the corners of the last LDS cell stay in
+                            // registers: a thread's particles share their sort cell
+                            if (rb != cached) {
 #pragma unroll
-                        for (int m = 0; m < 6; ++m) F[m] = TP(0);
+                                for (int k = 0; k < 8; ++k) corner[k] = fl[rb + coff[k]];
+                                cached = rb;
+                            }
+                            TP w[8];
+                            pweights(c.fx, c.fy, c.fz, w);
 #pragma unroll
-                        for (int k = 0; k < 8; ++k)
+                            for (int m = 0; m < 6; ++m) F[m] = TP(0);
 #pragma unroll
-                            for (int m = 0; m < 6; ++m) F[m] += w[k] * corner[k].v[m];
+                            for (int k = 0; k < 8; ++k)
+#pragma unroll
+                                for (int m = 0; m < 6; ++m) F[m] += w[k] * corner[k].v[m];
+                        }
+                    } else {
+                        gather_cell_global(f, c, F);
+                    }
+                },
+                xn, yn, zn, un, vn, wn);
+            const uint32_t o = i * ES;
+            st32(p.x, o, xn); st32(p.y, o, yn); st32(p.z, o, zn);
+            st32(p.u, o, un); st32(p.v, o, vn); st32(p.w, o, wn);
+
+            if (mom) {
+                // deposit of the new state in the accumulation precision
+                const TA qa = (TA)qp;
+                const TA ua = (TA)un, va = (TA)vn, wa = (TA)wn;
+                if constexpr (HOME) {
+                    int rb;
+                    Cell<TA> c;
+                    const bool in = region_locate(J.ga, tg, ox, oy, oz, (TA)xn, (TA)yn, (TA)zn, rb, c);
+                    if (in && home < 0) home = rb;
+                    if (in && rb == home) {
+                        TA wt8[8];
+                        pweights(c.fx, c.fy, c.fz, wt8);
+                        const TA val[10] = {TA(1), ua, va, wa, ua * ua, ua * va, ua * wa, va * va, va * wa, wa * wa};
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) {
+                            const TA qw = qa * wt8[k];
+#pragma unroll
+                            for (int m = 0; m < 10; ++m) acc[(k * 10 + m) % (HOME ? 80 : 1)] += qw * val[m];
+                        }
+                    } else {
+                        enq = true;  // another cell, or outside the region
                     }
                 } else {
-                    gather_cell_global(f, c, F);
+                    deposit_one<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, (TA)xn, (TA)yn, (TA)zn, qa, ua, va, wa,
+                                         ROTATE);
                 }
-            },
-            xn, yn, zn, un, vn, wn);
-        p.x[i] = xn; p.y[i] = yn; p.z[i] = zn;
-        p.u[i] = un; p.v[i] = vn; p.w[i] = wn;
-        if (!mom) continue;
-
-        // deposit of the new state in the accumulation precision
-        const TA qa = (TA)qp;
-        const TA ua = (TA)un, va = (TA)vn, wa = (TA)wn;
-        int rb;
-        Cell<TA> c;
-        const bool in = region_locate(J.ga, tg, ox, oy, oz, (TA)xn, (TA)yn, (TA)zn, rb, c);
-        TA wt8[8];
-        pweights(c.fx, c.fy, c.fz, wt8);
-        const TA val[10] = {TA(1), ua, va, wa, ua * ua, ua * va, ua * wa, va * va, va * wa, wa * wa};
-        if (HOME && in && home < 0) home = rb;
-        if (HOME && in && rb == home) {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const TA qw = qa * wt8[k];
-#pragma unroll
-                for (int m = 0; m < 10; ++m) acc[(k * 10 + m) % (HOME ? 80 : 1)] += qw * val[m];
             }
-        } else if (in && ROTATE) {
-            // instruction k of lane l deposits corner k ^ (l & 7): lanes that
-            // share a cell (particles that drifted into a neighbour's cell)
-            // then hit different nodes in the same instruction
-            const int s = threadIdx.x & 7;
-            const TA gx = TA(1) - c.fx, gy = TA(1) - c.fy, gz = TA(1) - c.fz;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int cc = k ^ s;
-                const TA wx = (cc & 1) ? c.fx : gx, wy = (cc & 2) ? c.fy : gy, wz = (cc & 4) ? c.fz : gz;
-                const TA qw = qa * (wx * wy * wz);
-                TA *dst = ml + rb + ((cc & 1) ? sx : 0) + ((cc & 2) ? sy : 0) + ((cc & 4) ? 1 : 0);
-#pragma unroll
-                for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, qw * val[m]);
-            }
-        } else if (in) {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const TA qw = qa * wt8[k];
-                TA *dst = ml + rb + coff[k];
-#pragma unroll
-                for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, qw * val[m]);
-            }
-        } else {  // rare: the particle left the region
-            int nd[8];
-            pnodes(c, nd);
-#pragma unroll 1
-            for (int k = 0; k < 8; ++k) {
-                const TA qw = qa * wt8[k];
-                TA *dst = mom + nd[k];
-#pragma unroll 1
-                for (int m = 0; m < 10; ++m) atomicAdd(dst + (size_t)m * nn, qw * val[m]);
+        }
+        if constexpr (HOME) {
+            // queue the drifted particles of this iteration; once 64 wait,
+            // deposit them with every lane active
+            const unsigned long long vote = __ballot(enq);
+            if (vote) {
+                const unsigned long long below = lane ? (vote & (~0ull >> (64 - lane))) : 0ull;
+                if (enq) {
+                    QueuedParticle<TP> r;
+                    r.x = xn; r.y = yn; r.z = zn; r.u = un; r.v = vn; r.w = wn; r.q = qp; r.pad = TP(0);
+                    queue[qn + __popcll(below)] = r;
+                }
+                qn += __popcll(vote);
+                if (qn >= 64) {
+                    // the records written above by other lanes of this wave
+                    // are visible after a wave-scope fence
+                    wave_sync();
+                    qn -= 64;
+                    const QueuedParticle<TP> r = queue[qn + lane];
+                    wave_sync();
+                    deposit_one<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, (TA)r.x, (TA)r.y, (TA)r.z, (TA)r.q,
+                                         (TA)r.u, (TA)r.v, (TA)r.w, false);
+                }
             }
         }
     }
     if (!mom) return;
-    if (HOME && home >= 0) {
+    if constexpr (HOME) {
+        wave_sync();
+        if (lane < qn) {
+            const QueuedParticle<TP> r = queue[lane];
+            deposit_one<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, (TA)r.x, (TA)r.y, (TA)r.z, (TA)r.q, (TA)r.u,
+                                 (TA)r.v, (TA)r.w, false);
+        }
+        if (home >= 0) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            TA *dst = ml + home + coff[k];
+            for (int k = 0; k < 8; ++k) {
+                TA *dst = ml + home + coff[k];
 #pragma unroll
-            for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, acc[(k * 10 + m) % (HOME ? 80 : 1)]);
+                for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, acc[(k * 10 + m) % (HOME ? 80 : 1)]);
+            }
         }
     }
     __syncthreads();
@@ -331,20 +448,20 @@ struct VariantWaves {
     static constexpr int value = (VAR == 0 || VAR == 3) ? 4 : (VAR == 1 ? 3 : 2);
 };
 
-template <typename TP, typename TF, typename TA, int VAR>
+template <typename TP, typename TF, typename TA, int VAR, class GEO>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VariantWaves<VAR>::value)))
 k_fused_tiled(TileJob<TP, TF, TA> J, int chunk) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int b = blockIdx.x;
     const int t = (b & 7) * chunk + (b >> 3);
     if (t >= J.tg.ntiles) return;
-    tile_body<TP, TF, TA, VAR>(J, t, smem);
+    tile_body<TP, TF, TA, VAR, GEO>(J, t, smem);
 }
 
 // Persistent work-list kernel: workgroups take (job, tile) items from an
 // atomic counter until the list is drained; every workgroup exits once the
 // counter passes nitems.  The counter must be zero at launch.
-template <typename TP, typename TF, typename TA, int VAR>
+template <typename TP, typename TF, typename TA, int VAR, class GEO>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VariantWaves<VAR>::value)))
 k_worklist(const TileJob<TP, TF, TA> *__restrict__ jobs, const uint2 *__restrict__ items, int nitems,
            unsigned *__restrict__ counter) {
@@ -358,14 +475,14 @@ k_worklist(const TileJob<TP, TF, TA> *__restrict__ jobs, const uint2 *__restrict
         if (it >= nitems) break;
         const uint2 item = items[it];
         const TileJob<TP, TF, TA> J = jobs[item.x];
-        tile_body<TP, TF, TA, VAR>(J, (int)item.y, smem);
+        tile_body<TP, TF, TA, VAR, GEO>(J, (int)item.y, smem);
     }
 }
 
-size_t tiled_lds_bytes(const TileGeom &tg, int dtype, int acc_dtype) {
+size_t tiled_lds_bytes(const TileGeom &tg, int dtype, int acc_dtype, int variant, int block) {
     const size_t fsz = (size_t)tg.rnp * 6 * (dtype == SPIC_F64 ? 8 : 4);
     const size_t msz = (size_t)tg.rnp * 10 * (acc_dtype == SPIC_F64 ? 8 : 4);
-    return ((fsz + 15) & ~(size_t)15) + msz;
+    return ((fsz + 15) & ~(size_t)15) + ((msz + 15) & ~(size_t)15) + queue_lds_bytes(variant, block, dtype);
 }
 
 // Dynamic LDS above 64 KiB must be allowed per kernel once.
@@ -379,34 +496,32 @@ static void allow_lds(K kernel, size_t bytes) {
     }
 }
 
+template <typename TP, typename TF, typename TA, int VAR, class GEO>
+static void tiled_launch(const TileJob<TP, TF, TA> &job, int chunk, size_t lds, int block, hipStream_t s) {
+    allow_lds(k_fused_tiled<TP, TF, TA, VAR, GEO>, lds);
+    hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, VAR, GEO>), dim3(8 * chunk), dim3(block), lds, s, job, chunk);
+}
+
+template <typename TP, typename TF, typename TA, class GEO>
+static void tiled_variant(const TileJob<TP, TF, TA> &job, int chunk, size_t lds, const LaunchCfg &cfg,
+                          hipStream_t s) {
+    switch (cfg.variant) {
+        case 1: tiled_launch<TP, TF, TA, 1, GEO>(job, chunk, lds, cfg.tile_block, s); break;
+        case 2: tiled_launch<TP, TF, TA, 2, GEO>(job, chunk, lds, cfg.tile_block, s); break;
+        case 3: tiled_launch<TP, TF, TA, 3, GEO>(job, chunk, lds, cfg.tile_block, s); break;
+        default: tiled_launch<TP, TF, TA, 0, GEO>(job, chunk, lds, cfg.tile_block, s);
+    }
+}
+
 template <typename TP, typename TF, typename TA>
 static void tiled_t(const spic_grid &g, const spic_params &prm, const spic_fields &f, const SpeciesWork &w,
                     const TileGeom &tg, const uint32_t *tile_off, const LaunchCfg &cfg, hipStream_t s) {
     const int chunk = (tg.ntiles + 7) / 8;
     const size_t lds = tiled_lds_bytes(tg, sizeof(TP) == 8 ? SPIC_F64 : SPIC_F32,
-                                       sizeof(TA) == 8 ? SPIC_F64 : SPIC_F32);
+                                       sizeof(TA) == 8 ? SPIC_F64 : SPIC_F32, cfg.variant, cfg.tile_block);
     const auto job = make_tile_job<TP, TF, TA>(g, prm, f, w, tg, tile_off);
-    switch (cfg.variant) {
-        case 1:
-            allow_lds(k_fused_tiled<TP, TF, TA, 1>, lds);
-            hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, 1>), dim3(8 * chunk), dim3(cfg.tile_block), lds, s, job,
-                               chunk);
-            break;
-        case 2:
-            allow_lds(k_fused_tiled<TP, TF, TA, 2>, lds);
-            hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, 2>), dim3(8 * chunk), dim3(cfg.tile_block), lds, s, job,
-                               chunk);
-            break;
-        case 3:
-            allow_lds(k_fused_tiled<TP, TF, TA, 3>, lds);
-            hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, 3>), dim3(8 * chunk), dim3(cfg.tile_block), lds, s, job,
-                               chunk);
-            break;
-        default:
-            allow_lds(k_fused_tiled<TP, TF, TA, 0>, lds);
-            hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, 0>), dim3(8 * chunk), dim3(cfg.tile_block), lds, s, job,
-                               chunk);
-    }
+    if (geo_is_default(tg) && cfg.fixed_geo) tiled_variant<TP, TF, TA, GeoDefault>(job, chunk, lds, cfg, s);
+    else tiled_variant<TP, TF, TA, GeoRuntime>(job, chunk, lds, cfg, s);
 }
 
 hipError_t launch_fused_tiled(const spic_grid &g, const spic_params &prm, const spic_fields &f,
@@ -466,9 +581,9 @@ void write_tile_job(int combo, void *dst, const spic_grid &g, const spic_params 
 // Workgroups of the persistent launch: resident workgroups per CU times
 // CUs, capped by the item count (and by max_groups when > 0).  Also allows
 // the LDS size; call before any stream capture.
-template <typename TP, typename TF, typename TA, int VAR>
+template <typename TP, typename TF, typename TA, int VAR, class GEO>
 static int worklist_groups_t(size_t lds, int block, int nitems, int max_groups) {
-    auto k = k_worklist<TP, TF, TA, VAR>;
+    auto k = k_worklist<TP, TF, TA, VAR, GEO>;
     allow_lds(k, lds);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, lds) != hipSuccess || per_cu < 1) per_cu = 1;
@@ -480,12 +595,20 @@ static int worklist_groups_t(size_t lds, int block, int nitems, int max_groups) 
     return groups < 1 ? 1 : groups;
 }
 
-int worklist_groups(int combo, int variant, size_t lds, int block, int nitems, int max_groups) {
-#define SPIC_WG(TP, TF, TA)                                                                           \
-    return variant == 3 ? worklist_groups_t<TP, TF, TA, 3>(lds, block, nitems, max_groups)           \
-           : variant == 2 ? worklist_groups_t<TP, TF, TA, 2>(lds, block, nitems, max_groups)         \
-           : variant == 1 ? worklist_groups_t<TP, TF, TA, 1>(lds, block, nitems, max_groups)         \
-                          : worklist_groups_t<TP, TF, TA, 0>(lds, block, nitems, max_groups)
+template <typename TP, typename TF, typename TA, class GEO>
+static int worklist_groups_v(int variant, size_t lds, int block, int nitems, int max_groups) {
+    switch (variant) {
+        case 1: return worklist_groups_t<TP, TF, TA, 1, GEO>(lds, block, nitems, max_groups);
+        case 2: return worklist_groups_t<TP, TF, TA, 2, GEO>(lds, block, nitems, max_groups);
+        case 3: return worklist_groups_t<TP, TF, TA, 3, GEO>(lds, block, nitems, max_groups);
+        default: return worklist_groups_t<TP, TF, TA, 0, GEO>(lds, block, nitems, max_groups);
+    }
+}
+
+int worklist_groups(int combo, bool fixed, int variant, size_t lds, int block, int nitems, int max_groups) {
+#define SPIC_WG(TP, TF, TA)                                                                  \
+    return fixed ? worklist_groups_v<TP, TF, TA, GeoDefault>(variant, lds, block, nitems, max_groups) \
+                 : worklist_groups_v<TP, TF, TA, GeoRuntime>(variant, lds, block, nitems, max_groups)
     switch (combo) {
         case 0: SPIC_WG(double, double, double);
         case 1: SPIC_WG(float, float, double);
@@ -496,22 +619,31 @@ int worklist_groups(int combo, int variant, size_t lds, int block, int nitems, i
 #undef SPIC_WG
 }
 
-template <typename TP, typename TF, typename TA, int VAR>
+template <typename TP, typename TF, typename TA, int VAR, class GEO>
 static hipError_t worklist_t(const void *jobs, const uint2 *items, int nitems, unsigned *counter, size_t lds,
                              int block, int groups, hipStream_t s) {
-    hipLaunchKernelGGL((k_worklist<TP, TF, TA, VAR>), dim3(groups), dim3(block), lds, s,
+    hipLaunchKernelGGL((k_worklist<TP, TF, TA, VAR, GEO>), dim3(groups), dim3(block), lds, s,
                        (const TileJob<TP, TF, TA> *)jobs, items, nitems, counter);
     return hipGetLastError();
 }
 
-hipError_t launch_worklist(int combo, int variant, const void *jobs, const uint2 *items, int nitems,
+template <typename TP, typename TF, typename TA, class GEO>
+static hipError_t worklist_v(int variant, const void *jobs, const uint2 *items, int nitems, unsigned *counter,
+                             size_t lds, int block, int groups, hipStream_t s) {
+    switch (variant) {
+        case 1: return worklist_t<TP, TF, TA, 1, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
+        case 2: return worklist_t<TP, TF, TA, 2, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
+        case 3: return worklist_t<TP, TF, TA, 3, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
+        default: return worklist_t<TP, TF, TA, 0, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
+    }
+}
+
+hipError_t launch_worklist(int combo, bool fixed, int variant, const void *jobs, const uint2 *items, int nitems,
                            unsigned *counter, size_t lds, int block, int groups, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-#define SPIC_WL(TP, TF, TA)                                                                                  \
-    return variant == 3 ? worklist_t<TP, TF, TA, 3>(jobs, items, nitems, counter, lds, block, groups, s)    \
-           : variant == 2 ? worklist_t<TP, TF, TA, 2>(jobs, items, nitems, counter, lds, block, groups, s)  \
-           : variant == 1 ? worklist_t<TP, TF, TA, 1>(jobs, items, nitems, counter, lds, block, groups, s)  \
-                          : worklist_t<TP, TF, TA, 0>(jobs, items, nitems, counter, lds, block, groups, s)
+#define SPIC_WL(TP, TF, TA)                                                                                   \
+    return fixed ? worklist_v<TP, TF, TA, GeoDefault>(variant, jobs, items, nitems, counter, lds, block, groups, s) \
+                 : worklist_v<TP, TF, TA, GeoRuntime>(variant, jobs, items, nitems, counter, lds, block, groups, s)
     switch (combo) {
         case 0: SPIC_WL(double, double, double);
         case 1: SPIC_WL(float, float, double);

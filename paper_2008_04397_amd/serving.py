@@ -10,8 +10,10 @@ Serial mode (the baseline): the same trace, one request at a time -- a
 request is submitted only after the previous one has completed.
 
 Latency of a request = completion time (results back in host memory) -
-arrival time.  Request inputs (fields on the device, particles in pinned
-host memory) are prepared before the arrival timestamp by the client.
+arrival time in the trace, so time spent queued behind earlier requests
+(and any delay of the client itself) counts in both modes.  The client
+prepares each request's inputs (fields on the device, particles in pinned
+host memory) just before waiting for its arrival time.
 """
 from __future__ import annotations
 
@@ -80,12 +82,11 @@ def serve(ctx: "spic.Context", requests: Sequence[W.Request], mode: str = "conti
 
     for k, req in enumerate(order):
         run = make_request_run(req, dtype, sort_every)
-        torch.cuda.current_stream().synchronize()  # the client's inputs are ready before it arrives
-        target = req.arrival * time_scale
-        while now() < target:
+        torch.cuda.current_stream().synchronize()
+        arrival = req.arrival * time_scale
+        while now() < arrival:
             poll_all()
             time.sleep(0.0005)
-        arrival = max(now(), target)
         if mode == "serial":
             while inflight:
                 poll_all(block=True)

@@ -182,3 +182,28 @@ def test_zero_step_run_and_errors(spic):
     run, _ = _run_of(spic, h, 1, host=True)
     assert spic.spic_batch_submit(tiny, [run], raw=True) == spic.SPIC_E_BUDGET
     tiny.close()
+
+
+def test_ticks_step_the_shortest_runs_first(spic):
+    """With tick_items = 1 every tick steps only the run with the least
+    remaining work: short runs submitted with a long one finish while the
+    long one has barely started, and all results still match the oracle."""
+    ctx = spic.Context(0)
+    ctx.set_option("tick_items", 1)
+    big = W.Harris(W.Grid(32, 16, 8), ppc=27, seed=21)
+    small = _boxes()[:2]
+    long_run, long_in = _run_of(spic, big, 60, dtype=torch.float32)
+    shorts = [_run_of(spic, h, 3) for h in small]
+    _say("case batch SRPT order: 1 long run (60 steps) + 2 short runs (3 steps), tick_items 1")
+    tickets = spic.spic_batch_submit(ctx, [long_run] + [r for r, _ in shorts])
+    for t in tickets[1:]:
+        spic.spic_wait(ctx, t)
+    assert not spic.spic_poll(ctx, tickets[0]), "the long run finished before the short ones"
+    spic.spic_wait(ctx, tickets[0])
+    for h, (run, sps) in zip(small, shorts):
+        st, ms = _oracle(h, sps, 3)
+        got = _host(run)
+        for s in range(4):
+            P.assert_state(got[s], st[s], h.grid, P.POS64, P.VEL64)
+            P.assert_moments(run.moments[s].cpu().numpy(), ms[s], P.MOM64)
+    ctx.close()

@@ -1,0 +1,87 @@
+"""Parity at the full size of the headline workload (128x64x32 cells, 64
+particles per cell x 4 species = 67,108,864 particles), in the launch
+configuration the benchmark times (tiled path, sort at step 0 and every 4
+steps), FP32 particles with FP64 moments and FP64 end to end.
+
+Checked, after 4 steps:
+  * a seeded 1/64 subsample of every species (by particle-id hash) against
+    the oracle's own 4 steps of those particles (fields are fixed, so each
+    trajectory is independent of the others);
+  * the moments of species 0 against the oracle's FP64 deposit of the
+    complete final GPU state of that species;
+  * for every species, the sums over nodes of rho, J and P against the
+    particle sums of q{1, v, v v} (exact up to rounding).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2008_04397_amd import workloads as W
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_full_size_sampled_parity(dtype):
+    from paper_2008_04397_amd import spic
+    h = W.harris_128x64x32()
+    g = h.grid
+    npdt = np.float32 if dtype == "f32" else np.float64
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    nsteps = 4
+    _say("case full size %s: generating 67M particles" % dtype)
+    f_np = {k: v.astype(npdt) for k, v in W.make_fields(h).items()}
+    f_dev = spic.to_device(f_np, tdt)
+    f64 = {k: v.astype(np.float64) for k, v in f_np.items()}
+    ctx = spic.Context(0)
+    dev, samples = [], []
+    for s in range(4):
+        sp = W.make_species(h, s, dtype=npdt)
+        m = W.subsample_mask(sp["id"], 64, seed=7)
+        samples.append(W.upcast({k: v[m] for k, v in sp.items()}))
+        dev.append(spic.to_device(sp, tdt))
+        del sp
+    moms = spic.moment_buffers(g, 4)
+    _say("case full size %s: %d GPU steps" % (dtype, nsteps))
+    for k in range(nsteps):
+        spic.spic_mover(ctx, g, spic.make_params(h.dt, h.c, h.niter, 4, k), f_dev, dev, h.qoms, moms)
+    torch.cuda.synchronize()
+    pos_tol, vel_tol = (P.POS64, P.VEL64) if dtype == "f64" else (None, None)
+    for s in range(4):
+        ids = dev[s]["id"].cpu().numpy()
+        mask = W.subsample_mask(ids, 64, seed=7)
+        got = {k: v.cpu().numpy()[mask] for k, v in dev[s].items()}
+        ora = samples[s]
+        for _ in range(nsteps):
+            ora = O.mover(g, h.dt, h.c, h.niter, h.qoms[s], f64, ora)
+        pe, ve = P.state_errors(got, ora, g)
+        _say("species %d (%d sampled): pos/L %.2e vel %.2e" % (s, mask.sum(), pe, ve))
+        if dtype == "f64":
+            assert pe <= pos_tol and ve <= vel_tol * P.vmax(ora)
+        else:
+            # 4 FP32 steps: rounding of order 4 * ulp(L) in position
+            assert pe <= 4e-5 and ve <= 4e-5 * max(P.vmax(ora), h.vths[s])
+        # moment sums over nodes equal the particle sums (any size)
+        full = {k: v.cpu().numpy().astype(np.float64) for k, v in dev[s].items() if k != "id"}
+        mm = moms[s].cpu().numpy()
+        u, v, w, q = full["u"], full["v"], full["w"], full["q"]
+        tot = [q, q * u, q * v, q * w, q * u * u, q * u * v, q * u * w, q * v * v, q * v * w, q * w * w]
+        # FP32 particles: weights and products rounded in FP32 (~1e-7 each)
+        stol = 1e-9 if dtype == "f64" else 1e-6
+        for c in range(10):
+            ref = tot[c].sum()
+            assert abs(mm[c].sum() - ref) <= stol * np.abs(tot[c]).sum(), (s, c)
+        if s == 0:
+            _say("species 0: oracle deposit of the full final state")
+            ref = O.deposit(g, full)
+            P.assert_moments(mm, ref, P.MOM64 if dtype == "f64" else P.MOM32)
+        del full
+    ctx.close()
