@@ -176,6 +176,11 @@ int spic_version(void);
  *   tile_variant   tiled-kernel variant (0..3; see spic_tiled.hip)
  *   fixed_geo      1 = kernels compiled for 4x4x4 tiles with halo 1 are used
  *                  when that tiling is in effect
+ *   bank_align     1 = LDS region layout that keeps a particle's bank pair
+ *                  when it drifts along the most-crossed axis (more LDS);
+ *                  0 = the most compact conflict-free layout (0/1)
+ *   sort_ordered   1 = a re-sort walks each tile of the current order in
+ *                  order, so ranks inside a cell keep that order (0/1)
  *   graph          batch engine: replay unchanged ticks as a hipGraph (0/1)
  *   batch_particles  batch engine: particles per streamed batch
  *   max_groups     batch engine: cap on workgroups of the persistent launch

@@ -1,6 +1,7 @@
 """Autotuner for the fused tiled path: picks the threads per workgroup, the
-kernel variant (LDS atomics, + field corners in registers, home-cell
-register accumulation), the halo and the sort
+kernel variant (LDS atomics; + field corners in registers; home-cell
+register accumulation with a queue of drifted particles; bank-balanced
+LDS deposit), the halo and the sort
 cadence by timing short runs of the actual workload, and caches the choice
 per (dtype, workload class) in a JSON file next to this module.
 
@@ -19,7 +20,8 @@ from typing import Dict, Iterable, Optional, Sequence
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 
-DEFAULT = {"tile_block": 256, "tile_variant": 0, "halo": 1, "tile_x": 4, "tile_y": 4, "tile_z": 4, "sort_every": 4}
+DEFAULT = {"tile_block": 256, "tile_variant": 0, "halo": 1, "tile_x": 4, "tile_y": 4, "tile_z": 4,
+           "bank_align": 1, "sort_ordered": 1, "sort_every": 4}
 
 
 def workload_class(dtype_name: str, grid, ppc: int) -> str:
@@ -56,13 +58,16 @@ def apply(ctx, cfg: Dict[str, int]):
 
 
 def candidates(quick: bool = True) -> Iterable[Dict[str, int]]:
+    """quick: the variants that have won on MI355X (plain LDS atomics and the
+    bank-balanced deposit); otherwise every variant, cadence and halo."""
     blocks = (256, 512)
-    variants = (0, 1, 2, 3)
+    variants = (0, 3) if quick else (0, 1, 2, 3)
     cadences = (2, 4, 8) if quick else (1, 2, 4, 8, 16)
     halos = (1,) if quick else (1, 2)
-    for blk, var, se, halo in itertools.product(blocks, variants, cadences, halos):
+    aligns = (1, 0)
+    for blk, var, se, halo, al in itertools.product(blocks, variants, cadences, halos, aligns):
         c = dict(DEFAULT)
-        c.update(tile_block=blk, tile_variant=var, sort_every=se, halo=halo)
+        c.update(tile_block=blk, tile_variant=var, sort_every=se, halo=halo, bank_align=al)
         yield c
 
 

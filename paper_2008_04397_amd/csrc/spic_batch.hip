@@ -149,7 +149,7 @@ struct BatchEngine {
     std::vector<uint64_t> graph_key;
 
     // tuning, read from the ctx options when the engine starts
-    int tile_block = 256, variant = 0, use_graph = 1, max_groups = 0, fixed_geo = 1;
+    int tile_block = 256, variant = 0, use_graph = 1, max_groups = 0, fixed_geo = 1, sort_ordered = 1;
     int64_t tick_items = 4096;  // 0: every active run steps at every tick
     int64_t batch_particles = (int64_t)1 << 26;
     LaunchCfg lcfg;
@@ -426,7 +426,7 @@ struct BatchEngine {
                 }
                 ensure_sort_scratch(sort_scratch_bytes(sl.dev.n, sl.dev.dtype, sl.dev.id != nullptr, r.tg));
                 hipError_t e = launch_sort(r.grid, work_of(sl.dev, nullptr), r.tg, sort_scr, sl.tile_off,
-                                           r.done_steps > 0, cs);
+                                           sort_ordered && r.done_steps > 0, cs);
                 if (e != hipSuccess) fail_run(r, e, "sort");
             }
             sorted_now = true;
@@ -777,7 +777,8 @@ void BatchEngine::stream_run(RunState &r) {
                     (void)hipStreamWaitEvent(cs, loaded[k], 0);
                     uint32_t *toff = (uint32_t *)tiles + bidx * (r.tg.ntiles + 1);
                     SpeciesWork w = work_of(dv, m);
-                    if (sort_due && (e = launch_sort(r.grid, w, r.tg, sort_scr, toff, step > 0, cs)) != hipSuccess)
+                    if (sort_due &&
+                        (e = launch_sort(r.grid, w, r.tg, sort_scr, toff, sort_ordered && step > 0, cs)) != hipSuccess)
                         fail_run(r, e, "batch sort");
                     LaunchCfg bcfg = lcfg;  // variant 0 when the configured one's LDS does not fit
                     if (tiled_lds_bytes(r.tg, w.dtype, w.acc_dtype, bcfg.variant, bcfg.tile_block) > ctx->lds_max)
@@ -831,6 +832,7 @@ int spic_ctx_s::batch_submit(const spic_run *runs, int32_t nruns, uint64_t *tick
         batch->tile_block = (int)opt("tile_block", 256);
         batch->variant = (int)opt("tile_variant", 0);
         batch->fixed_geo = (int)opt("fixed_geo", 1);
+        batch->sort_ordered = (int)opt("sort_ordered", 1);
         batch->use_graph = (int)opt("graph", 1);
         batch->batch_particles = opt("batch_particles", (int64_t)1 << 26);
         batch->max_groups = (int)opt("max_groups", 0);

@@ -33,7 +33,7 @@ std::string spic_ctx_s::layout_key(const spic_grid &g, const spic_species &s) co
 
 TileGeom spic_ctx_s::tile_geom(const spic_grid &g) const {
     return make_tile_geom(g, (int)opt("tile_x", 4), (int)opt("tile_y", 4), (int)opt("tile_z", 4),
-                          (int)opt("halo", 1));
+                          (int)opt("halo", 1), opt("bank_align", 1) != 0);
 }
 
 
@@ -41,31 +41,49 @@ int spic_ctx_s::mover(const spic_grid &g, const spic_params &p, const spic_field
                       int32_t nsp, spic_moment_array *mom, hipStream_t s) {
     const int64_t nn = (int64_t)g.nx * g.ny * g.nz;
     const LaunchCfg cfg = launch_cfg();
-    if (p.sort_every > 0 && p.step % p.sort_every == 0) {
-        int rc = sort(g, sp, nsp, s);
+    const bool sort_now = p.sort_every > 0 && p.step % p.sort_every == 0;
+    const bool generic_only = opt("path", 0) == 1;
+    TileGeom tg_now{};
+    size_t sort_need = 0;
+    if (sort_now) {
+        int rc = sort_prepare(g, sp, nsp, tg_now, sort_need);
         if (rc) return rc;
     }
-    const bool generic_only = opt("path", 0) == 1;
     for (int i = 0; i < nsp; ++i) {
         SpeciesWork w = work_of(sp[i], mom ? &mom[i] : nullptr);
         if (w.mom) {
             int rc = hip(launch_fill(w.mom, w.acc_dtype, 10 * nn, s), "zero moments");
             if (rc) return rc;
         }
-        const Layout *lay = nullptr;
+        // the tiled kernel runs for a sorted species whose region fits in LDS;
+        // a variant whose extra LDS does not fit falls back to variant 0
         LaunchCfg tcfg = cfg;
-        if (!generic_only) {
-            auto it = layouts.find(layout_key(g, sp[i]));
-            if (it != layouts.end() && tiled_fits(w.n, w.dtype)) {
-                // a variant whose extra LDS does not fit falls back to variant 0,
-                // a region that does not fit at all to the unsorted path
-                if (tiled_lds_bytes(it->second.tg, w.dtype, w.acc_dtype, tcfg.variant, tcfg.tile_block) > lds_max)
-                    tcfg.variant = 0;
-                if (tiled_lds_bytes(it->second.tg, w.dtype, w.acc_dtype, tcfg.variant, tcfg.tile_block) <= lds_max)
-                    lay = &it->second;
-            }
-        }
+        auto tiled_ok = [&](const TileGeom &tg) {
+            if (generic_only || !tiled_fits(w.n, w.dtype)) return false;
+            if (tiled_lds_bytes(tg, w.dtype, w.acc_dtype, tcfg.variant, tcfg.tile_block) > lds_max) tcfg.variant = 0;
+            return tiled_lds_bytes(tg, w.dtype, w.acc_dtype, tcfg.variant, tcfg.tile_block) <= lds_max;
+        };
         int rc;
+        if (sort_now) {
+            // sort this species; the tiled kernel then reads the reordered
+            // copy directly instead of it being copied back first
+            const bool tiled = tiled_ok(tg_now);
+            uint32_t *toff = nullptr;
+            SpeciesWork sorted;
+            if ((rc = sort_one(g, sp[i], tg_now, sort_need, s, &toff, tiled ? &sorted : nullptr))) return rc;
+            if (tiled) {
+                sorted.mom = w.mom;
+                sorted.acc_dtype = w.acc_dtype;
+                rc = hip(launch_fused_tiled(g, p, f, sorted, tg_now, toff, tcfg, s), "fused mover (tiled)");
+            } else {
+                rc = hip(launch_fused_generic(g, p, f, w, cfg, s), "fused mover");
+            }
+            if (rc) return rc;
+            continue;
+        }
+        const Layout *lay = nullptr;
+        auto it = layouts.find(layout_key(g, sp[i]));
+        if (it != layouts.end() && tiled_ok(it->second.tg)) lay = &it->second;
         if (lay) {
             void *toff = nullptr;
             if ((rc = reserve(lay->slot.c_str(), (size_t)(lay->tg.ntiles + 1) * 4, &toff))) return rc;
@@ -91,29 +109,45 @@ int spic_ctx_s::moments(const spic_grid &g, const spic_species *sp, int32_t nsp,
     return SPIC_OK;
 }
 
-int spic_ctx_s::sort(const spic_grid &g, spic_species *sp, int32_t nsp, hipStream_t s) {
-    const TileGeom tg = tile_geom(g);
+// Tile geometry of the next sort and the scratch it needs for every species.
+int spic_ctx_s::sort_prepare(const spic_grid &g, const spic_species *sp, int32_t nsp, TileGeom &tg, size_t &need) {
+    tg = tile_geom(g);
     if (tg.cells < 1 || tg.cells > 64 || tg.halo < 0 || tg.halo > 8)
         return fail(SPIC_E_ARG, "tile shape %dx%dx%d (halo %d): a tile holds 1..64 cells, halo 0..8", tg.tx, tg.ty,
                     tg.tz, tg.halo);
-    size_t need = 0;
+    need = 0;
     for (int i = 0; i < nsp; ++i) {
         if (sp[i].n >= ((int64_t)1 << 31)) return fail(SPIC_E_UNSUPPORTED, "species %d: sort needs n < 2^31", i);
         need = std::max(need, sort_scratch_bytes(sp[i].n, sp[i].dtype, sp[i].id != nullptr, tg));
     }
-    for (int i = 0; i < nsp; ++i) {
-        const std::string key = layout_key(g, sp[i]);
-        const std::string slot = "tileoff:" + key;
-        void *toff = nullptr, *scr = nullptr;
-        int rc;
-        if ((rc = reserve(slot.c_str(), (size_t)(tg.ntiles + 1) * 4, &toff))) return rc;
-        if ((rc = reserve("sort", need, &scr))) return rc;
-        SpeciesWork w = work_of(sp[i], nullptr);
-        auto it = layouts.find(key);
-        const bool prev = it != layouts.end() && same_tiling(it->second.tg, tg);
-        if ((rc = hip(launch_sort(g, w, tg, scr, (uint32_t *)toff, prev, s), "sort"))) return rc;
-        layouts[key] = Layout{tg, slot};
-    }
     return SPIC_OK;
 }
 
+// Sort one species and record its layout.  With sorted_out the reordered
+// particles stay in the shared scratch for the kernel launched next.
+int spic_ctx_s::sort_one(const spic_grid &g, const spic_species &sp, const TileGeom &tg, size_t need,
+                         hipStream_t s, uint32_t **toff_out, SpeciesWork *sorted_out) {
+    const std::string key = layout_key(g, sp);
+    const std::string slot = "tileoff:" + key;
+    void *toff = nullptr, *scr = nullptr;
+    int rc;
+    if ((rc = reserve(slot.c_str(), (size_t)(tg.ntiles + 1) * 4, &toff))) return rc;
+    if ((rc = reserve("sort", need, &scr))) return rc;
+    SpeciesWork w = work_of(sp, nullptr);
+    auto it = layouts.find(key);
+    const bool prev = opt("sort_ordered", 1) && it != layouts.end() && same_tiling(it->second.tg, tg);
+    if ((rc = hip(launch_sort(g, w, tg, scr, (uint32_t *)toff, prev, s, sorted_out), "sort"))) return rc;
+    layouts[key] = Layout{tg, slot};
+    if (toff_out) *toff_out = (uint32_t *)toff;
+    return SPIC_OK;
+}
+
+int spic_ctx_s::sort(const spic_grid &g, spic_species *sp, int32_t nsp, hipStream_t s) {
+    TileGeom tg;
+    size_t need = 0;
+    int rc = sort_prepare(g, sp, nsp, tg, need);
+    if (rc) return rc;
+    for (int i = 0; i < nsp; ++i)
+        if ((rc = sort_one(g, sp[i], tg, need, s, nullptr, nullptr))) return rc;
+    return SPIC_OK;
+}

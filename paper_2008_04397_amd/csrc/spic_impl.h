@@ -47,6 +47,11 @@ struct SpeciesWork {
     int64_t *id;
     void *mom;          // NULL or [10][nodes]
     int acc_dtype;
+    // when set, the tiled kernel reads the particles from src (the sort's
+    // reordered copy) and writes all of them, q and id included, to a / id
+    bool from_src = false;
+    void *src[7] = {};
+    int64_t *src_id = nullptr;
 };
 
 struct LaunchCfg {
@@ -65,65 +70,94 @@ struct TileGeom {
     int tx, ty, tz, cells;
     int ntx, nty, ntz, ntiles;
     int halo, rx, ry, rz;
-    int ryp, rzp, rnp, pad;  // padded LDS extents (bank spread) and slots rx*ryp*rzp
+    // Axis roles (0 x, 1 y, 2 z): a tile's cells are numbered with `slow`
+    // slowest and `fast` fastest, and the region's LDS slot of a node with
+    // region coordinates (a, b, c) is a*sx + b*sy + c*sz.
+    int slow, mid, fast;
+    int sx, sy, sz, rnp;  // slot strides and slots (padded for bank spread)
 };
 
-// Padded LDS extents RYP >= ry, RZP >= rz of a region: the lower corners of
-// a full tile's cells (one cell per lane) should hit the 16 pairs of 4-byte
-// banks as evenly as possible, for every corner offset; among the most even
-// paddings the one with the fewest slots wins.  constexpr so that kernels
-// specialised for one tiling use the same layout as the host.
-struct RegionPadding {
-    int ryp, rzp;
+// LDS bank spread of a region layout.  A wave deposits with one lane per
+// cell of a tile (rank-major order), and an FP64 LDS access by 16
+// consecutive lanes is conflict free when their slots are distinct modulo
+// 16 (16 pairs of 4-byte banks).  The fast and middle extents are padded to
+// P_fast >= r_fast, P_mid >= r_mid so that (1) every group of 16 consecutive
+// cells hits the 16 pairs as evenly as possible, for every corner, (2)
+// preferably the slow stride P_mid * P_fast is a multiple of 16, so that a
+// particle that drifted one cell along the slow axis keeps its bank pair,
+// and (3) the region has the fewest slots (without (2) when prefer_align is
+// false: the compact layout keeps two FP64 workgroups per CU).  constexpr so
+// that kernels specialised for one tiling use the same layout as the host.
+struct RegionLayout {
+    int sx, sy, sz, rnp;
 };
 
-constexpr RegionPadding region_padding(int tx, int ty, int tz, int halo) {
-    const int rx = tx + 2 * halo + 1, ry = ty + 2 * halo + 1, rz = tz + 2 * halo + 1;
-    int best_w = 1 << 30, best_n = 1 << 30, bry = ry, brz = rz;
-    for (int ryp = ry; ryp < ry + 9; ++ryp)
-        for (int rzp = rz; rzp < rz + 9; ++rzp) {
-            const int sx = ryp * rzp, sy = rzp;
+constexpr RegionLayout region_layout(int tx, int ty, int tz, int halo, int slow, int mid, int fast,
+                                     bool prefer_align = true) {
+    const int t[3] = {tx, ty, tz};
+    const int r[3] = {tx + 2 * halo + 1, ty + 2 * halo + 1, tz + 2 * halo + 1};
+    const int cells = tx * ty * tz;
+    int best_w = 1 << 30, best_a = 2, best_n = 1 << 30, bpm = r[mid], bpf = r[fast];
+    for (int pm = r[mid]; pm < r[mid] + 9; ++pm)
+        for (int pf = r[fast]; pf < r[fast] + 9; ++pf) {
+            int st[3] = {0, 0, 0};
+            st[fast] = 1;
+            st[mid] = pf;
+            st[slow] = pm * pf;
             int worst = 0;
-            for (int c = 0; c < 8; ++c) {
-                int cnt[16] = {};
-                for (int li = 0; li < tx; ++li)
-                    for (int lj = 0; lj < ty; ++lj)
-                        for (int lk = 0; lk < tz; ++lk) {
-                            const int slot = (li + halo + (c & 1)) * sx + (lj + halo + ((c >> 1) & 1)) * sy +
-                                             (lk + halo + (c >> 2));
-                            const int v = ++cnt[slot & 15];
-                            worst = v > worst ? v : worst;
-                        }
-            }
-            const int slots = rx * sx;
-            if (worst < best_w || (worst == best_w && slots < best_n)) {
+            for (int g0 = 0; g0 < cells; g0 += 16)
+                for (int k = 0; k < 8; ++k) {
+                    int cnt[16] = {};
+                    for (int l = g0; l < g0 + 16 && l < cells; ++l) {
+                        // local cell l -> (slow, mid, fast) coordinates
+                        const int cf = l % t[fast], cm = (l / t[fast]) % t[mid], cs = l / (t[fast] * t[mid]);
+                        int c3[3] = {0, 0, 0};
+                        c3[slow] = cs;
+                        c3[mid] = cm;
+                        c3[fast] = cf;
+                        int slot = 0;
+                        for (int d = 0; d < 3; ++d) slot += (c3[d] + halo + ((k >> d) & 1)) * st[d];
+                        const int v = ++cnt[slot & 15];
+                        worst = v > worst ? v : worst;
+                    }
+                }
+            const int align = (!prefer_align || (pm * pf) % 16 == 0) ? 0 : 1;
+            const int slots = r[slow] * pm * pf;
+            if (worst < best_w || (worst == best_w && (align < best_a || (align == best_a && slots < best_n)))) {
                 best_w = worst;
+                best_a = align;
                 best_n = slots;
-                bry = ryp;
-                brz = rzp;
+                bpm = pm;
+                bpf = pf;
             }
         }
-    return RegionPadding{bry, brz};
+    int st[3] = {0, 0, 0};
+    st[fast] = 1;
+    st[mid] = bpf;
+    st[slow] = bpm * bpf;
+    return RegionLayout{st[0], st[1], st[2], r[slow] * bpm * bpf};
 }
 
 // Region geometry known at compile time (the default tiling): LDS offsets of
 // corners and moment components fold into instruction immediates.
 struct GeoRuntime {
     static constexpr bool fixed = false;
-    static constexpr int tx = 0, ty = 0, tz = 0, halo = 0, rx = 0, ry = 0, rz = 0, ryp = 0, rzp = 0, rnp = 0;
+    static constexpr int tx = 0, ty = 0, tz = 0, halo = 0, rx = 0, ry = 0, rz = 0, slow = 0, mid = 0, fast = 0,
+                         sx = 0, sy = 0, sz = 0, rnp = 0;
 };
 
-template <int TX, int TY, int TZ, int HALO>
+template <int TX, int TY, int TZ, int HALO, int SLOW, int MID, int FAST>
 struct GeoFixed {
     static constexpr bool fixed = true;
-    static constexpr int tx = TX, ty = TY, tz = TZ, halo = HALO;
+    static constexpr int tx = TX, ty = TY, tz = TZ, halo = HALO, slow = SLOW, mid = MID, fast = FAST;
     static constexpr int rx = TX + 2 * HALO + 1, ry = TY + 2 * HALO + 1, rz = TZ + 2 * HALO + 1;
-    static constexpr int ryp = region_padding(TX, TY, TZ, HALO).ryp;
-    static constexpr int rzp = region_padding(TX, TY, TZ, HALO).rzp;
-    static constexpr int rnp = rx * ryp * rzp;
+    static constexpr RegionLayout lay = region_layout(TX, TY, TZ, HALO, SLOW, MID, FAST);
+    static constexpr int sx = lay.sx, sy = lay.sy, sz = lay.sz, rnp = lay.rnp;
 };
 
-using GeoDefault = GeoFixed<4, 4, 4, 1>;
+// 4x4x4 tiles, halo 1, z slowest (the Harris boxes have their finest cells
+// along z, which particles cross most often)
+using GeoDefault = GeoFixed<4, 4, 4, 1, 2, 0, 1>;
 
 // The tiled kernels address particle arrays with 32-bit byte offsets.
 inline bool tiled_fits(int64_t n, int dtype) {
@@ -132,8 +166,9 @@ inline bool tiled_fits(int64_t n, int dtype) {
 
 inline bool geo_is_default(const TileGeom &t) {
     return t.tx == GeoDefault::tx && t.ty == GeoDefault::ty && t.tz == GeoDefault::tz &&
-           t.halo == GeoDefault::halo && t.ryp == GeoDefault::ryp && t.rzp == GeoDefault::rzp &&
-           t.rnp == GeoDefault::rnp;
+           t.halo == GeoDefault::halo && t.slow == GeoDefault::slow && t.mid == GeoDefault::mid &&
+           t.fast == GeoDefault::fast && t.sx == GeoDefault::sx && t.sy == GeoDefault::sy &&
+           t.sz == GeoDefault::sz && t.rnp == GeoDefault::rnp;
 }
 
 template <typename T>
@@ -189,11 +224,13 @@ struct TileJob {
     GridT<TA> ga;
     FieldPtrs<TF> f;
     MoveT<TP> mv;
-    PartPtrs<TP> p;
+    PartPtrs<TP> p;   // particles written
+    PartPtrs<TP> in;  // particles read (p, or the sort's reordered copy)
     TA *mom;
     const uint32_t *tile_off;
     TileGeom tg;
-    int nn, pad;
+    int nn;
+    int copy_rest;    // in != p: also write q (and id) to p
 };
 
 template <typename TP, typename TF, typename TA>
@@ -205,11 +242,18 @@ inline TileJob<TP, TF, TA> make_tile_job(const spic_grid &g, const spic_params &
     J.f = field_ptrs<TF>(f);
     J.mv = make_move<TP>(prm, w.qom);
     J.p = part_ptrs<TP>(w);
+    J.in = J.p;
+    J.copy_rest = 0;
+    if (w.from_src) {
+        J.in.x = (TP *)w.src[0]; J.in.y = (TP *)w.src[1]; J.in.z = (TP *)w.src[2];
+        J.in.u = (TP *)w.src[3]; J.in.v = (TP *)w.src[4]; J.in.w = (TP *)w.src[5]; J.in.q = (TP *)w.src[6];
+        J.in.id = w.src_id;
+        J.copy_rest = 1;
+    }
     J.mom = (TA *)w.mom;
     J.tile_off = tile_off;
     J.tg = tg;
     J.nn = g.nx * g.ny * g.nz;
-    J.pad = 0;
     return J;
 }
 
@@ -228,16 +272,19 @@ hipError_t launch_deposit_generic(const spic_grid &g, const SpeciesWork &w, cons
                                   hipStream_t s);
 
 // Sort (spic_sort.hip).
-TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo);
+TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo, bool align = true);
 size_t sort_scratch_bytes(int64_t n, int dtype, bool with_id, const TileGeom &tg);
 // prev: tile_off already holds the per-tile ranges of the particles'
 // current order (an earlier sort with the same tiles and n); the key pass
-// then walks tiles in that order, which keeps the scatter's writes local.
+// then walks each tile in that order, which keeps the gather's reads local.
+// sorted_out: when not NULL the reordered particles stay in the scratch and
+// are not copied back; *sorted_out receives w with from_src/src set, for a
+// tiled launch that reads them (and writes every array of w) right after.
 hipError_t launch_sort(const spic_grid &g, const SpeciesWork &w, const TileGeom &tg, void *scratch,
-                       uint32_t *tile_off, bool prev, hipStream_t s);
+                       uint32_t *tile_off, bool prev, hipStream_t s, SpeciesWork *sorted_out = nullptr);
 inline bool same_tiling(const TileGeom &a, const TileGeom &b) {
-    return a.tx == b.tx && a.ty == b.ty && a.tz == b.tz && a.halo == b.halo && a.ntiles == b.ntiles &&
-           a.ntx == b.ntx && a.nty == b.nty && a.ntz == b.ntz;
+    return a.tx == b.tx && a.ty == b.ty && a.tz == b.tz && a.ntx == b.ntx && a.nty == b.nty && a.ntz == b.ntz &&
+           a.slow == b.slow && a.mid == b.mid && a.fast == b.fast;
 }
 
 // Tiled fused path (spic_tiled.hip): one workgroup per tile of a sorted

@@ -189,8 +189,10 @@ static const char *const kOptionNames[] = {
     "halo",         // cells of halo staged around a tile
     "lds_max",      // read only: LDS bytes per workgroup on the device
     "tile_variant", // tiled kernel: 0 LDS atomics, 1 + field corners in registers, 2 home-cell registers,
-                    // 3 LDS atomics with lane-rotated corners
+                    // 3 bank-balanced LDS deposit
     "fixed_geo",    // tiled kernel: 1 = compile-time region geometry for 4x4x4 tiles, halo 1
+    "sort_ordered", // sort: 1 = ranks follow the previous order (a sorted species' tiles walked in order)
+    "bank_align",   // tiled kernel: 1 = LDS layout whose slow-axis stride keeps bank pairs (more slots)
     "graph",        // batch engine: 1 = replay unchanged ticks as a hipGraph
     "batch_particles",  // batch engine: particles per streamed batch (upper bound)
     "max_groups",   // batch engine: cap on workgroups of the persistent launch (0 = occupancy)
@@ -282,13 +284,14 @@ int spic_set_option(spic_ctx ctx, const char *key, int64_t value) {
                 (value < 1 || value > 64))
                 return ctx->fail(SPIC_E_ARG, "tile sizes must be in [1, 64]");
             if (!strcmp(key, "tile_variant") && (value < 0 || value > 3))
-                return ctx->fail(SPIC_E_ARG, "tile_variant must be 0, 1, 2 or 3");
+                return ctx->fail(SPIC_E_ARG, "tile_variant must be in 0..3");
             if (!strcmp(key, "batch_particles") && (value < 1024 || value > ((int64_t)1 << 29)))
                 return ctx->fail(SPIC_E_ARG, "batch_particles must be in [1024, 2^29]");
             if (!strcmp(key, "tick_items") && (value < 0 || value > ((int64_t)1 << 30)))
                 return ctx->fail(SPIC_E_ARG, "tick_items must be in [0, 2^30]");
-            if (!strcmp(key, "fixed_geo") && (value < 0 || value > 1))
-                return ctx->fail(SPIC_E_ARG, "fixed_geo must be 0 or 1");
+            if ((!strcmp(key, "fixed_geo") || !strcmp(key, "sort_ordered") || !strcmp(key, "bank_align")) &&
+                (value < 0 || value > 1))
+                return ctx->fail(SPIC_E_ARG, "%s must be 0 or 1", key);
             if (!strcmp(key, "halo") && (value < 0 || value > 8))
                 return ctx->fail(SPIC_E_ARG, "halo must be in [0, 8]");
             if (!strcmp(key, "lds_max")) return ctx->fail(SPIC_E_ARG, "lds_max is read only");

@@ -13,11 +13,14 @@
 //
 // Passes (all on the caller's stream):
 //   1 key:     cell key of every particle; rank within its cell from a
-//              wave-aggregated atomic histogram
+//              wave-aggregated atomic histogram, or, for particles still in
+//              an earlier sort's layout, from per-tile LDS counters in order
 //   2 scan:    exclusive prefix of the per-key counts (three kernels)
 //   3 tables:  per tile and rank, the start of the rank block and the mask
 //              of cells holding a particle of that rank
-//   4 scatter: particle -> scratch at its rank-major slot; copy back
+//   4 slots:   rank-major slot of every particle (an index scatter), then a
+//              gather of the particles into slot order in scratch; copy
+//              back (or the fused kernel reads the scratch directly)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,11 +38,14 @@ __device__ __forceinline__ int sort_locate(T s, T L, T invL, T invd, int n) {
     return plocate(s, L, invL, invd, n, xi);
 }
 
+// Tile (flat in x, y, z order) and local cell (slow, mid, fast order) of a
+// cell, as one key.
 __device__ __forceinline__ uint32_t tile_key(const TileGeom &tg, int i, int j, int k) {
     const int tx = i / tg.tx, ty = j / tg.ty, tz = k / tg.tz;
-    const int li = i - tx * tg.tx, lj = j - ty * tg.ty, lk = k - tz * tg.tz;
+    const int l[3] = {i - tx * tg.tx, j - ty * tg.ty, k - tz * tg.tz};
+    const int t[3] = {tg.tx, tg.ty, tg.tz};
     const uint32_t tile = (uint32_t)((tx * tg.nty + ty) * tg.ntz + tz);
-    return tile * (uint32_t)tg.cells + (uint32_t)((li * tg.ty + lj) * tg.tz + lk);
+    return tile * (uint32_t)tg.cells + (uint32_t)((l[tg.slow] * t[tg.mid] + l[tg.mid]) * t[tg.fast] + l[tg.fast]);
 }
 
 // Key of every particle and its rank inside its key.  Lanes holding the
@@ -80,28 +86,49 @@ k_sort_keys(GridT<T> g, TileGeom tg, const T *__restrict__ x, const T *__restric
     }
 }
 
-// Keys and ranks of particles that are still in the tile layout of an
-// earlier sort with the same tiles (prev_off = that sort's per-tile ranges,
-// a partition of [0, n)).  One workgroup walks one tile's range in order, so
-// a cell's ranks follow the earlier order up to the few waves in flight, and
-// the scatter writes nearly contiguous runs instead of one scattered value
-// per lane.  Correct for any partition of [0, n): only locality depends on
-// the particles still being near their earlier tiles.
+// Keys and ranks of particles that are still laid out by an earlier sort
+// with the same tiles (prev_off = that sort's per-tile ranges, a partition
+// of [0, n)).  One workgroup walks one tile's range in order.  Particles
+// whose cell is in that tile are ranked with LDS counters (own[] at the
+// end), so a cell's ranks follow the earlier order up to the waves in
+// flight; particles that arrived from another tile's range are ranked on a
+// global counter imm[] and flagged, their final rank being own + that rank
+// (k_sort_slots).  The gather below then reads long runs for the particles
+// that stayed.  Correct for any partition of [0, n).
+constexpr uint32_t kImmigrant = 0x80000000u;
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_sort_keys_tiled(GridT<T> g, TileGeom tg, const T *__restrict__ x, const T *__restrict__ y,
-                  const T *__restrict__ z, const uint32_t *__restrict__ prev_off, uint32_t *__restrict__ counts,
-                  uint2 *__restrict__ keyrank) {
+                  const T *__restrict__ z, const uint32_t *__restrict__ prev_off, uint32_t *__restrict__ own,
+                  uint32_t *__restrict__ imm, uint2 *__restrict__ keyrank) {
+    __shared__ uint32_t lc[64];
     for (int t = blockIdx.x; t < tg.ntiles; t += gridDim.x) {
+        if (threadIdx.x < 64) lc[threadIdx.x] = 0u;
+        __syncthreads();
         const uint32_t b = prev_off[t], e = prev_off[t + 1];
+        const uint32_t key0 = (uint32_t)t * (uint32_t)tg.cells;
         for (uint32_t p = b + threadIdx.x; p < e; p += blockDim.x) {
             const int i = sort_locate(x[p], g.L[0], g.invL[0], g.invd[0], g.nx);
             const int j = sort_locate(y[p], g.L[1], g.invL[1], g.invd[1], g.ny);
             const int k = sort_locate(z[p], g.L[2], g.invL[2], g.invd[2], g.nz);
             const uint32_t key = tile_key(tg, i, j, k);
-            keyrank[p] = make_uint2(key, atomicAdd(counts + key, 1u));
+            uint32_t r;
+            if (key - key0 < (uint32_t)tg.cells) r = atomicAdd(&lc[key - key0], 1u);
+            else r = atomicAdd(imm + key, 1u) | kImmigrant;
+            keyrank[p] = make_uint2(key, r);
         }
+        __syncthreads();
+        if (threadIdx.x < tg.cells) own[key0 + threadIdx.x] = lc[threadIdx.x];
+        __syncthreads();
     }
+}
+
+// counts = own + imm per key (imm becomes the total; own is kept for the
+// immigrants' final ranks).
+__global__ void k_sort_counts(const uint32_t *__restrict__ own, uint32_t *__restrict__ imm, int64_t nkeys) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nkeys; k += (int64_t)gridDim.x * blockDim.x)
+        imm[k] += own[k];
 }
 
 // ----------------------------------------------------------------- scan
@@ -240,19 +267,36 @@ k_tile_table(const uint32_t *__restrict__ offsets, TileGeom tg, const uint32_t *
     }
 }
 
-// Scatter every particle straight to its rank-major slot in scratch.
-template <typename T>
+// Rank-major slot of every particle: srcidx[slot] = particle.  Only this
+// 4-byte index is written scattered; a rank change by one moves a particle
+// by a whole rank block, so after a few steps nearly every lane of a wave
+// writes a different cache line.
 __global__ void __launch_bounds__(256)
-k_sort_scatter_rm(PartPtrs<T> src, PartPtrs<T> dst, int64_t n, const uint2 *__restrict__ keyrank,
-                  const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ tab_off,
-                  const uint4 *__restrict__ tab, int cells) {
+k_sort_slots(int64_t n, const uint2 *__restrict__ keyrank, const uint32_t *__restrict__ offsets,
+             const uint32_t *__restrict__ tab_off, const uint4 *__restrict__ tab, int cells,
+             const uint32_t *__restrict__ own, uint32_t *__restrict__ srcidx) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
         const uint2 kr = keyrank[p];
         const uint32_t t = kr.x / (uint32_t)cells, l = kr.x - t * (uint32_t)cells;
-        const uint4 e = tab[tab_off[t] + kr.y];
+        // ranked in the tiled key pass as an immigrant: after the cell's own particles
+        const uint32_t rank = (own && (kr.y & kImmigrant)) ? own[kr.x] + (kr.y & ~kImmigrant) : kr.y;
+        const uint4 e = tab[tab_off[t] + rank];
         const uint64_t m = ((uint64_t)e.z << 32) | e.y;
         const uint64_t below = (l == 0) ? 0ull : (m & ((1ull << l) - 1));
         const uint32_t d = offsets[t * (uint32_t)cells] + e.x + (uint32_t)__popcll(below);
+        srcidx[d] = (uint32_t)p;
+    }
+}
+
+// Gather the particles into slot order: writes are coalesced; the reads
+// are scattered over the tile's earlier range and its neighbours' (L2
+// resident) wherever particles changed cell since the last sort.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sort_gather(PartPtrs<T> src, PartPtrs<T> dst, int64_t n, const uint32_t *__restrict__ srcidx) {
+    for (int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t p = srcidx[d];
+        if (p >= (uint64_t)n) continue;  // never taken: the slots are a permutation of [0, n)
         dst.x[d] = src.x[p]; dst.y[d] = src.y[p]; dst.z[d] = src.z[p];
         dst.u[d] = src.u[p]; dst.v[d] = src.v[p]; dst.w[d] = src.w[p];
         dst.q[d] = src.q[p];
@@ -279,7 +323,7 @@ __global__ void k_tile_offsets(const uint32_t *__restrict__ offsets, TileGeom tg
 
 // ------------------------------------------------------------------ host
 
-TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo) {
+TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo, bool align) {
     TileGeom t;
     t.tx = tx; t.ty = ty; t.tz = tz;
     t.cells = tx * ty * tz;
@@ -291,12 +335,20 @@ TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo) {
     t.rx = tx + 2 * halo + 1;
     t.ry = ty + 2 * halo + 1;
     t.rz = tz + 2 * halo + 1;
-    const RegionPadding pad = region_padding(tx, ty, tz, halo);
-    const int bry = pad.ryp, brz = pad.rzp;
-    t.ryp = bry;
-    t.rzp = brz;
-    t.rnp = t.rx * bry * brz;
-    t.pad = 0;
+    // the slow axis is the one with the finest cells (crossed most often by
+    // particles moving alike in every direction); ties go to z, then y
+    const double d[3] = {g.Lx / g.nx, g.Ly / g.ny, g.Lz / g.nz};
+    int slow = 2;
+    if (d[1] < d[slow]) slow = 1;
+    if (d[0] < d[slow]) slow = 0;
+    t.slow = slow;
+    t.mid = slow == 0 ? 1 : 0;
+    t.fast = slow == 2 ? 1 : 2;
+    const RegionLayout lay = region_layout(tx, ty, tz, halo, t.slow, t.mid, t.fast, align);
+    t.sx = lay.sx;
+    t.sy = lay.sy;
+    t.sz = lay.sz;
+    t.rnp = lay.rnp;
     return t;
 }
 
@@ -306,9 +358,11 @@ size_t sort_scratch_bytes(int64_t n, int dtype, bool with_id, const TileGeom &tg
     const size_t sp = dtype == SPIC_F64 ? 8 : 4;
     size_t b = 0;
     b += (size_t)nkeys * 4 + 256;          // counts
+    b += (size_t)nkeys * 4 + 256;          // counts of a tile's own particles (ordered key pass)
     b += (size_t)(nkeys + 1) * 4 + 256;    // offsets
     b += (size_t)nparts * 4 + 256;         // partials
     b += (size_t)n * 8 + 256;              // key/rank
+    b += (size_t)n * 4 + 256;              // source index of every slot
     b += (size_t)(tg.ntiles + 1) * 4 * 2 + 512;   // maxc, tab_off
     b += ((size_t)n + tg.ntiles) * 16 + 256;      // rank tables (sum of max counts <= n)
     b += (size_t)((tg.ntiles + SCAN_CHUNK) / SCAN_CHUNK) * 4 + 256;  // partials of the tile scan
@@ -325,15 +379,17 @@ static inline char *carve(char *&cur, size_t bytes) {
 
 template <typename T>
 static hipError_t sort_t(const spic_grid &g, const SpeciesWork &w, const TileGeom &tg, void *scratch,
-                         uint32_t *tile_off, bool prev, hipStream_t s) {
+                         uint32_t *tile_off, bool prev, hipStream_t s, SpeciesWork *sorted_out) {
     const int64_t n = w.n;
     const int64_t nkeys = (int64_t)tg.ntiles * tg.cells;
     const int nparts = (int)((nkeys + SCAN_CHUNK - 1) / SCAN_CHUNK);
     char *cur = (char *)scratch;
     uint32_t *counts = (uint32_t *)carve(cur, (size_t)nkeys * 4);
+    uint32_t *own = (uint32_t *)carve(cur, (size_t)nkeys * 4);
     uint32_t *offsets = (uint32_t *)carve(cur, (size_t)(nkeys + 1) * 4);
     uint32_t *partial = (uint32_t *)carve(cur, (size_t)nparts * 4);
     uint2 *keyrank = (uint2 *)carve(cur, (size_t)n * 8);
+    uint32_t *srcidx = (uint32_t *)carve(cur, (size_t)n * 4);
     uint32_t *maxc = (uint32_t *)carve(cur, (size_t)(tg.ntiles + 1) * 4);
     uint32_t *tab_off = (uint32_t *)carve(cur, (size_t)(tg.ntiles + 1) * 4);
     uint4 *tab = (uint4 *)carve(cur, ((size_t)n + tg.ntiles) * 16);
@@ -352,12 +408,16 @@ static hipError_t sort_t(const spic_grid &g, const SpeciesWork &w, const TileGeo
     hipError_t e;
     if ((e = launch_zero32(counts, nkeys, s)) != hipSuccess) return e;
     const int gp = (int)std::min<int64_t>((n + 255) / 256, 1 << 16);
-    if (prev)  // tile_off still holds the ranges of the current order
-        hipLaunchKernelGGL((k_sort_keys_tiled<T>), dim3(std::min(tg.ntiles, 1 << 16)), dim3(256), 0, s,
-                           make_grid_t<T>(g), tg, src.x, src.y, src.z, (const uint32_t *)tile_off, counts, keyrank);
-    else
+    if (prev) {  // tile_off still holds the ranges of the current order
+        hipLaunchKernelGGL((k_sort_keys_tiled<T>), dim3(std::min(tg.ntiles, 1 << 20)), dim3(256), 0, s,
+                           make_grid_t<T>(g), tg, src.x, src.y, src.z, (const uint32_t *)tile_off, own, counts,
+                           keyrank);
+        const int gk = (int)std::min<int64_t>((nkeys + 255) / 256, 1 << 16);
+        hipLaunchKernelGGL(k_sort_counts, dim3(gk > 0 ? gk : 1), dim3(256), 0, s, own, counts, nkeys);
+    } else {
         hipLaunchKernelGGL((k_sort_keys<T>), dim3(gp > 0 ? gp : 1), dim3(256), 0, s, make_grid_t<T>(g), tg, src.x,
                            src.y, src.z, n, counts, keyrank);
+    }
     hipLaunchKernelGGL(k_scan_partials, dim3(nparts), dim3(SCAN_BLOCK), 0, s, counts, nkeys, partial);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, partial, nparts);
     hipLaunchKernelGGL(k_scan_apply, dim3(nparts), dim3(SCAN_BLOCK), 0, s, counts, nkeys, partial, offsets);
@@ -368,21 +428,32 @@ static hipError_t sort_t(const spic_grid &g, const SpeciesWork &w, const TileGeo
     hipLaunchKernelGGL(k_scan_apply, dim3(tparts), dim3(SCAN_BLOCK), 0, s, maxc, (int64_t)tg.ntiles, tpartial,
                        tab_off);
     hipLaunchKernelGGL(k_tile_table, dim3(tg.ntiles), dim3(64), 0, s, offsets, tg, tab_off, tab);
-    hipLaunchKernelGGL((k_sort_scatter_rm<T>), dim3(gp > 0 ? gp : 1), dim3(256), 0, s, src, tmp, n, keyrank,
-                       offsets, tab_off, tab, tg.cells);
-    hipLaunchKernelGGL((k_copy_parts<T>), dim3(gp > 0 ? gp : 1), dim3(256), 0, s, tmp, src, n);
+    hipLaunchKernelGGL(k_sort_slots, dim3(gp > 0 ? gp : 1), dim3(256), 0, s, n, keyrank, offsets, tab_off, tab,
+                       tg.cells, prev ? (const uint32_t *)own : nullptr, srcidx);
+    hipLaunchKernelGGL((k_sort_gather<T>), dim3(gp > 0 ? gp : 1), dim3(256), 0, s, src, tmp, n, srcidx);
+    if (sorted_out) {  // the next kernel reads the reordered copy and writes w's arrays
+        *sorted_out = w;
+        sorted_out->from_src = true;
+        sorted_out->src[0] = tmp.x; sorted_out->src[1] = tmp.y; sorted_out->src[2] = tmp.z;
+        sorted_out->src[3] = tmp.u; sorted_out->src[4] = tmp.v; sorted_out->src[5] = tmp.w;
+        sorted_out->src[6] = tmp.q;
+        sorted_out->src_id = tmp.id;
+    } else {
+        hipLaunchKernelGGL((k_copy_parts<T>), dim3(gp > 0 ? gp : 1), dim3(256), 0, s, tmp, src, n);
+    }
     hipLaunchKernelGGL(k_tile_offsets, dim3((tg.ntiles + 1 + 255) / 256), dim3(256), 0, s, offsets, tg, tg.ntiles,
                        tile_off);
     return hipGetLastError();
 }
 
 hipError_t launch_sort(const spic_grid &g, const SpeciesWork &w, const TileGeom &tg, void *scratch,
-                       uint32_t *tile_off, bool prev, hipStream_t s) {
+                       uint32_t *tile_off, bool prev, hipStream_t s, SpeciesWork *sorted_out) {
     if (w.n <= 0) {
+        if (sorted_out) *sorted_out = w;
         return launch_zero32(tile_off, tg.ntiles + 1, s);
     }
-    return w.dtype == SPIC_F64 ? sort_t<double>(g, w, tg, scratch, tile_off, prev, s)
-                               : sort_t<float>(g, w, tg, scratch, tile_off, prev, s);
+    return w.dtype == SPIC_F64 ? sort_t<double>(g, w, tg, scratch, tile_off, prev, s, sorted_out)
+                               : sort_t<float>(g, w, tg, scratch, tile_off, prev, s, sorted_out);
 }
 
 }  // namespace spic

@@ -10,18 +10,20 @@
 // the global moments with coalesced global atomics (neighbouring tiles'
 // regions overlap).
 //
-// Deposit.  Rank-major order inside a tile (spic_sort.hip) gives every
-// thread a run of particles from one cell, and every lane of a wave a
-// different cell.  A thread keeps the 80 sums (8 corners x 10 moments) of
-// its "home" cell -- the cell of the first particle it deposits -- in
-// registers of the accumulation type; only particles that have drifted into
-// another cell go to the region accumulator in LDS with atomics, and a
-// thread adds its register sums to the region once at the end of the tile.
+// Deposit.  Rank-major order inside a tile (spic_sort.hip) gives every lane
+// of a wave a different cell (and every thread a run of particles from one
+// cell), so the 80 FP64 LDS atomics per particle (8 corners x 10 moments)
+// of one wave instruction hit distinct words.  The variants (below) differ
+// in how they treat particles that have drifted out of their sort cell: in
+// LDS, register accumulation of the home cell with a queue of drifted
+// particles, or one lane per cell per atomic pass.
 //
-// LDS layout.  Region slots are (di*RYP + dj)*RZP + dk with padded extents
-// RYP >= ry, RZP >= rz chosen on the host so that the nodes of a wave's 64
-// cells fall evenly on the LDS banks.  Fields are node-major (6 values per
-// slot), moments component-major ([10][slots]).
+// LDS layout.  The region slot of a node is di*sx + dj*sy + dk*sz, with the
+// strides of a padded layout whose slow axis is the one particles cross most
+// often (region_layout): the nodes of a wave's 64 cells fall on distinct
+// bank pairs per 16 lanes, and a particle that drifted along the slow axis
+// keeps its bank pair.  Fields are node-major (6 values per slot), moments
+// component-major ([10][slots]).
 //
 // Particles whose cell lies outside the region (they drifted farther than
 // the halo since the last sort) take the global path for that gather or
@@ -63,7 +65,7 @@ __device__ __forceinline__ bool region_locate(const GridT<T> &g, const TileGeom 
     di += (di < 0) ? g.nx : 0;
     dj += (dj < 0) ? g.ny : 0;
     dk += (dk < 0) ? g.nz : 0;
-    slot = (di * tg.ryp + dj) * tg.rzp + dk;
+    slot = di * tg.sx + dj * tg.sy + dk * tg.sz;
     const bool in = di < tg.rx - 1 && dj < tg.ry - 1 && dk < tg.rz - 1;
     if (!in) {
         const int nyz = g.ny * g.nz;
@@ -80,8 +82,8 @@ __device__ __forceinline__ void gather_lds(const LdsFieldNode<TP> *__restrict__ 
                                            const Cell<TP> &c, TP out[6]) {
     TP w[8];
     pweights(c.fx, c.fy, c.fz, w);
-    const int sx = tg.ryp * tg.rzp, sy = tg.rzp;
-    const int nd[8] = {rb, rb + sx, rb + sy, rb + sx + sy, rb + 1, rb + sx + 1, rb + sy + 1, rb + sx + sy + 1};
+    const int sx = tg.sx, sy = tg.sy, sz = tg.sz;
+    const int nd[8] = {rb, rb + sx, rb + sy, rb + sx + sy, rb + sz, rb + sx + sz, rb + sy + sz, rb + sx + sy + sz};
 #pragma unroll
     for (int m = 0; m < 6; ++m) out[m] = TP(0);
 #pragma unroll
@@ -127,7 +129,7 @@ __device__ __forceinline__ RegionNode region_node(const TileGeom &tg, int nx, in
     const int rj = rem / tg.rz;
     const int rk = rem - rj * tg.rz;
     RegionNode n;
-    n.slot = (ri * tg.ryp + rj) * tg.rzp + rk;
+    n.slot = ri * tg.sx + rj * tg.sy + rk * tg.sz;
     n.gnode = (pwrap_index(ox + ri, nx) * ny + pwrap_index(oy + rj, ny)) * nz + pwrap_index(oz + rk, nz);
     return n;
 }
@@ -137,32 +139,16 @@ __device__ __forceinline__ RegionNode region_node(const TileGeom &tg, int nx, in
 template <typename TA, class GEO>
 __device__ __forceinline__ void deposit_one(const GridT<TA> &ga, const TileGeom &tg, int ox, int oy, int oz,
                                             TA *__restrict__ ml, TA *__restrict__ mom, int nn, TA x, TA y, TA z,
-                                            TA qa, TA ua, TA va, TA wa, bool rotate) {
-    const int RNP = tg.rnp, sx = tg.ryp * tg.rzp, sy = tg.rzp;
+                                            TA qa, TA ua, TA va, TA wa) {
+    const int RNP = tg.rnp, sx = tg.sx, sy = tg.sy, sz = tg.sz;
     int rb;
     Cell<TA> c;
     const bool in = region_locate(ga, tg, ox, oy, oz, x, y, z, rb, c);
     const TA val[10] = {TA(1), ua, va, wa, ua * ua, ua * va, ua * wa, va * va, va * wa, wa * wa};
-    if (in && rotate) {
-        // instruction k of lane l deposits corner k ^ (l & 7): lanes that
-        // share a cell then hit different nodes in the same instruction
-        const int s = threadIdx.x & 7;
-        const TA gx = TA(1) - c.fx, gy = TA(1) - c.fy, gz = TA(1) - c.fz;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int cc = k ^ s;
-            const TA wx = (cc & 1) ? c.fx : gx, wy = (cc & 2) ? c.fy : gy, wz = (cc & 4) ? c.fz : gz;
-            const TA qw = qa * (wx * wy * wz);
-            TA *dst = ml + rb + ((cc & 1) ? sx : 0) + ((cc & 2) ? sy : 0) + ((cc & 4) ? 1 : 0);
-#pragma unroll
-            for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, qw * val[m]);
-        }
-        return;
-    }
     TA wt8[8];
     pweights(c.fx, c.fy, c.fz, wt8);
     if (in) {
-        const int coff[8] = {0, sx, sy, sx + sy, 1, sx + 1, sy + 1, sx + sy + 1};
+        const int coff[8] = {0, sx, sy, sx + sy, sz, sx + sz, sy + sz, sx + sy + sz};
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const TA qw = qa * wt8[k];
@@ -191,20 +177,74 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One moved particle waiting in a wave's queue (variant 2).
+// A moved particle staged in LDS (variants 2 and 3).
 template <typename TP>
-struct QueuedParticle {
+struct StagedParticle {
     TP x, y, z, u, v, w, q, pad;
 };
 
-// Records per wave queue: at most 63 wait between drains, and one
-// iteration adds at most 64.
-constexpr int kQueueCap = 128;
+// Variant 3: bank-balanced deposit.  An FP64 LDS access by 16 consecutive
+// lanes is conflict free when their slots differ modulo 16; the rank-major
+// order gives that for particles still in their sort cells, but drifted
+// particles land on the bank pairs of their neighbours (measured: 8 clk per
+// atomic instruction without drift, 22-28 clk with a quarter to half of the
+// lanes drifted).  Before its 80 atomics a wave therefore re-places its
+// moved particles: the r-th particle (r < 4) whose slot is b modulo 16 goes
+// to lane 16 r + b, so each group of 16 lanes holds distinct bank pairs;
+// the rest fill the lanes left empty.  All 64 lanes must be active.
+struct BalanceLds {
+    int count[16];  // particles per bank pair
+    int hole[64];   // lanes left empty, in lane order
+};
 
-// LDS bytes of the per-wave queues of variant 2 (0 for the others).
-inline size_t queue_lds_bytes(int variant, int block, int dtype) {
-    if (variant != 2) return 0;
-    return (size_t)(block / 64) * kQueueCap * 8 * (dtype == SPIC_F64 ? 8 : 4);
+template <typename TP, typename TA, class GEO>
+__device__ __forceinline__ void deposit_balanced(const GridT<TA> &ga, const TileGeom &tg, int ox, int oy, int oz,
+                                                 TA *__restrict__ ml, TA *__restrict__ mom, int nn,
+                                                 StagedParticle<TP> *__restrict__ stage, BalanceLds *__restrict__ bl,
+                                                 int lane, bool valid, TP x, TP y, TP z, TP u, TP v, TP w, TP q) {
+    int rb = 0;
+    bool rec = false;
+    if (valid) {
+        Cell<TA> c;
+        rec = region_locate(ga, tg, ox, oy, oz, (TA)x, (TA)y, (TA)z, rb, c);
+        if (!rec)  // rare: outside the region, straight to the global moments
+            deposit_one<TA, GEO>(ga, tg, ox, oy, oz, ml, mom, nn, (TA)x, (TA)y, (TA)z, (TA)q, (TA)u, (TA)v, (TA)w);
+    }
+    if (lane < 16) bl->count[lane] = 0;
+    wave_sync();
+    const int b = rb & 15;
+    int r = 0;
+    if (rec) r = (int)atomicAdd(&bl->count[b], 1);
+    wave_sync();
+    StagedParticle<TP> me;
+    me.x = x; me.y = y; me.z = z; me.u = u; me.v = v; me.w = w; me.q = q; me.pad = TP(0);
+    const bool primary = rec && r < 4;
+    const bool over = rec && r >= 4;
+    if (primary) stage[16 * r + b] = me;
+    // lane l is filled by a primary particle iff bank pair l % 16 has more than l / 16 of them
+    const bool hole = bl->count[lane & 15] <= (lane >> 4);
+    const unsigned long long hmask = __ballot(hole), omask = __ballot(over);
+    const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const int h = __popcll(hmask & below), k = __popcll(omask & below);
+    if (hole) bl->hole[h] = lane;
+    wave_sync();
+    if (over) stage[bl->hole[k]] = me;
+    wave_sync();
+    if (!hole || h < __popcll(omask)) {
+        const StagedParticle<TP> s = stage[lane];
+        deposit_one<TA, GEO>(ga, tg, ox, oy, oz, ml, mom, nn, (TA)s.x, (TA)s.y, (TA)s.z, (TA)s.q, (TA)s.u, (TA)s.v,
+                             (TA)s.w);
+    }
+    wave_sync();  // the stage is rewritten by the next call
+}
+
+// LDS bytes of the per-wave staging of variants 2 (queue) and 3 (balance).
+constexpr int kQueueCap = 128;  // variant 2: at most 63 wait between drains, one iteration adds <= 64
+inline size_t stage_lds_bytes(int variant, int block, int dtype) {
+    const size_t rec = 8 * (dtype == SPIC_F64 ? 8 : 4);
+    if (variant == 2) return (size_t)(block / 64) * kQueueCap * rec;
+    if (variant == 3) return (size_t)(block / 64) * (64 * rec + sizeof(BalanceLds));
+    return 0;
 }
 
 // One tile of one species: stage the region, move and deposit the tile's
@@ -216,13 +256,14 @@ template <typename TP, typename TF, typename TA, int VAR, class GEO>
 __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, unsigned char *smem) {
     constexpr bool HOME = VAR == 2;   // home-cell registers + queue of drifted particles
     constexpr bool CACHE = VAR == 1;  // field corners of the last cell in registers
-    constexpr bool ROTATE = VAR == 3; // lane-rotated corner order of the LDS deposit
+    constexpr bool BAL = VAR == 3;    // bank-balanced deposit
     const GridT<TP> &g = J.g;
     TileGeom tg = J.tg;
     if constexpr (GEO::fixed) {  // the host launches this only for a matching tiling
         tg.tx = GEO::tx; tg.ty = GEO::ty; tg.tz = GEO::tz; tg.halo = GEO::halo;
         tg.rx = GEO::rx; tg.ry = GEO::ry; tg.rz = GEO::rz;
-        tg.ryp = GEO::ryp; tg.rzp = GEO::rzp; tg.rnp = GEO::rnp;
+        tg.slow = GEO::slow; tg.mid = GEO::mid; tg.fast = GEO::fast;
+        tg.sx = GEO::sx; tg.sy = GEO::sy; tg.sz = GEO::sz; tg.rnp = GEO::rnp;
     }
     const FieldPtrs<TF> &f = J.f;
     const PartPtrs<TP> &p = J.p;
@@ -240,7 +281,7 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
     int oy = (tyi * tg.ty - tg.halo) % g.ny; oy += oy < 0 ? g.ny : 0;
     int oz = (tzi * tg.tz - tg.halo) % g.nz; oz += oz < 0 ? g.nz : 0;
     const int RL = tg.rx * tg.ry * tg.rz;  // logical region nodes
-    const int sx = tg.ryp * tg.rzp, sy = tg.rzp;
+    const int sx = tg.sx, sy = tg.sy, sz = tg.sz;
 
     // stage the region's node fields, zero the region's moments
     for (int r = threadIdx.x; r < RL; r += blockDim.x) {
@@ -254,29 +295,37 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
         for (int q = threadIdx.x; q < 10 * RNP; q += blockDim.x) ml[q] = TA(0);
     __syncthreads();
 
-    const int coff[8] = {0, sx, sy, sx + sy, 1, sx + 1, sy + 1, sx + sy + 1};
+    const int coff[8] = {0, sx, sy, sx + sy, sz, sx + sz, sy + sz, sx + sy + sz};
     TA acc[HOME ? 80 : 1];
 #pragma unroll
     for (int q = 0; q < (HOME ? 80 : 1); ++q) acc[q] = TA(0);
     int home = -1;
     LdsFieldNode<TP> corner[CACHE ? 8 : 1];  // field corners of the cell `cached`
     int cached = -1;
-    // variant 2: this wave's queue of drifted particles, a stack of qn records
-    QueuedParticle<TP> *queue = nullptr;
+    // per-wave staging after the moments: variant 2's queue of drifted
+    // particles (a stack of qn records), variant 3's balance buffers
+    unsigned char *wstage = smem + fbytes + (((size_t)10 * RNP * sizeof(TA) + 15) & ~(size_t)15);
+    StagedParticle<TP> *queue = nullptr;
     int qn = 0;  // uniform across the wave
-    if constexpr (HOME)
-        queue = (QueuedParticle<TP> *)(smem + fbytes + (((size_t)10 * RNP * sizeof(TA) + 15) & ~(size_t)15)) +
-                (threadIdx.x >> 6) * kQueueCap;
+    if constexpr (HOME) queue = (StagedParticle<TP> *)wstage + (threadIdx.x >> 6) * kQueueCap;
+    StagedParticle<TP> *stage = nullptr;
+    BalanceLds *bal = nullptr;
+    if constexpr (BAL) {
+        unsigned char *mine = wstage + (threadIdx.x >> 6) * (64 * sizeof(StagedParticle<TP>) + sizeof(BalanceLds));
+        stage = (StagedParticle<TP> *)mine;
+        bal = (BalanceLds *)(mine + 64 * sizeof(StagedParticle<TP>));
+    }
     const int lane = threadIdx.x & 63;
 
     const uint32_t stride = blockDim.x;
     constexpr uint32_t ES = sizeof(TP);
     uint32_t i = beg + threadIdx.x;
     TP nx_ = 0, ny_ = 0, nz_ = 0, nu_ = 0, nv_ = 0, nw_ = 0, nq_ = 0;
+    const PartPtrs<TP> &pin = J.in;
     if (i < end) {
         const uint32_t o = i * ES;
-        nx_ = ld32(p.x, o); ny_ = ld32(p.y, o); nz_ = ld32(p.z, o);
-        nu_ = ld32(p.u, o); nv_ = ld32(p.v, o); nw_ = ld32(p.w, o); nq_ = ld32(p.q, o);
+        nx_ = ld32(pin.x, o); ny_ = ld32(pin.y, o); nz_ = ld32(pin.z, o);
+        nu_ = ld32(pin.u, o); nv_ = ld32(pin.v, o); nw_ = ld32(pin.w, o); nq_ = ld32(pin.q, o);
     }
     // uniform per wave: the first index of this wave's lane 0
     for (uint32_t i0 = beg + (threadIdx.x & ~63u); i0 < end; i0 += stride, i += stride) {
@@ -286,8 +335,8 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
         const uint32_t inext = i + stride;
         if (inext < end) {  // prefetch the next particle while this one is moved
             const uint32_t o = inext * ES;
-            nx_ = ld32(p.x, o); ny_ = ld32(p.y, o); nz_ = ld32(p.z, o);
-            nu_ = ld32(p.u, o); nv_ = ld32(p.v, o); nw_ = ld32(p.w, o); nq_ = ld32(p.q, o);
+            nx_ = ld32(pin.x, o); ny_ = ld32(pin.y, o); nz_ = ld32(pin.z, o);
+            nu_ = ld32(pin.u, o); nv_ = ld32(pin.v, o); nw_ = ld32(pin.w, o); nq_ = ld32(pin.q, o);
         }
         bool enq = false;
         if (valid) {
@@ -351,6 +400,10 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
             const uint32_t o = i * ES;
             st32(p.x, o, xn); st32(p.y, o, yn); st32(p.z, o, zn);
             st32(p.u, o, un); st32(p.v, o, vn); st32(p.w, o, wn);
+            if (J.copy_rest) {  // reading the sort's copy: q and id move too
+                st32(p.q, o, qp);
+                if (pin.id) p.id[i] = pin.id[i];
+            }
 
             if (mom) {
                 // deposit of the new state in the accumulation precision
@@ -374,11 +427,15 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
                     } else {
                         enq = true;  // another cell, or outside the region
                     }
-                } else {
-                    deposit_one<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, (TA)xn, (TA)yn, (TA)zn, qa, ua, va, wa,
-                                         ROTATE);
+                } else if constexpr (!BAL) {
+                    deposit_one<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, (TA)xn, (TA)yn, (TA)zn, qa, ua, va, wa);
                 }
             }
+        }
+        if constexpr (BAL) {
+            if (mom)
+                deposit_balanced<TP, TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, stage, bal, lane, valid, xn, yn, zn,
+                                              un, vn, wn, qp);
         }
         if constexpr (HOME) {
             // queue the drifted particles of this iteration; once 64 wait,
@@ -387,7 +444,7 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
             if (vote) {
                 const unsigned long long below = lane ? (vote & (~0ull >> (64 - lane))) : 0ull;
                 if (enq) {
-                    QueuedParticle<TP> r;
+                    StagedParticle<TP> r;
                     r.x = xn; r.y = yn; r.z = zn; r.u = un; r.v = vn; r.w = wn; r.q = qp; r.pad = TP(0);
                     queue[qn + __popcll(below)] = r;
                 }
@@ -397,10 +454,10 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
                     // are visible after a wave-scope fence
                     wave_sync();
                     qn -= 64;
-                    const QueuedParticle<TP> r = queue[qn + lane];
+                    const StagedParticle<TP> r = queue[qn + lane];
                     wave_sync();
                     deposit_one<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, (TA)r.x, (TA)r.y, (TA)r.z, (TA)r.q,
-                                         (TA)r.u, (TA)r.v, (TA)r.w, false);
+                                         (TA)r.u, (TA)r.v, (TA)r.w);
                 }
             }
         }
@@ -409,9 +466,9 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
     if constexpr (HOME) {
         wave_sync();
         if (lane < qn) {
-            const QueuedParticle<TP> r = queue[lane];
+            const StagedParticle<TP> r = queue[lane];
             deposit_one<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, (TA)r.x, (TA)r.y, (TA)r.z, (TA)r.q, (TA)r.u,
-                                 (TA)r.v, (TA)r.w, false);
+                                 (TA)r.v, (TA)r.w);
         }
         if (home >= 0) {
 #pragma unroll
@@ -442,7 +499,7 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
 //      so gathers in a thread's cell skip LDS; <= 168 VGPRs, 3 waves/SIMD
 //   2  home-cell register accumulation of the deposit (80 sums) with LDS
 //      atomics for drifted particles; <= 256 VGPRs, 2 waves/SIMD
-//   3  as 0, with a lane-rotated corner order in the LDS deposit
+//   3  as 0, with the bank-balanced deposit (per-wave staging in LDS)
 template <int VAR>
 struct VariantWaves {
     static constexpr int value = (VAR == 0 || VAR == 3) ? 4 : (VAR == 1 ? 3 : 2);
@@ -482,7 +539,7 @@ k_worklist(const TileJob<TP, TF, TA> *__restrict__ jobs, const uint2 *__restrict
 size_t tiled_lds_bytes(const TileGeom &tg, int dtype, int acc_dtype, int variant, int block) {
     const size_t fsz = (size_t)tg.rnp * 6 * (dtype == SPIC_F64 ? 8 : 4);
     const size_t msz = (size_t)tg.rnp * 10 * (acc_dtype == SPIC_F64 ? 8 : 4);
-    return ((fsz + 15) & ~(size_t)15) + ((msz + 15) & ~(size_t)15) + queue_lds_bytes(variant, block, dtype);
+    return ((fsz + 15) & ~(size_t)15) + ((msz + 15) & ~(size_t)15) + stage_lds_bytes(variant, block, dtype);
 }
 
 // Dynamic LDS above 64 KiB must be allowed per kernel once.

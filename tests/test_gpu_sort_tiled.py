@@ -46,7 +46,18 @@ def _keys_np(g, st, tile):
     k = np.minimum((np.asarray(st["z"], np.float64) / dz).astype(np.int64), g.nz - 1)
     nty, ntz = -(-g.ny // ty), -(-g.nz // tz)
     tile_id = ((i // tx) * nty + (j // ty)) * ntz + (k // tz)
-    local = ((i % tx) * ty + (j % ty)) * tz + (k % tz)
+    # local cells: slow axis = the one with the finest cells (ties: z, y, x),
+    # then the other two in x, y, z order
+    d = [dx, dy, dz]
+    slow = 2
+    if d[1] < d[slow]:
+        slow = 1
+    if d[0] < d[slow]:
+        slow = 0
+    mid, fast = [a for a in range(3) if a != slow]
+    loc = [i % tx, j % ty, k % tz]
+    t = [tx, ty, tz]
+    local = (loc[slow] * t[mid] + loc[mid]) * t[fast] + loc[fast]
     return tile_id, local
 
 
@@ -141,7 +152,8 @@ def test_tiled_fp32_one_step(spic, ctx, variant):
 
 @pytest.mark.parametrize("tile,halo,variant", [((4, 4, 4), 0, 0), ((4, 4, 4), 0, 2), ((2, 4, 8), 1, 1),
                                                ((3, 3, 3), 1, 2), ((2, 2, 2), 2, 3), ((2, 8, 4), 1, 2),
-                                               ((4, 4, 2), 1, 1), ((4, 4, 4), 1, 3)])
+                                               ((4, 4, 2), 1, 1), ((4, 4, 4), 1, 3), ((4, 4, 4), 0, 3),
+                                               ((3, 2, 4), 2, 3)])
 def test_tile_shapes_and_halo_overflow_match_oracle(spic, ctx, tile, halo, variant):
     """Fast particles leave small regions (halo 0) -> global fallbacks; tile
     shapes that do not divide the grid leave ragged edge tiles."""
