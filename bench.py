@@ -27,10 +27,13 @@ Other measured configurations (one JSON line each):
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
+from typing import Optional
 
 import numpy as np
 
@@ -45,6 +48,31 @@ METRIC = "particle-steps/s (mover+moments) FP32 vs FP64; % HBM peak; p99 latency
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "fused_tiled_harris_128x64x32_f32_traffic.md")
+KERNEL_SOURCES = ("paper_2008_04397_amd/csrc/spic_tiled.hip", "paper_2008_04397_amd/csrc/spic_device.h",
+                  "paper_2008_04397_amd/csrc/spic_impl.h")
+
+
+def measured_traffic(tuned) -> Optional[float]:
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary, or None when the kernel sources changed
+    since the counters were taken or the launch configuration differs."""
+    try:
+        txt = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    fields = dict(re.findall(r"^(\w+): (.*)$", txt, re.M))
+    h = hashlib.sha256(b"".join(open(os.path.join(HERE, p), "rb").read() for p in KERNEL_SOURCES)).hexdigest()
+    if fields.get("kernel_source_sha256", "").strip() != h:
+        return None
+    cfg = fields.get("config", "")
+    want = {"tile_variant": 0, "tile_block": 512, "bank_align": 1, "sort_every": 4}
+    got = {k: int(v) for k, v in re.findall(r"(\w+) (\d+)", cfg)}
+    if tuned is not None and any(tuned.get(k) != got.get(k) for k in want):
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def algorithmic_bytes(n_particles: int, nodes: int, s_p: int, s_f: int) -> float:
@@ -80,7 +108,7 @@ def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: 
         key = autotune.workload_class(dtype_name, g, h.ppc)
         tuned = autotune.load(key)
         if tuned is None:
-            tuned = autotune.tune(h, f, species, h.qoms, moms, steps=6, log=log)
+            tuned = autotune.tune(h, f, species, h.qoms, moms, steps=16, log=log)
             autotune.store(key, tuned)
         autotune.apply(ctx, tuned)
         if sort_every < 0:
@@ -131,6 +159,12 @@ def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: 
     fused_ms = launch_ms[~sort_step] if (~sort_step).any() else launch_ms
     avg_launch_s = float(fused_ms.mean()) / 1e3
     achieved = per_launch_bytes / avg_launch_s / 1e9
+    # measured HBM bytes of the same launches (rocprofv3 counters, profiles/)
+    traffic_bytes = measured_traffic(tuned if tuned is not None else {"tile_variant": variant if variant >= 0 else 0,
+                                                                      "tile_block": 512, "bank_align": 1,
+                                                                      "sort_every": sort_every}) \
+        if dtype_name == "f32" and not path else None
+    traffic = traffic_bytes / avg_launch_s / 1e9 if traffic_bytes else None
     step_ms = total_ms / steps
     per_step = launch_ms.sum(axis=1)
     sort_ms = float(launch_ms[sort_step].mean() - fused_ms.mean()) if sort_step.any() else 0.0
@@ -144,9 +178,10 @@ def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: 
         "wall_s": wall,
         "sort_ms_per_species": sort_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_fused_tiled (one launch per species)",
-                     "bytes_per_launch": per_launch_bytes, "avg_launch_ms": avg_launch_s * 1e3},
+                     "bytes_per_launch": per_launch_bytes, "avg_launch_ms": avg_launch_s * 1e3,
+                     "traffic_bytes_per_launch": traffic_bytes},
     }
 
 
@@ -315,6 +350,8 @@ def main():
     ap.add_argument("--path", type=int, default=0)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with a plain 1 GiB device-to-device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -373,6 +410,13 @@ def main():
         out["fp64"] = {"value": r64["value"], "unit": "particle-steps/s", "dtype": "f64",
                        "ms_per_step": r64["ms_per_step"], "roofline": r64["roofline"], "tuned": r64["tuned"],
                        "sort_every": r64["sort_every"]}
+    if args.copy_calibration:
+        # 2^28 FP32 = 1 GiB read + 1 GiB written by one copy kernel
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     print(json.dumps(out), flush=True)
 
 

@@ -169,7 +169,7 @@ int spic_version(void);
  *   block          threads per block of the unsorted-path kernels (64..1024, x64)
  *   grid_cap       cap on blocks of grid-stride kernels
  *   path           0 = tiled kernel for sorted species, 1 = unsorted path only
- *   tile_block     threads per block of the tiled kernel (64..512, x64)
+ *   tile_block     threads per block of the tiled kernel (64..512, x64; 512)
  *   tile_x/y/z     sort tile shape in cells (product <= 64)
  *   halo           cells of halo staged around a tile in LDS (0..8)
  *   lds_max        read only: LDS bytes a workgroup may use on the device
@@ -178,7 +178,8 @@ int spic_version(void);
  *                  when that tiling is in effect
  *   bank_align     1 = LDS region layout that keeps a particle's bank pair
  *                  when it drifts along the most-crossed axis (more LDS);
- *                  0 = the most compact conflict-free layout (0/1)
+ *                  0 = the most compact conflict-free layout (default: 1
+ *                  for FP32 particles, 0 for FP64)
  *   sort_ordered   1 = a re-sort walks each tile of the current order in
  *                  order, so ranks inside a cell keep that order (0/1)
  *   graph          batch engine: replay unchanged ticks as a hipGraph (0/1)

@@ -14,13 +14,14 @@ from __future__ import annotations
 
 import itertools
 import json
+import math
 import os
 import time
 from typing import Dict, Iterable, Optional, Sequence
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 
-DEFAULT = {"tile_block": 256, "tile_variant": 0, "halo": 1, "tile_x": 4, "tile_y": 4, "tile_z": 4,
+DEFAULT = {"tile_block": 512, "tile_variant": 0, "halo": 1, "tile_x": 4, "tile_y": 4, "tile_z": 4,
            "bank_align": 1, "sort_ordered": 1, "sort_every": 4}
 
 
@@ -71,14 +72,21 @@ def candidates(quick: bool = True) -> Iterable[Dict[str, int]]:
         yield c
 
 
-def tune(h, fields, species, qoms, moments, steps: int = 8, quick: bool = True, log=None) -> Dict[str, int]:
+def tune(h, fields, species, qoms, moments, steps: int = 16, quick: bool = True, log=None) -> Dict[str, int]:
     """Time `steps` fused steps (after the first sort) for every candidate on
     the given device-resident inputs; returns the fastest configuration.  The
-    inputs are advanced in time by the trials (a real run's state)."""
+    inputs are advanced in time by the trials (a real run's state).  `steps`
+    is rounded up to a multiple of every candidate cadence, so each trial
+    pays its own sorts in full."""
     import torch
     from . import spic
     best, best_ms = None, float("inf")
-    for cfg in candidates(quick):
+    cands = list(candidates(quick))
+    period = 1
+    for c in cands:
+        period = period * c["sort_every"] // math.gcd(period, c["sort_every"])
+    steps = -(-steps // period) * period
+    for cfg in cands:
         ctx = spic.Context(0)
         apply(ctx, cfg)
         se = cfg["sort_every"]

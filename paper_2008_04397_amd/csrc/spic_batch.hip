@@ -149,7 +149,7 @@ struct BatchEngine {
     std::vector<uint64_t> graph_key;
 
     // tuning, read from the ctx options when the engine starts
-    int tile_block = 256, variant = 0, use_graph = 1, max_groups = 0, fixed_geo = 1, sort_ordered = 1;
+    int tile_block = 512, variant = 0, use_graph = 1, max_groups = 0, fixed_geo = 1, sort_ordered = 1;
     int64_t tick_items = 4096;  // 0: every active run steps at every tick
     int64_t batch_particles = (int64_t)1 << 26;
     LaunchCfg lcfg;
@@ -202,7 +202,8 @@ struct BatchEngine {
             st->params = R.params;
             st->fields = R.fields;
             st->nsteps = R.nsteps;
-            st->tg = ctx->tile_geom(R.grid);
+            // one tiling per run, for the dtype of its first species
+            st->tg = ctx->tile_geom(R.grid, R.nspecies > 0 ? R.species[0].dtype : SPIC_F32);
             if (st->tg.cells < 1 || st->tg.cells > 64)
                 return ctx->fail(SPIC_E_ARG, "run %d: tile shape must hold 1..64 cells", r);
             size_t fp = 0;
@@ -829,7 +830,7 @@ int spic_ctx_s::batch_submit(const spic_run *runs, int32_t nruns, uint64_t *tick
     if (nruns == 0) return SPIC_OK;
     if (!batch) {
         batch.reset(new BatchEngine(this));
-        batch->tile_block = (int)opt("tile_block", 256);
+        batch->tile_block = (int)opt("tile_block", 512);
         batch->variant = (int)opt("tile_variant", 0);
         batch->fixed_geo = (int)opt("fixed_geo", 1);
         batch->sort_ordered = (int)opt("sort_ordered", 1);

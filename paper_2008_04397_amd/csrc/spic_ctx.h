@@ -40,7 +40,7 @@ struct spic_ctx_s {
     };
     std::map<std::string, Layout> layouts;
     std::string layout_key(const spic_grid &g, const spic_species &s) const;
-    spic::TileGeom tile_geom(const spic_grid &g) const;
+    spic::TileGeom tile_geom(const spic_grid &g, int dtype) const;
 
     spic_ctx_s();
     ~spic_ctx_s();
@@ -70,7 +70,7 @@ struct spic_ctx_s {
     int moments(const spic_grid &g, const spic_species *sp, int32_t nsp, spic_moment_array *mom, bool accumulate,
                 hipStream_t s);
     int sort(const spic_grid &g, spic_species *sp, int32_t nsp, hipStream_t s);
-    int sort_prepare(const spic_grid &g, const spic_species *sp, int32_t nsp, spic::TileGeom &tg, size_t &need);
+    int sort_prepare(const spic_grid &g, const spic_species *sp, int32_t nsp, size_t &need);
     int sort_one(const spic_grid &g, const spic_species &sp, const spic::TileGeom &tg, size_t need, hipStream_t s,
                  uint32_t **toff_out, spic::SpeciesWork *sorted_out);
     int batch_submit(const spic_run *runs, int32_t nruns, uint64_t *tickets);

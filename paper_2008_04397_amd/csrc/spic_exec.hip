@@ -31,9 +31,11 @@ std::string spic_ctx_s::layout_key(const spic_grid &g, const spic_species &s) co
     return buf;
 }
 
-TileGeom spic_ctx_s::tile_geom(const spic_grid &g) const {
+// The bank-preserving layout pays off for FP32 particles; FP64 particles
+// keep the compact one (two workgroups per CU) unless bank_align is set.
+TileGeom spic_ctx_s::tile_geom(const spic_grid &g, int dtype) const {
     return make_tile_geom(g, (int)opt("tile_x", 4), (int)opt("tile_y", 4), (int)opt("tile_z", 4),
-                          (int)opt("halo", 1), opt("bank_align", 1) != 0);
+                          (int)opt("halo", 1), opt("bank_align", dtype == SPIC_F64 ? 0 : 1) != 0);
 }
 
 
@@ -43,10 +45,9 @@ int spic_ctx_s::mover(const spic_grid &g, const spic_params &p, const spic_field
     const LaunchCfg cfg = launch_cfg();
     const bool sort_now = p.sort_every > 0 && p.step % p.sort_every == 0;
     const bool generic_only = opt("path", 0) == 1;
-    TileGeom tg_now{};
     size_t sort_need = 0;
     if (sort_now) {
-        int rc = sort_prepare(g, sp, nsp, tg_now, sort_need);
+        int rc = sort_prepare(g, sp, nsp, sort_need);
         if (rc) return rc;
     }
     for (int i = 0; i < nsp; ++i) {
@@ -67,6 +68,7 @@ int spic_ctx_s::mover(const spic_grid &g, const spic_params &p, const spic_field
         if (sort_now) {
             // sort this species; the tiled kernel then reads the reordered
             // copy directly instead of it being copied back first
+            const TileGeom tg_now = tile_geom(g, sp[i].dtype);
             const bool tiled = tiled_ok(tg_now);
             uint32_t *toff = nullptr;
             SpeciesWork sorted;
@@ -109,16 +111,17 @@ int spic_ctx_s::moments(const spic_grid &g, const spic_species *sp, int32_t nsp,
     return SPIC_OK;
 }
 
-// Tile geometry of the next sort and the scratch it needs for every species.
-int spic_ctx_s::sort_prepare(const spic_grid &g, const spic_species *sp, int32_t nsp, TileGeom &tg, size_t &need) {
-    tg = tile_geom(g);
+// Checks the tile shape and sizes the scratch the next sort of every
+// species needs (each species gets the tiling of its dtype).
+int spic_ctx_s::sort_prepare(const spic_grid &g, const spic_species *sp, int32_t nsp, size_t &need) {
+    const TileGeom tg = tile_geom(g, SPIC_F32);
     if (tg.cells < 1 || tg.cells > 64 || tg.halo < 0 || tg.halo > 8)
         return fail(SPIC_E_ARG, "tile shape %dx%dx%d (halo %d): a tile holds 1..64 cells, halo 0..8", tg.tx, tg.ty,
                     tg.tz, tg.halo);
     need = 0;
     for (int i = 0; i < nsp; ++i) {
         if (sp[i].n >= ((int64_t)1 << 31)) return fail(SPIC_E_UNSUPPORTED, "species %d: sort needs n < 2^31", i);
-        need = std::max(need, sort_scratch_bytes(sp[i].n, sp[i].dtype, sp[i].id != nullptr, tg));
+        need = std::max(need, sort_scratch_bytes(sp[i].n, sp[i].dtype, sp[i].id != nullptr, tile_geom(g, sp[i].dtype)));
     }
     return SPIC_OK;
 }
@@ -143,11 +146,10 @@ int spic_ctx_s::sort_one(const spic_grid &g, const spic_species &sp, const TileG
 }
 
 int spic_ctx_s::sort(const spic_grid &g, spic_species *sp, int32_t nsp, hipStream_t s) {
-    TileGeom tg;
     size_t need = 0;
-    int rc = sort_prepare(g, sp, nsp, tg, need);
+    int rc = sort_prepare(g, sp, nsp, need);
     if (rc) return rc;
     for (int i = 0; i < nsp; ++i)
-        if ((rc = sort_one(g, sp[i], tg, need, s, nullptr, nullptr))) return rc;
+        if ((rc = sort_one(g, sp[i], tile_geom(g, sp[i].dtype), need, s, nullptr, nullptr))) return rc;
     return SPIC_OK;
 }

@@ -57,7 +57,7 @@ struct SpeciesWork {
 struct LaunchCfg {
     int block = 256;        // generic kernels
     int grid_cap = 1 << 20;
-    int tile_block = 256;   // tiled fused kernel
+    int tile_block = 512;   // tiled fused kernel
     int variant = 0;        // tiled kernel variant (see spic_tiled.hip)
     int fixed_geo = 1;      // compile-time region geometry for the default tiling
 };

@@ -208,7 +208,7 @@ LaunchCfg spic_ctx_s::launch_cfg() const {
     LaunchCfg c;
     c.block = (int)opt("block", 256);
     c.grid_cap = (int)opt("grid_cap", 1 << 20);
-    c.tile_block = (int)opt("tile_block", 256);
+    c.tile_block = (int)opt("tile_block", 512);
     c.variant = (int)opt("tile_variant", 0);
     c.fixed_geo = (int)opt("fixed_geo", 1);
     return c;
