@@ -173,7 +173,7 @@ int spic_version(void);
  *   tile_x/y/z     sort tile shape in cells (product <= 64)
  *   halo           cells of halo staged around a tile in LDS (0..8)
  *   lds_max        read only: LDS bytes a workgroup may use on the device
- *   tile_variant   tiled-kernel variant (0..3; see spic_tiled.hip)
+ *   tile_variant   tiled-kernel variant (0..4; see spic_tiled.hip)
  *   fixed_geo      1 = kernels compiled for 4x4x4 tiles with halo 1 are used
  *                  when that tiling is in effect
  *   bank_align     1 = LDS region layout that keeps a particle's bank pair

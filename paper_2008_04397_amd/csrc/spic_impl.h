@@ -75,6 +75,11 @@ struct TileGeom {
     // region coordinates (a, b, c) is a*sx + b*sy + c*sz.
     int slow, mid, fast;
     int sx, sy, sz, rnp;  // slot strides and slots (padded for bank spread)
+    // Order of a tile's particles after a sort: 0 rank-major (rank 0 of
+    // every cell, then rank 1, ...: a wave's lanes in distinct cells), 1
+    // cell-major (all particles of cell 0, then cell 1, ...: a wave's lanes
+    // mostly in one cell, for the segmented deposit).
+    int cellmajor, pad;
 };
 
 // LDS bank spread of a region layout.  A wave deposits with one lane per
@@ -272,7 +277,8 @@ hipError_t launch_deposit_generic(const spic_grid &g, const SpeciesWork &w, cons
                                   hipStream_t s);
 
 // Sort (spic_sort.hip).
-TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo, bool align = true);
+TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo, bool align = true,
+                        bool cellmajor = false);
 size_t sort_scratch_bytes(int64_t n, int dtype, bool with_id, const TileGeom &tg);
 // prev: tile_off already holds the per-tile ranges of the particles'
 // current order (an earlier sort with the same tiles and n); the key pass
@@ -284,7 +290,7 @@ hipError_t launch_sort(const spic_grid &g, const SpeciesWork &w, const TileGeom 
                        uint32_t *tile_off, bool prev, hipStream_t s, SpeciesWork *sorted_out = nullptr);
 inline bool same_tiling(const TileGeom &a, const TileGeom &b) {
     return a.tx == b.tx && a.ty == b.ty && a.tz == b.tz && a.ntx == b.ntx && a.nty == b.nty && a.ntz == b.ntz &&
-           a.slow == b.slow && a.mid == b.mid && a.fast == b.fast;
+           a.slow == b.slow && a.mid == b.mid && a.fast == b.fast && a.cellmajor == b.cellmajor;
 }
 
 // Tiled fused path (spic_tiled.hip): one workgroup per tile of a sorted

@@ -189,7 +189,7 @@ static const char *const kOptionNames[] = {
     "halo",         // cells of halo staged around a tile
     "lds_max",      // read only: LDS bytes per workgroup on the device
     "tile_variant", // tiled kernel: 0 LDS atomics, 1 + field corners in registers, 2 home-cell registers,
-                    // 3 bank-balanced LDS deposit
+                    // 3 bank-balanced LDS deposit, 4 segmented wave pre-reduction (cell-major order)
     "fixed_geo",    // tiled kernel: 1 = compile-time region geometry for 4x4x4 tiles, halo 1
     "sort_ordered", // sort: 1 = ranks follow the previous order (a sorted species' tiles walked in order)
     "bank_align",   // tiled kernel: 1 = LDS layout whose slow-axis stride keeps bank pairs (more slots)
@@ -283,8 +283,8 @@ int spic_set_option(spic_ctx ctx, const char *key, int64_t value) {
             if ((!strcmp(key, "tile_x") || !strcmp(key, "tile_y") || !strcmp(key, "tile_z")) &&
                 (value < 1 || value > 64))
                 return ctx->fail(SPIC_E_ARG, "tile sizes must be in [1, 64]");
-            if (!strcmp(key, "tile_variant") && (value < 0 || value > 3))
-                return ctx->fail(SPIC_E_ARG, "tile_variant must be in 0..3");
+            if (!strcmp(key, "tile_variant") && (value < 0 || value > 4))
+                return ctx->fail(SPIC_E_ARG, "tile_variant must be in 0..4");
             if (!strcmp(key, "batch_particles") && (value < 1024 || value > ((int64_t)1 << 29)))
                 return ctx->fail(SPIC_E_ARG, "batch_particles must be in [1024, 2^29]");
             if (!strcmp(key, "tick_items") && (value < 0 || value > ((int64_t)1 << 30)))

@@ -18,7 +18,8 @@
 //   2 scan:    exclusive prefix of the per-key counts (three kernels)
 //   3 tables:  per tile and rank, the start of the rank block and the mask
 //              of cells holding a particle of that rank
-//   4 slots:   rank-major slot of every particle (an index scatter), then a
+//   4 slots:   rank-major (or cell-major) slot of every particle (an index
+//              scatter), then a
 //              gather of the particles into slot order in scratch; copy
 //              back (or the fused kernel reads the scratch directly)
 #include <hip/hip_runtime.h>
@@ -288,6 +289,18 @@ k_sort_slots(int64_t n, const uint2 *__restrict__ keyrank, const uint32_t *__res
     }
 }
 
+// Cell-major slot of every particle: all particles of a cell together, in
+// rank order.
+__global__ void __launch_bounds__(256)
+k_sort_slots_cm(int64_t n, const uint2 *__restrict__ keyrank, const uint32_t *__restrict__ offsets,
+                const uint32_t *__restrict__ own, uint32_t *__restrict__ srcidx) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const uint2 kr = keyrank[p];
+        const uint32_t rank = (own && (kr.y & kImmigrant)) ? own[kr.x] + (kr.y & ~kImmigrant) : kr.y;
+        srcidx[offsets[kr.x] + rank] = (uint32_t)p;
+    }
+}
+
 // Gather the particles into slot order: writes are coalesced; the reads
 // are scattered over the tile's earlier range and its neighbours' (L2
 // resident) wherever particles changed cell since the last sort.
@@ -323,7 +336,7 @@ __global__ void k_tile_offsets(const uint32_t *__restrict__ offsets, TileGeom tg
 
 // ------------------------------------------------------------------ host
 
-TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo, bool align) {
+TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo, bool align, bool cellmajor) {
     TileGeom t;
     t.tx = tx; t.ty = ty; t.tz = tz;
     t.cells = tx * ty * tz;
@@ -349,6 +362,8 @@ TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo, bo
     t.sy = lay.sy;
     t.sz = lay.sz;
     t.rnp = lay.rnp;
+    t.cellmajor = cellmajor ? 1 : 0;
+    t.pad = 0;
     return t;
 }
 
@@ -421,15 +436,21 @@ static hipError_t sort_t(const spic_grid &g, const SpeciesWork &w, const TileGeo
     hipLaunchKernelGGL(k_scan_partials, dim3(nparts), dim3(SCAN_BLOCK), 0, s, counts, nkeys, partial);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, partial, nparts);
     hipLaunchKernelGGL(k_scan_apply, dim3(nparts), dim3(SCAN_BLOCK), 0, s, counts, nkeys, partial, offsets);
-    // rank tables: max count per tile, exclusive scan of the max counts, fill
-    hipLaunchKernelGGL(k_tile_maxc, dim3(tg.ntiles), dim3(64), 0, s, offsets, tg, maxc);
-    hipLaunchKernelGGL(k_scan_partials, dim3(tparts), dim3(SCAN_BLOCK), 0, s, maxc, (int64_t)tg.ntiles, tpartial);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tpartial, tparts);
-    hipLaunchKernelGGL(k_scan_apply, dim3(tparts), dim3(SCAN_BLOCK), 0, s, maxc, (int64_t)tg.ntiles, tpartial,
-                       tab_off);
-    hipLaunchKernelGGL(k_tile_table, dim3(tg.ntiles), dim3(64), 0, s, offsets, tg, tab_off, tab);
-    hipLaunchKernelGGL(k_sort_slots, dim3(gp > 0 ? gp : 1), dim3(256), 0, s, n, keyrank, offsets, tab_off, tab,
-                       tg.cells, prev ? (const uint32_t *)own : nullptr, srcidx);
+    if (tg.cellmajor) {
+        hipLaunchKernelGGL(k_sort_slots_cm, dim3(gp > 0 ? gp : 1), dim3(256), 0, s, n, keyrank, offsets,
+                           prev ? (const uint32_t *)own : nullptr, srcidx);
+    } else {
+        // rank tables: max count per tile, exclusive scan of the max counts, fill
+        hipLaunchKernelGGL(k_tile_maxc, dim3(tg.ntiles), dim3(64), 0, s, offsets, tg, maxc);
+        hipLaunchKernelGGL(k_scan_partials, dim3(tparts), dim3(SCAN_BLOCK), 0, s, maxc, (int64_t)tg.ntiles,
+                           tpartial);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tpartial, tparts);
+        hipLaunchKernelGGL(k_scan_apply, dim3(tparts), dim3(SCAN_BLOCK), 0, s, maxc, (int64_t)tg.ntiles, tpartial,
+                           tab_off);
+        hipLaunchKernelGGL(k_tile_table, dim3(tg.ntiles), dim3(64), 0, s, offsets, tg, tab_off, tab);
+        hipLaunchKernelGGL(k_sort_slots, dim3(gp > 0 ? gp : 1), dim3(256), 0, s, n, keyrank, offsets, tab_off, tab,
+                           tg.cells, prev ? (const uint32_t *)own : nullptr, srcidx);
+    }
     hipLaunchKernelGGL((k_sort_gather<T>), dim3(gp > 0 ? gp : 1), dim3(256), 0, s, src, tmp, n, srcidx);
     if (sorted_out) {  // the next kernel reads the reordered copy and writes w's arrays
         *sorted_out = w;

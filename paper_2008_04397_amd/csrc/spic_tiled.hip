@@ -238,6 +238,121 @@ __device__ __forceinline__ void deposit_balanced(const GridT<TA> &ga, const Tile
     wave_sync();  // the stage is rewritten by the next call
 }
 
+// Variant 4: segmented wave pre-reduction of the deposit.  In cell-major
+// order a wave's lanes mostly hold particles of one cell; lanes whose moved
+// particles sit in the same region cell, in consecutive lanes, form a
+// segment, and the 80 contributions (8 corners x 10 moments) are summed
+// over each segment by an inclusive segmented scan across the wave (DPP row
+// shifts and row broadcasts, FP64), after which only each segment's last
+// lane issues the LDS atomics: 80 atomic instructions per wave, each with a
+// handful of active lanes on distinct words, instead of 80 per particle
+// lane with bank conflicts.  All 64 lanes must be active.
+namespace seg {
+// DPP controls (GFX9 encoding): row shift right by 1/2/4/8 lanes, and the
+// broadcasts of lane 15 of each row to the next row / of lane 31 to rows 2-3
+constexpr int kShr1 = 0x111, kShr2 = 0x112, kShr4 = 0x114, kShr8 = 0x118, kBcast15 = 0x142, kBcast31 = 0x143;
+constexpr int kWaveShr1 = 0x138;  // whole-wave shift right by one lane
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Which of the six scan steps may add the source lane's partial sum: the
+// source lane lies in this lane's segment.
+struct Steps {
+    bool s1, s2, s4, s8, b15, b31;
+};
+
+__device__ __forceinline__ Steps steps_for(int lane, int start) {
+    Steps t;
+    const int r = lane & 15, row = lane >> 4;
+    t.s1 = r >= 1 && lane - 1 >= start;
+    t.s2 = r >= 2 && lane - 2 >= start;
+    t.s4 = r >= 4 && lane - 4 >= start;
+    t.s8 = r >= 8 && lane - 8 >= start;
+    t.b15 = (row == 1 || row == 3) && 16 * row - 1 >= start;
+    t.b31 = row >= 2 && 31 >= start;
+    return t;
+}
+
+// Inclusive segmented scan of N values at once (N independent chains keep
+// the VALU busy between the dependent DPP steps).
+template <int N>
+__device__ __forceinline__ void scan(double (&v)[N], const Steps &t) {
+    double x[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = dpp<kShr1, 0xF>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += t.s1 ? x[i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = dpp<kShr2, 0xF>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += t.s2 ? x[i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = dpp<kShr4, 0xF>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += t.s4 ? x[i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = dpp<kShr8, 0xF>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += t.s8 ? x[i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = dpp<kBcast15, 0xA>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += t.b15 ? x[i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = dpp<kBcast31, 0xC>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += t.b31 ? x[i] : 0.0;
+}
+}  // namespace seg
+
+template <typename TA, class GEO>
+__device__ __forceinline__ void deposit_segmented(const GridT<TA> &ga, const TileGeom &tg, int ox, int oy, int oz,
+                                                  TA *__restrict__ ml, TA *__restrict__ mom, int nn, int lane,
+                                                  bool valid, TA x, TA y, TA z, TA qa, TA ua, TA va, TA wa) {
+    const int RNP = tg.rnp, sx = tg.sx, sy = tg.sy, sz = tg.sz;
+    int rb = 0;
+    Cell<TA> c;
+    c.fx = c.fy = c.fz = TA(0);
+    bool in = false;
+    if (valid) {
+        in = region_locate(ga, tg, ox, oy, oz, x, y, z, rb, c);
+        if (!in)  // rare: outside the region, straight to the global moments
+            deposit_one<TA, GEO>(ga, tg, ox, oy, oz, ml, mom, nn, x, y, z, qa, ua, va, wa);
+    }
+    // segments: runs of consecutive lanes in the same region cell; lanes
+    // without an LDS deposit get a key of their own
+    const int key = in ? rb : -1 - lane;
+    const int left = __builtin_amdgcn_update_dpp(-1 - 64, key, seg::kWaveShr1, 0xF, 0xF, false);
+    const unsigned long long heads = __ballot(lane == 0 || left != key);
+    const unsigned long long upto = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1));
+    const int start = 63 - __clzll(upto);
+    const bool tail = lane == 63 || ((heads >> (lane + 1)) & 1ull);
+    const seg::Steps st = seg::steps_for(lane, start);
+    TA wt8[8];
+    pweights(c.fx, c.fy, c.fz, wt8);
+    const TA q0 = in ? qa : TA(0);
+    const TA val[10] = {TA(1), ua, va, wa, ua * ua, ua * va, ua * wa, va * va, va * wa, wa * wa};
+    const int coff[8] = {0, sx, sy, sx + sy, sz, sx + sz, sy + sz, sx + sy + sz};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const TA qw = q0 * wt8[k];
+        double sum[10];
+#pragma unroll
+        for (int m = 0; m < 10; ++m) sum[m] = (double)(qw * val[m]);
+        seg::scan(sum, st);
+        if (in && tail) {
+#pragma unroll
+            for (int m = 0; m < 10; ++m) atomicAdd(ml + rb + coff[k] + m * RNP, (TA)sum[m]);
+        }
+    }
+}
+
 // LDS bytes of the per-wave staging of variants 2 (queue) and 3 (balance).
 constexpr int kQueueCap = 128;  // variant 2: at most 63 wait between drains, one iteration adds <= 64
 inline size_t stage_lds_bytes(int variant, int block, int dtype) {
@@ -257,6 +372,7 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
     constexpr bool HOME = VAR == 2;   // home-cell registers + queue of drifted particles
     constexpr bool CACHE = VAR == 1;  // field corners of the last cell in registers
     constexpr bool BAL = VAR == 3;    // bank-balanced deposit
+    constexpr bool SEG = VAR == 4;    // segmented wave pre-reduction of the deposit
     const GridT<TP> &g = J.g;
     TileGeom tg = J.tg;
     if constexpr (GEO::fixed) {  // the host launches this only for a matching tiling
@@ -427,7 +543,7 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
                     } else {
                         enq = true;  // another cell, or outside the region
                     }
-                } else if constexpr (!BAL) {
+                } else if constexpr (!BAL && !SEG) {
                     deposit_one<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, (TA)xn, (TA)yn, (TA)zn, qa, ua, va, wa);
                 }
             }
@@ -436,6 +552,11 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
             if (mom)
                 deposit_balanced<TP, TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, stage, bal, lane, valid, xn, yn, zn,
                                               un, vn, wn, qp);
+        }
+        if constexpr (SEG) {
+            if (mom)
+                deposit_segmented<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, lane, valid, (TA)xn, (TA)yn, (TA)zn,
+                                           (TA)qp, (TA)un, (TA)vn, (TA)wn);
         }
         if constexpr (HOME) {
             // queue the drifted particles of this iteration; once 64 wait,
@@ -500,9 +621,10 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
 //   2  home-cell register accumulation of the deposit (80 sums) with LDS
 //      atomics for drifted particles; <= 256 VGPRs, 2 waves/SIMD
 //   3  as 0, with the bank-balanced deposit (per-wave staging in LDS)
+//   4  segmented wave pre-reduction of the deposit (cell-major sort order)
 template <int VAR>
 struct VariantWaves {
-    static constexpr int value = (VAR == 0 || VAR == 3) ? 4 : (VAR == 1 ? 3 : 2);
+    static constexpr int value = (VAR == 0 || VAR == 3 || VAR == 4) ? 4 : (VAR == 1 ? 3 : 2);
 };
 
 template <typename TP, typename TF, typename TA, int VAR, class GEO>
@@ -566,6 +688,7 @@ static void tiled_variant(const TileJob<TP, TF, TA> &job, int chunk, size_t lds,
         case 1: tiled_launch<TP, TF, TA, 1, GEO>(job, chunk, lds, cfg.tile_block, s); break;
         case 2: tiled_launch<TP, TF, TA, 2, GEO>(job, chunk, lds, cfg.tile_block, s); break;
         case 3: tiled_launch<TP, TF, TA, 3, GEO>(job, chunk, lds, cfg.tile_block, s); break;
+        case 4: tiled_launch<TP, TF, TA, 4, GEO>(job, chunk, lds, cfg.tile_block, s); break;
         default: tiled_launch<TP, TF, TA, 0, GEO>(job, chunk, lds, cfg.tile_block, s);
     }
 }
@@ -658,6 +781,7 @@ static int worklist_groups_v(int variant, size_t lds, int block, int nitems, int
         case 1: return worklist_groups_t<TP, TF, TA, 1, GEO>(lds, block, nitems, max_groups);
         case 2: return worklist_groups_t<TP, TF, TA, 2, GEO>(lds, block, nitems, max_groups);
         case 3: return worklist_groups_t<TP, TF, TA, 3, GEO>(lds, block, nitems, max_groups);
+        case 4: return worklist_groups_t<TP, TF, TA, 4, GEO>(lds, block, nitems, max_groups);
         default: return worklist_groups_t<TP, TF, TA, 0, GEO>(lds, block, nitems, max_groups);
     }
 }
@@ -691,6 +815,7 @@ static hipError_t worklist_v(int variant, const void *jobs, const uint2 *items, 
         case 1: return worklist_t<TP, TF, TA, 1, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
         case 2: return worklist_t<TP, TF, TA, 2, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
         case 3: return worklist_t<TP, TF, TA, 3, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
+        case 4: return worklist_t<TP, TF, TA, 4, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
         default: return worklist_t<TP, TF, TA, 0, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
     }
 }

@@ -60,11 +60,13 @@ def spic_to_host(s):
     return {k: v.detach().cpu().numpy() for k, v in s.items()}
 
 
-def test_resident_runs_together_match_oracle(spic):
+@pytest.mark.parametrize("variant", [0, 4])
+def test_resident_runs_together_match_oracle(spic, variant):
     ctx = spic.Context(0)
+    ctx.set_option("tile_variant", variant)
     boxes = _boxes()
     runs, inputs = zip(*[_run_of(spic, h, 4) for h in boxes])
-    _say("case batch resident 3 boxes x 4 steps")
+    _say("case batch resident 3 boxes x 4 steps, variant %d" % variant)
     tickets = spic.spic_batch_submit(ctx, runs)
     for t in tickets:
         assert spic.spic_wait(ctx, t) >= 0.0

@@ -90,6 +90,29 @@ def test_sort_permutes_into_tile_rank_major_order(spic, ctx, dtype):
             assert np.array_equal(blk, np.flatnonzero(counts > r)), (t, r)
 
 
+def test_sort_cell_major_for_the_segmented_variant(spic, ctx):
+    """With tile_variant 4 the sort lays a tile's particles out cell by cell
+    (the segmented deposit wants a wave's lanes in one cell); a second sort
+    (ordered key pass) keeps that order and still only permutes."""
+    h = W.harris_32x16x4()
+    sp = W.make_species(h, W.SHEET_E)
+    perm = np.random.default_rng(2).permutation(sp["x"].size)
+    sp = {k: v[perm] for k, v in sp.items()}
+    dev = spic.to_device(sp, torch.float64)
+    ctx.set_option("tile_variant", 4)
+    _say("case sort cell-major harris_32x16x4 sheet_e")
+    for _ in range(2):
+        spic.spic_sort(ctx, h.grid, [dev])
+        torch.cuda.synchronize()
+        out = spic.to_host(dev)
+        a, b = P.by_id(out), P.by_id(sp)
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
+        tile_id, local = _keys_np(h.grid, out, (4, 4, 4))
+        key = tile_id * 64 + local
+        assert np.all(np.diff(key) >= 0), "not cell-major"
+
+
 def _oracle_steps(h, f, sps, qoms, nsteps):
     st = [dict(s) for s in sps]
     ms = None
@@ -115,7 +138,7 @@ def _gpu_steps(spic, ctx, h, f, sps, qoms, nsteps, dtype=torch.float64, sort_eve
     return [spic.to_host(d) for d in dev], [m.cpu().numpy() for m in moms]
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 def test_tiled_fp64_every_step_matches_oracle(spic, ctx, variant):
     """32x16x4 cells, 4 species, 10 steps, sorted every 4 steps; with and
     without home-cell register accumulation of the deposit."""
@@ -135,7 +158,7 @@ def test_tiled_fp64_every_step_matches_oracle(spic, ctx, variant):
     _gpu_steps(spic, ctx, h, f, sps, h.qoms, 10, check=check)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 def test_tiled_fp32_one_step(spic, ctx, variant):
     ctx.set_option("tile_variant", variant)
     h = W.harris_32x16x4()
@@ -153,7 +176,8 @@ def test_tiled_fp32_one_step(spic, ctx, variant):
 @pytest.mark.parametrize("tile,halo,variant", [((4, 4, 4), 0, 0), ((4, 4, 4), 0, 2), ((2, 4, 8), 1, 1),
                                                ((3, 3, 3), 1, 2), ((2, 2, 2), 2, 3), ((2, 8, 4), 1, 2),
                                                ((4, 4, 2), 1, 1), ((4, 4, 4), 1, 3), ((4, 4, 4), 0, 3),
-                                               ((3, 2, 4), 2, 3)])
+                                               ((3, 2, 4), 2, 3), ((4, 4, 4), 0, 4), ((2, 4, 8), 1, 4),
+                                               ((3, 3, 3), 2, 4)])
 def test_tile_shapes_and_halo_overflow_match_oracle(spic, ctx, tile, halo, variant):
     """Fast particles leave small regions (halo 0) -> global fallbacks; tile
     shapes that do not divide the grid leave ragged edge tiles."""
@@ -173,13 +197,15 @@ def test_tile_shapes_and_halo_overflow_match_oracle(spic, ctx, tile, halo, varia
         P.assert_moments(ms[s], oms[s], P.MOM64)
 
 
+@pytest.mark.parametrize("variant", [0, 4])
 @pytest.mark.parametrize("cells", [(5, 3, 2), (2, 2, 2), (9, 7, 5)])
-def test_tiny_and_odd_grids(spic, ctx, cells):
+def test_tiny_and_odd_grids(spic, ctx, cells, variant):
     """Grids smaller than one LDS region: periodic images alias inside it."""
+    ctx.set_option("tile_variant", variant)
     h = W.Harris(W.Grid(*cells, 3.0, 2.0, 1.0), ppc=8)
     f = W.make_fields(h)
     sps = [W.make_species(h, s) for s in range(4)]
-    _say("case tiny grid %s" % (cells,))
+    _say("case tiny grid %s variant %d" % (cells, variant))
     st, ms = _gpu_steps(spic, ctx, h, f, sps, h.qoms, 3, sort_every=1)
     ora, oms = _oracle_steps(h, f, sps, h.qoms, 3)
     for s in range(4):
