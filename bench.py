@@ -7,7 +7,7 @@ analytic fields.  One step = the fused mover + moment pass over every
 species (plus the cell sort at its cadence).  The headline `value` is the
 FP32-particle / FP64-moment path; the FP64 path is reported beside it.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64] [--no-cpu] [--tune]
 Prints one JSON line.
 
 Other measured configurations (one JSON line each):
@@ -20,6 +20,9 @@ Other measured configurations (one JSON line each):
                     particles in pinned host memory) streamed through a 16 GB
                     HBM budget in batches of 2^26, sort every 4 steps, 5 steps
                     (--fraction f keeps the first f of the x-slabs)
+  --mode cadence    the 128x64x32 box for --steps steps (e.g. 500) with a sort
+                    only at step 0 and every 1, 4 and 10 steps: throughput
+                    per window of steps (how fast locality decays)
   --mode serving    Poisson arrivals (20/s) of Harris-box runs (16x8x4 ..
                     256x128x8 cells, ppc 8..64, 10..200 steps), continuous
                     batching vs one-at-a-time on the same GPU, p50/p99 latency
@@ -55,7 +58,7 @@ KERNEL_SOURCES = ("paper_2008_04397_amd/csrc/spic_tiled.hip", "paper_2008_04397_
                   "paper_2008_04397_amd/csrc/spic_impl.h")
 
 
-def measured_traffic(tuned) -> Optional[float]:
+def measured_traffic(launch) -> Optional[float]:
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
     FETCH_SIZE/WRITE_SIZE summary, or None when the kernel sources changed
     since the counters were taken or the launch configuration differs."""
@@ -68,9 +71,8 @@ def measured_traffic(tuned) -> Optional[float]:
     if fields.get("kernel_source_sha256", "").strip() != h:
         return None
     cfg = fields.get("config", "")
-    want = {"tile_variant": 0, "tile_block": 512, "bank_align": 1, "sort_every": 4}
-    got = {k: int(v) for k, v in re.findall(r"(\w+) (\d+)", cfg)}
-    if tuned is not None and any(tuned.get(k) != got.get(k) for k in want):
+    profiled = {k: int(v) for k, v in re.findall(r"(\w+) (\d+)", cfg)}
+    if any(launch.get(k) != profiled.get(k) for k in ("tile_variant", "tile_block", "bank_align", "sort_every")):
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -118,6 +120,12 @@ def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: 
         sort_every = 4
     if variant >= 0:
         ctx.set_option("tile_variant", variant)
+    launch = {k: ctx.get_option(k) for k in ("tile_variant", "tile_block", "bank_align", "sort_ordered", "halo")}
+    # unset options take the library defaults
+    dflt = {"tile_variant": 0, "tile_block": 512, "bank_align": 1 if dtype_name == "f32" else 0,
+            "sort_ordered": 1, "halo": 1}
+    launch = {k: (v if v >= 0 else dflt[k]) for k, v in launch.items()}
+    launch["sort_every"] = sort_every
 
     def step(k, ev=None):
         prm = spic.make_params(h.dt, h.c, h.niter, sort_every, k)
@@ -160,16 +168,13 @@ def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: 
     avg_launch_s = float(fused_ms.mean()) / 1e3
     achieved = per_launch_bytes / avg_launch_s / 1e9
     # measured HBM bytes of the same launches (rocprofv3 counters, profiles/)
-    traffic_bytes = measured_traffic(tuned if tuned is not None else {"tile_variant": variant if variant >= 0 else 0,
-                                                                      "tile_block": 512, "bank_align": 1,
-                                                                      "sort_every": sort_every}) \
-        if dtype_name == "f32" and not path else None
+    traffic_bytes = measured_traffic(launch) if dtype_name == "f32" and not path else None
     traffic = traffic_bytes / avg_launch_s / 1e9 if traffic_bytes else None
     step_ms = total_ms / steps
     per_step = launch_ms.sum(axis=1)
     sort_ms = float(launch_ms[sort_step].mean() - fused_ms.mean()) if sort_step.any() else 0.0
     return {
-        "tuned": tuned, "sort_every": sort_every,
+        "tuned": tuned, "sort_every": sort_every, "launch": launch,
         "value": n * steps / (total_ms / 1e3),
         "ms_per_step": step_ms,
         "ms_per_step_mean": float(per_step.mean()),
@@ -311,6 +316,49 @@ def bench_streamed(args):
                                  "nominal 64 GB/s per direction"}}
 
 
+def bench_cadence(args):
+    """Long-run sort-cadence study on the 128x64x32 box (FP32): throughput
+    per window of steps for a sort only at step 0 and for sorts every 1, 4
+    and 10 steps (Sec. VI: locality decays without re-sorting)."""
+    import torch
+    from paper_2008_04397_amd import spic
+    h = W.harris_128x64x32()
+    g = h.grid
+    nsteps, window = args.steps, max(1, args.steps // 10)
+    f = spic.to_device(W.make_fields(h), torch.float32)
+    moms = spic.moment_buffers(g, 4, torch.float64)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for cad in ("once", 1, 4, 10):
+        species = [spic.to_device(W.make_species(h, s, dtype=np.float32, with_id=False), torch.float32)
+                   for s in range(4)]
+        ctx = spic.Context(0)
+        if cad == "once":
+            spic.spic_sort(ctx, g, species, stream=stream)
+        se = 0 if cad == "once" else cad
+        rates = []
+        for w0 in range(0, nsteps, window):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for k in range(w0, min(nsteps, w0 + window)):
+                spic.spic_mover(ctx, g, spic.make_params(h.dt, h.c, h.niter, se, k), f, species, h.qoms, moms,
+                                stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            n = min(nsteps, w0 + window) - w0
+            rates.append(h.n_total * n / (a.elapsed_time(b) / 1e3))
+            log("[cadence %s] steps %d-%d: %.3e particle-steps/s" % (cad, w0, w0 + n - 1, rates[-1]))
+        out[str(cad)] = rates
+        ctx.close()
+        del species
+        torch.cuda.empty_cache()
+    return {"metric": METRIC, "mode": "cadence", "value": float(np.mean(out["4"])), "unit": "particle-steps/s",
+            "n_gpus": 1, "steps": nsteps, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "harris_128x64x32_ppc64_4species", "window_steps": window,
+                       "cadences": ["sort at step 0 only", 1, 4, 10]},
+            "rates_per_window": out}
+
+
 def bench_serving(args):
     """Poisson request stream: continuous batching vs one at a time."""
     import torch
@@ -342,10 +390,13 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--sort-every", type=int, default=-1, help="-1: the autotuned cadence")
-    ap.add_argument("--mode", default="main", choices=("main", "ensemble", "streamed", "serving"))
+    ap.add_argument("--mode", default="main", choices=("main", "ensemble", "streamed", "serving", "cadence"))
     ap.add_argument("--fraction", type=float, default=1.0)
     ap.add_argument("--requests", type=int, default=120)
-    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune block size, variant, layout and cadence first (cached per workload class); "
+                         "the default uses the library defaults, which are the measured best on MI355X")
+    ap.add_argument("--no-tune", action="store_true", help="(default) use the library defaults")
     ap.add_argument("--variant", type=int, default=-1, help="tiled kernel variant (-1: autotuned)")
     ap.add_argument("--path", type=int, default=0)
     ap.add_argument("--no-fp64", action="store_true")
@@ -364,18 +415,20 @@ def main():
     from paper_2008_04397_amd import spic
     spic.lib()  # fail loudly if the HIP library is missing
     if args.mode != "main":
-        out = {"ensemble": bench_ensemble, "streamed": bench_streamed, "serving": bench_serving}[args.mode](args)
+        out = {"ensemble": bench_ensemble, "streamed": bench_streamed, "serving": bench_serving,
+               "cadence": bench_cadence}[args.mode](args)
         print(json.dumps(out), flush=True)
         return
 
     h = W.harris_128x64x32()
-    r32 = run_gpu(h, "f32", args.steps, args.warmup, args.sort_every, args.path, tune=not args.no_tune,
+    tune = args.tune and not args.no_tune
+    r32 = run_gpu(h, "f32", args.steps, args.warmup, args.sort_every, args.path, tune=tune,
                   variant=args.variant)
     log("[bench] f32: %.3e particle-steps/s, %.3f ms/step, %.1f%% HBM" %
         (r32["value"], r32["ms_per_step"], 100 * r32["roofline"]["frac"]))
     r64 = None
     if not args.no_fp64:
-        r64 = run_gpu(h, "f64", args.steps, args.warmup, args.sort_every, args.path, tune=not args.no_tune,
+        r64 = run_gpu(h, "f64", args.steps, args.warmup, args.sort_every, args.path, tune=tune,
                       variant=args.variant)
         log("[bench] f64: %.3e particle-steps/s, %.3f ms/step, %.1f%% HBM" %
             (r64["value"], r64["ms_per_step"], 100 * r64["roofline"]["frac"]))
@@ -400,7 +453,8 @@ def main():
         "config": {"workload": "harris_128x64x32_ppc64_4species", "cells": [128, 64, 32],
                    "particles": h.n_total, "species": 4, "ppc": 64, "niter_mover": h.niter, "dt": h.dt,
                    "precision": "f32 particles and mover, f64 moment accumulation",
-                   "sort_every": r32["sort_every"], "path": args.path or "auto", "tuned": r32["tuned"]},
+                   "sort_every": r32["sort_every"], "path": args.path or "auto", "launch": r32["launch"],
+                   "tuned": r32["tuned"]},
         "roofline": r32["roofline"],
         "cpu_baseline": cpu,
         "ms_per_step_stats": {k: r32[k] for k in ("ms_per_step_mean", "ms_per_step_std", "ms_per_step_median",
@@ -408,7 +462,8 @@ def main():
     }
     if r64 is not None:
         out["fp64"] = {"value": r64["value"], "unit": "particle-steps/s", "dtype": "f64",
-                       "ms_per_step": r64["ms_per_step"], "roofline": r64["roofline"], "tuned": r64["tuned"],
+                       "ms_per_step": r64["ms_per_step"], "roofline": r64["roofline"], "launch": r64["launch"],
+                       "tuned": r64["tuned"],
                        "sort_every": r64["sort_every"]}
     if args.copy_calibration:
         # 2^28 FP32 = 1 GiB read + 1 GiB written by one copy kernel
