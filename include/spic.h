@@ -187,7 +187,11 @@ int spic_version(void);
  *   max_groups     batch engine: cap on workgroups of the persistent launch
  *   tick_items     batch engine: a tick steps the runs with the least
  *                  remaining work until it holds this many (run, species,
- *                  tile) items (default 4096; 0 = every active run) */
+ *                  tile) items (default 4096; 0 = every active run)
+ *   srpt_aging     batch engine: remaining work is credited this many
+ *                  million particle-steps per second since submission, so
+ *                  long runs are not starved by a stream of short ones
+ *                  (default 10000; 0 = pure least-remaining-work) */
 int spic_set_option(spic_ctx ctx, const char *key, int64_t value);
 int spic_get_option(spic_ctx ctx, const char *key, int64_t *value);
 
@@ -227,8 +231,9 @@ int spic_sort(spic_ctx ctx, const spic_grid *grid, spic_species *sp, int32_t nsp
  * Queued runs are admitted, in submission order, as soon as their HBM
  * footprint fits the ctx's budget (host_resident species are uploaded on
  * admission and copied back on completion).  Each tick advances admitted
- * runs by one step -- those with the least remaining work first, until the
- * tick holds `tick_items` (run, species, tile) items -- in one launch per
+ * runs by one step -- those with the least remaining work (less the
+ * `srpt_aging` credit for time waited) first, until the tick holds
+ * `tick_items` (run, species, tile) items -- in one launch per
  * precision combination.  A host_resident run larger than the budget, or
  * with a species of 4 GiB or more per array, is streamed through HBM in
  * batches on two streams (copy of the next batch overlapping the kernel on

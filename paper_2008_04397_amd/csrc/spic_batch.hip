@@ -108,6 +108,7 @@ struct RunState {
     int status = SPIC_OK;
     std::string err;
     double secs = 0;
+    std::chrono::steady_clock::time_point submitted;
 
     // particle-steps still to do, and (job, tile) items of one tick
     double remaining_work() const {
@@ -151,6 +152,7 @@ struct BatchEngine {
     // tuning, read from the ctx options when the engine starts
     int tile_block = 512, variant = 0, use_graph = 1, max_groups = 0, fixed_geo = 1, sort_ordered = 1;
     int64_t tick_items = 4096;  // 0: every active run steps at every tick
+    double srpt_aging = 1e10;   // particle-steps of credit per second waited
     int64_t batch_particles = (int64_t)1 << 26;
     LaunchCfg lcfg;
 
@@ -252,6 +254,7 @@ struct BatchEngine {
             std::lock_guard<std::mutex> lk(mu);
             for (size_t i = 0; i < made.size(); ++i) {
                 made[i]->ticket = next_ticket++;
+                made[i]->submitted = std::chrono::steady_clock::now();
                 tickets[i] = made[i]->ticket;
                 all[made[i]->ticket] = made[i];
                 queued.push_back(made[i]);
@@ -613,23 +616,35 @@ struct BatchEngine {
     // Streamed run: batches of at most nb particles through two slots.
     void stream_run(RunState &r);
 
-    // The runs the next tick steps: shortest remaining work first, until the
+    // The runs the next tick steps: least remaining work first, until the
     // tick holds tick_items (job, tile) items -- enough to fill the GPU -- so
     // that short requests finish first instead of being slowed down by every
-    // long run they share the GPU with.  Returned in ticket order, so an
-    // unchanged set replays its graph.
+    // long run they share the GPU with.  Pure shortest-first starves a long
+    // run for as long as shorter ones keep arriving, so each run's remaining
+    // work is credited srpt_aging particle-steps per second since it was
+    // submitted: with the credit rate near the engine's throughput, a run
+    // that has waited about as long as it takes to serve alone overtakes any
+    // newcomer.  Returned in ticket order, so an unchanged set replays its
+    // graph.
     std::vector<std::shared_ptr<RunState>> pick(const std::vector<std::shared_ptr<RunState>> &all) const {
         if (tick_items <= 0 || all.size() <= 1) return all;
-        std::vector<std::shared_ptr<RunState>> v(all), out;
-        std::stable_sort(v.begin(), v.end(), [](const std::shared_ptr<RunState> &a,
-                                                const std::shared_ptr<RunState> &b) {
-            return a->remaining_work() < b->remaining_work();
+        const auto now = std::chrono::steady_clock::now();
+        std::vector<std::pair<double, std::shared_ptr<RunState>>> v;
+        v.reserve(all.size());
+        for (auto &r : all) {
+            const double waited = std::chrono::duration<double>(now - r->submitted).count();
+            v.emplace_back(r->remaining_work() - srpt_aging * waited, r);
+        }
+        std::stable_sort(v.begin(), v.end(), [](const std::pair<double, std::shared_ptr<RunState>> &a,
+                                                const std::pair<double, std::shared_ptr<RunState>> &b) {
+            return a.first < b.first;
         });
+        std::vector<std::shared_ptr<RunState>> out;
         int64_t items = 0;
-        for (auto &r : v) {
+        for (auto &e : v) {
             if (!out.empty() && items >= tick_items) break;
-            out.push_back(r);
-            items += r->tick_items();
+            out.push_back(e.second);
+            items += e.second->tick_items();
         }
         std::sort(out.begin(), out.end(), [](const std::shared_ptr<RunState> &a, const std::shared_ptr<RunState> &b) {
             return a->ticket < b->ticket;
@@ -838,6 +853,7 @@ int spic_ctx_s::batch_submit(const spic_run *runs, int32_t nruns, uint64_t *tick
         batch->batch_particles = opt("batch_particles", (int64_t)1 << 26);
         batch->max_groups = (int)opt("max_groups", 0);
         batch->tick_items = opt("tick_items", 4096);
+        batch->srpt_aging = 1e6 * (double)opt("srpt_aging", 10000);
         batch->lcfg = launch_cfg();
         int rc = batch->start();
         if (rc) {

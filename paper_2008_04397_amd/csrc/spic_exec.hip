@@ -34,11 +34,15 @@ std::string spic_ctx_s::layout_key(const spic_grid &g, const spic_species &s) co
 // The bank-preserving layout pays off for FP32 particles; FP64 particles
 // keep the compact one (two workgroups per CU) unless bank_align is set.
 // The segmented-deposit variant wants cell-major order (its lanes share
-// cells, so no padding for bank spread either); the others rank-major.
+// cells, so no padding for bank spread either); the others rank-major.  The
+// two-phase variant deposits mostly from registers and takes the dense
+// layout (the smallest LDS footprint, more workgroups per CU).
 TileGeom spic_ctx_s::tile_geom(const spic_grid &g, int dtype) const {
-    const bool cm = opt("tile_variant", 0) == 4;
+    const int var = (int)opt("tile_variant", 0);
+    const bool cm = var == 4;
+    const int dflt = var == 6 ? 2 : (dtype == SPIC_F64 || cm) ? 0 : 1;
     return make_tile_geom(g, (int)opt("tile_x", 4), (int)opt("tile_y", 4), (int)opt("tile_z", 4),
-                          (int)opt("halo", 1), opt("bank_align", (dtype == SPIC_F64 || cm) ? 0 : 1) != 0, cm);
+                          (int)opt("halo", 1), (int)opt("bank_align", dflt), cm);
 }
 
 

@@ -90,17 +90,27 @@ struct TileGeom {
 // cells hits the 16 pairs as evenly as possible, for every corner, (2)
 // preferably the slow stride P_mid * P_fast is a multiple of 16, so that a
 // particle that drifted one cell along the slow axis keeps its bank pair,
-// and (3) the region has the fewest slots (without (2) when prefer_align is
-// false: the compact layout keeps two FP64 workgroups per CU).  constexpr so
+// and (3) the region has the fewest slots (without (2) for layout 0: the
+// compact layout keeps two FP64 workgroups per CU).  Layout 2 is dense (no
+// padding, bank spread ignored): for the kernels that deposit most of their
+// moments from registers and want the smallest LDS footprint.  constexpr so
 // that kernels specialised for one tiling use the same layout as the host.
 struct RegionLayout {
     int sx, sy, sz, rnp;
 };
 
 constexpr RegionLayout region_layout(int tx, int ty, int tz, int halo, int slow, int mid, int fast,
-                                     bool prefer_align = true) {
+                                     int layout = 1) {
     const int t[3] = {tx, ty, tz};
     const int r[3] = {tx + 2 * halo + 1, ty + 2 * halo + 1, tz + 2 * halo + 1};
+    if (layout == 2) {
+        int st[3] = {0, 0, 0};
+        st[fast] = 1;
+        st[mid] = r[fast];
+        st[slow] = r[mid] * r[fast];
+        return RegionLayout{st[0], st[1], st[2], r[0] * r[1] * r[2]};
+    }
+    const bool prefer_align = layout == 1;
     const int cells = tx * ty * tz;
     int best_w = 1 << 30, best_a = 2, best_n = 1 << 30, bpm = r[mid], bpf = r[fast];
     for (int pm = r[mid]; pm < r[mid] + 9; ++pm)
@@ -151,30 +161,34 @@ struct GeoRuntime {
                          sx = 0, sy = 0, sz = 0, rnp = 0;
 };
 
-template <int TX, int TY, int TZ, int HALO, int SLOW, int MID, int FAST>
+template <int TX, int TY, int TZ, int HALO, int SLOW, int MID, int FAST, int LAYOUT = 1>
 struct GeoFixed {
     static constexpr bool fixed = true;
     static constexpr int tx = TX, ty = TY, tz = TZ, halo = HALO, slow = SLOW, mid = MID, fast = FAST;
     static constexpr int rx = TX + 2 * HALO + 1, ry = TY + 2 * HALO + 1, rz = TZ + 2 * HALO + 1;
-    static constexpr RegionLayout lay = region_layout(TX, TY, TZ, HALO, SLOW, MID, FAST);
+    static constexpr RegionLayout lay = region_layout(TX, TY, TZ, HALO, SLOW, MID, FAST, LAYOUT);
     static constexpr int sx = lay.sx, sy = lay.sy, sz = lay.sz, rnp = lay.rnp;
 };
 
 // 4x4x4 tiles, halo 1, z slowest (the Harris boxes have their finest cells
 // along z, which particles cross most often)
 using GeoDefault = GeoFixed<4, 4, 4, 1, 2, 0, 1>;
+// the same tiling with the dense layout
+using GeoDense = GeoFixed<4, 4, 4, 1, 2, 0, 1, 2>;
 
 // The tiled kernels address particle arrays with 32-bit byte offsets.
 inline bool tiled_fits(int64_t n, int dtype) {
     return n >= 0 && (uint64_t)n * (dtype == SPIC_F64 ? 8u : 4u) < ((uint64_t)1 << 32);
 }
 
-inline bool geo_is_default(const TileGeom &t) {
-    return t.tx == GeoDefault::tx && t.ty == GeoDefault::ty && t.tz == GeoDefault::tz &&
-           t.halo == GeoDefault::halo && t.slow == GeoDefault::slow && t.mid == GeoDefault::mid &&
-           t.fast == GeoDefault::fast && t.sx == GeoDefault::sx && t.sy == GeoDefault::sy &&
-           t.sz == GeoDefault::sz && t.rnp == GeoDefault::rnp;
+template <class GEO>
+inline bool geo_is(const TileGeom &t) {
+    return t.tx == GEO::tx && t.ty == GEO::ty && t.tz == GEO::tz && t.halo == GEO::halo && t.slow == GEO::slow &&
+           t.mid == GEO::mid && t.fast == GEO::fast && t.sx == GEO::sx && t.sy == GEO::sy && t.sz == GEO::sz &&
+           t.rnp == GEO::rnp;
 }
+
+inline bool geo_is_default(const TileGeom &t) { return geo_is<GeoDefault>(t); }
 
 template <typename T>
 inline GridT<T> make_grid_t(const spic_grid &g) {
@@ -277,7 +291,7 @@ hipError_t launch_deposit_generic(const spic_grid &g, const SpeciesWork &w, cons
                                   hipStream_t s);
 
 // Sort (spic_sort.hip).
-TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo, bool align = true,
+TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo, int layout = 1,
                         bool cellmajor = false);
 size_t sort_scratch_bytes(int64_t n, int dtype, bool with_id, const TileGeom &tg);
 // prev: tile_off already holds the per-tile ranges of the particles'

@@ -192,11 +192,13 @@ static const char *const kOptionNames[] = {
                     // 3 bank-balanced LDS deposit, 4 segmented wave pre-reduction (cell-major order)
     "fixed_geo",    // tiled kernel: 1 = compile-time region geometry for 4x4x4 tiles, halo 1
     "sort_ordered", // sort: 1 = ranks follow the previous order (a sorted species' tiles walked in order)
-    "bank_align",   // tiled kernel: 1 = LDS layout whose slow-axis stride keeps bank pairs (more slots)
+    "bank_align",   // tiled kernel LDS layout: 0 compact conflict-free, 1 + slow-axis stride keeps bank pairs,
+                    // 2 dense (no padding)
     "graph",        // batch engine: 1 = replay unchanged ticks as a hipGraph
     "batch_particles",  // batch engine: particles per streamed batch (upper bound)
     "max_groups",   // batch engine: cap on workgroups of the persistent launch (0 = occupancy)
     "tick_items",   // batch engine: (job, tile) items per tick, shortest runs first (0 = all runs)
+    "srpt_aging",   // batch engine: credit, in M particle-steps per second waited, against starvation
 };
 
 int64_t spic_ctx_s::opt(const char *k, int64_t dflt) const {
@@ -283,15 +285,18 @@ int spic_set_option(spic_ctx ctx, const char *key, int64_t value) {
             if ((!strcmp(key, "tile_x") || !strcmp(key, "tile_y") || !strcmp(key, "tile_z")) &&
                 (value < 1 || value > 64))
                 return ctx->fail(SPIC_E_ARG, "tile sizes must be in [1, 64]");
-            if (!strcmp(key, "tile_variant") && (value < 0 || value > 4))
-                return ctx->fail(SPIC_E_ARG, "tile_variant must be in 0..4");
+            if (!strcmp(key, "tile_variant") && (value < 0 || value > 6))
+                return ctx->fail(SPIC_E_ARG, "tile_variant must be in 0..6");
             if (!strcmp(key, "batch_particles") && (value < 1024 || value > ((int64_t)1 << 29)))
                 return ctx->fail(SPIC_E_ARG, "batch_particles must be in [1024, 2^29]");
             if (!strcmp(key, "tick_items") && (value < 0 || value > ((int64_t)1 << 30)))
                 return ctx->fail(SPIC_E_ARG, "tick_items must be in [0, 2^30]");
-            if ((!strcmp(key, "fixed_geo") || !strcmp(key, "sort_ordered") || !strcmp(key, "bank_align")) &&
-                (value < 0 || value > 1))
+            if (!strcmp(key, "srpt_aging") && (value < 0 || value > ((int64_t)1 << 40)))
+                return ctx->fail(SPIC_E_ARG, "srpt_aging must be in [0, 2^40]");
+            if ((!strcmp(key, "fixed_geo") || !strcmp(key, "sort_ordered")) && (value < 0 || value > 1))
                 return ctx->fail(SPIC_E_ARG, "%s must be 0 or 1", key);
+            if (!strcmp(key, "bank_align") && (value < 0 || value > 2))
+                return ctx->fail(SPIC_E_ARG, "bank_align must be 0, 1 or 2");
             if (!strcmp(key, "halo") && (value < 0 || value > 8))
                 return ctx->fail(SPIC_E_ARG, "halo must be in [0, 8]");
             if (!strcmp(key, "lds_max")) return ctx->fail(SPIC_E_ARG, "lds_max is read only");

@@ -336,7 +336,7 @@ __global__ void k_tile_offsets(const uint32_t *__restrict__ offsets, TileGeom tg
 
 // ------------------------------------------------------------------ host
 
-TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo, bool align, bool cellmajor) {
+TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo, int layout, bool cellmajor) {
     TileGeom t;
     t.tx = tx; t.ty = ty; t.tz = tz;
     t.cells = tx * ty * tz;
@@ -357,7 +357,7 @@ TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo, bo
     t.slow = slow;
     t.mid = slow == 0 ? 1 : 0;
     t.fast = slow == 2 ? 1 : 2;
-    const RegionLayout lay = region_layout(tx, ty, tz, halo, t.slow, t.mid, t.fast, align);
+    const RegionLayout lay = region_layout(tx, ty, tz, halo, t.slow, t.mid, t.fast, layout);
     t.sx = lay.sx;
     t.sy = lay.sy;
     t.sz = lay.sz;

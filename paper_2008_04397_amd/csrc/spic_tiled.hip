@@ -94,6 +94,16 @@ __device__ __forceinline__ void gather_lds(const LdsFieldNode<TP> *__restrict__ 
     }
 }
 
+// Ends the data flow of values loaded on a rare path inside that path.
+// Without it the compiler may sink the path's last multiply-adds into the
+// code both paths share, and the shared code then waits for every
+// outstanding global load -- including the next particle's prefetch.
+template <typename T, int N>
+__device__ __forceinline__ void settle(T (&v)[N]) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) asm volatile("" : "+v"(v[m]));
+}
+
 // Element i of a particle array through a 32-bit byte offset from the
 // array base (the host sends only species with n * sizeof(T) < 2^32 here):
 // a uniform 64-bit base plus one 32-bit offset per lane, shared by all
@@ -134,6 +144,24 @@ __device__ __forceinline__ RegionNode region_node(const TileGeom &tg, int nx, in
     return n;
 }
 
+// Ten moments of a particle whose cell left the region: global atomics
+// (terms formed in T, added in the accumulation type TA).
+template <typename T, typename TA>
+__device__ __forceinline__ void deposit_global_cell(const Cell<T> &c, TA *__restrict__ mom, int nn, T qa,
+                                                    const T val[10]) {
+    T wt8[8];
+    pweights(c.fx, c.fy, c.fz, wt8);
+    int nd[8];
+    pnodes(c, nd);
+#pragma unroll 1
+    for (int k = 0; k < 8; ++k) {
+        const T qw = qa * wt8[k];
+        TA *dst = mom + nd[k];
+#pragma unroll 1
+        for (int m = 0; m < 10; ++m) atomicAdd(dst + (size_t)m * nn, (TA)(qw * val[m]));
+    }
+}
+
 // Ten moments of one moved particle into the region accumulator with LDS
 // atomics, or into the global moments when its cell left the region.
 template <typename TA, class GEO>
@@ -145,9 +173,9 @@ __device__ __forceinline__ void deposit_one(const GridT<TA> &ga, const TileGeom 
     Cell<TA> c;
     const bool in = region_locate(ga, tg, ox, oy, oz, x, y, z, rb, c);
     const TA val[10] = {TA(1), ua, va, wa, ua * ua, ua * va, ua * wa, va * va, va * wa, wa * wa};
-    TA wt8[8];
-    pweights(c.fx, c.fy, c.fz, wt8);
     if (in) {
+        TA wt8[8];
+        pweights(c.fx, c.fy, c.fz, wt8);
         const int coff[8] = {0, sx, sy, sx + sy, sz, sx + sz, sy + sz, sx + sy + sz};
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -157,16 +185,115 @@ __device__ __forceinline__ void deposit_one(const GridT<TA> &ga, const TileGeom 
             for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, qw * val[m]);
         }
     } else {  // rare: the particle left the region
-        int nd[8];
-        pnodes(c, nd);
+        deposit_global_cell(c, mom, nn, qa, val);
+    }
+}
+
+// deposit_one with the corner loop rolled (each corner's weight formed in
+// the loop, the same products as pweights): few live registers, for the
+// variant whose 80 register sums stay live across it.
+template <typename TA, class GEO>
+__device__ __forceinline__ void deposit_lean(const GridT<TA> &ga, const TileGeom &tg, int ox, int oy, int oz,
+                                             TA *__restrict__ ml, TA *__restrict__ mom, int nn, TA x, TA y, TA z,
+                                             TA qa, TA ua, TA va, TA wa) {
+    const int RNP = tg.rnp, sx = tg.sx, sy = tg.sy, sz = tg.sz;
+    int rb;
+    Cell<TA> c;
+    const bool in = region_locate(ga, tg, ox, oy, oz, x, y, z, rb, c);
+    const TA val[10] = {TA(1), ua, va, wa, ua * ua, ua * va, ua * wa, va * va, va * wa, wa * wa};
+    if (in) {
 #pragma unroll 1
         for (int k = 0; k < 8; ++k) {
-            const TA qw = qa * wt8[k];
-            TA *dst = mom + nd[k];
-#pragma unroll 1
-            for (int m = 0; m < 10; ++m) atomicAdd(dst + (size_t)m * nn, qw * val[m]);
+            const TA wx = (k & 1) ? c.fx : TA(1) - c.fx;
+            const TA wy = (k & 2) ? c.fy : TA(1) - c.fy;
+            const TA wz = (k & 4) ? c.fz : TA(1) - c.fz;
+            const TA qw = qa * ((wx * wy) * wz);
+            TA *dst = ml + rb + (k & 1) * sx + ((k >> 1) & 1) * sy + (k >> 2) * sz;
+#pragma unroll
+            for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, qw * val[m]);
         }
+    } else {
+        deposit_global_cell(c, mom, nn, qa, val);
     }
+}
+
+// deposit_lean with the velocity products formed per corner instead of
+// held for all ten moments: fewer live registers still (the second pass of
+// the two-phase variant keeps 80 sums live across it at 4 waves per SIMD).
+template <typename TA, class GEO>
+__device__ __forceinline__ void deposit_tight(const GridT<TA> &ga, const TileGeom &tg, int ox, int oy, int oz,
+                                              TA *__restrict__ ml, TA *__restrict__ mom, int nn, TA x, TA y, TA z,
+                                              TA qa, TA ua, TA va, TA wa) {
+    const int RNP = tg.rnp, sx = tg.sx, sy = tg.sy, sz = tg.sz;
+    int rb;
+    Cell<TA> c;
+    const bool in = region_locate(ga, tg, ox, oy, oz, x, y, z, rb, c);
+    if (in) {
+#pragma unroll 1
+        for (int k = 0; k < 8; ++k) {
+            const TA wx = (k & 1) ? c.fx : TA(1) - c.fx;
+            const TA wy = (k & 2) ? c.fy : TA(1) - c.fy;
+            const TA wz = (k & 4) ? c.fz : TA(1) - c.fz;
+            const TA qw = qa * ((wx * wy) * wz);
+            TA *dst = ml + rb + (k & 1) * sx + ((k >> 1) & 1) * sy + (k >> 2) * sz;
+            atomicAdd(dst, qw * TA(1));
+            atomicAdd(dst + RNP, qw * ua);
+            atomicAdd(dst + 2 * RNP, qw * va);
+            atomicAdd(dst + 3 * RNP, qw * wa);
+            atomicAdd(dst + 4 * RNP, qw * (ua * ua));
+            atomicAdd(dst + 5 * RNP, qw * (ua * va));
+            atomicAdd(dst + 6 * RNP, qw * (ua * wa));
+            atomicAdd(dst + 7 * RNP, qw * (va * va));
+            atomicAdd(dst + 8 * RNP, qw * (va * wa));
+            atomicAdd(dst + 9 * RNP, qw * (wa * wa));
+        }
+    } else {
+        const TA val[10] = {TA(1), ua, va, wa, ua * ua, ua * va, ua * wa, va * va, va * wa, wa * wa};
+        deposit_global_cell(c, mom, nn, qa, val);
+    }
+}
+
+// deposit_lean with the terms formed in the particle precision T (FP32
+// particles: FP32 weights and products, as the register sums of the lane
+// cells) and added to the accumulation type TA.
+template <typename T, typename TA, class GEO>
+__device__ __forceinline__ void deposit_mixed(const GridT<T> &g, const TileGeom &tg, int ox, int oy, int oz,
+                                              TA *__restrict__ ml, TA *__restrict__ mom, int nn, T x, T y, T z,
+                                              T qa, T ua, T va, T wa) {
+    const int RNP = tg.rnp, sx = tg.sx, sy = tg.sy, sz = tg.sz;
+    int rb;
+    Cell<T> c;
+    const bool in = region_locate(g, tg, ox, oy, oz, x, y, z, rb, c);
+    const T val[10] = {T(1), ua, va, wa, ua * ua, ua * va, ua * wa, va * va, va * wa, wa * wa};
+    if (in) {
+#pragma unroll 1
+        for (int k = 0; k < 8; ++k) {
+            const T wx = (k & 1) ? c.fx : T(1) - c.fx;
+            const T wy = (k & 2) ? c.fy : T(1) - c.fy;
+            const T wz = (k & 4) ? c.fz : T(1) - c.fz;
+            const T qw = qa * ((wx * wy) * wz);
+            TA *dst = ml + rb + (k & 1) * sx + ((k >> 1) & 1) * sy + (k >> 2) * sz;
+#pragma unroll
+            for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, (TA)(qw * val[m]));
+        }
+    } else {
+        deposit_global_cell(c, mom, nn, qa, val);
+    }
+}
+
+// LDS slot of local cell `lane` of a full tile of 64 cells (the cell a
+// rank-major sort puts at that lane of every full rank block), or -1 when
+// the tile is ragged or does not hold 64 cells.
+__device__ __forceinline__ int lane_cell(const TileGeom &tg, int nx, int ny, int nz, int txi, int tyi, int tzi,
+                                         int lane) {
+    const int t3[3] = {tg.tx, tg.ty, tg.tz};
+    const int ext[3] = {min(tg.tx, nx - txi * tg.tx), min(tg.ty, ny - tyi * tg.ty), min(tg.tz, nz - tzi * tg.tz)};
+    if (tg.cells != 64 || ext[0] != t3[0] || ext[1] != t3[1] || ext[2] != t3[2]) return -1;
+    int loc[3];
+    loc[tg.fast] = lane % t3[tg.fast];
+    loc[tg.mid] = (lane / t3[tg.fast]) % t3[tg.mid];
+    loc[tg.slow] = lane / (t3[tg.fast] * t3[tg.mid]);
+    return (tg.halo + loc[0]) * tg.sx + (tg.halo + loc[1]) * tg.sy + (tg.halo + loc[2]) * tg.sz;
 }
 
 // Orders one wave's LDS accesses across lanes (a wave's LDS operations are
@@ -359,6 +486,7 @@ inline size_t stage_lds_bytes(int variant, int block, int dtype) {
     const size_t rec = 8 * (dtype == SPIC_F64 ? 8 : 4);
     if (variant == 2) return (size_t)(block / 64) * kQueueCap * rec;
     if (variant == 3) return (size_t)(block / 64) * (64 * rec + sizeof(BalanceLds));
+    if (variant == 5 || variant == 6) return (size_t)(block / 64) * 64 * 7 * (dtype == SPIC_F64 ? 8 : 4);
     return 0;
 }
 
@@ -373,6 +501,8 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
     constexpr bool CACHE = VAR == 1;  // field corners of the last cell in registers
     constexpr bool BAL = VAR == 3;    // bank-balanced deposit
     constexpr bool SEG = VAR == 4;    // segmented wave pre-reduction of the deposit
+    constexpr bool LANE = VAR == 5;   // lane-cell registers in particle precision + compact queue
+    constexpr bool SPLIT = VAR == 6;  // as 5, with the deposit in a second pass over the moved particles
     const GridT<TP> &g = J.g;
     TileGeom tg = J.tg;
     if constexpr (GEO::fixed) {  // the host launches this only for a matching tiling
@@ -432,27 +562,45 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
         bal = (BalanceLds *)(mine + 64 * sizeof(StagedParticle<TP>));
     }
     const int lane = threadIdx.x & 63;
+    // variant 5: lane l of every full rank block holds a particle sorted
+    // into local cell l, so lane l keeps the moments of that cell's 8 nodes
+    // in registers (particle precision) and queues the particles that left
+    // it; lcell = -1 where the tile is ragged or not 64 cells
+    TP lacc[LANE ? 80 : 1];
+#pragma unroll
+    for (int q = 0; q < (LANE ? 80 : 1); ++q) lacc[q] = TP(0);
+    int lcell = -1;
+    TP *lq = nullptr;  // per-wave queue, 7 arrays of 64 (x y z u v w q)
+    if constexpr (LANE) {
+        lq = (TP *)wstage + (threadIdx.x >> 6) * (7 * 64);
+        lcell = lane_cell(tg, g.nx, g.ny, g.nz, txi, tyi, tzi, lane);
+    }
 
     const uint32_t stride = blockDim.x;
     constexpr uint32_t ES = sizeof(TP);
     uint32_t i = beg + threadIdx.x;
     TP nx_ = 0, ny_ = 0, nz_ = 0, nu_ = 0, nv_ = 0, nw_ = 0, nq_ = 0;
+    int64_t nid_ = 0;
     const PartPtrs<TP> &pin = J.in;
+    const bool copy_id = J.copy_rest && pin.id;  // ids move with the sort's copy
     if (i < end) {
         const uint32_t o = i * ES;
         nx_ = ld32(pin.x, o); ny_ = ld32(pin.y, o); nz_ = ld32(pin.z, o);
         nu_ = ld32(pin.u, o); nv_ = ld32(pin.v, o); nw_ = ld32(pin.w, o); nq_ = ld32(pin.q, o);
+        if (copy_id) nid_ = pin.id[i];
     }
     // uniform per wave: the first index of this wave's lane 0
     for (uint32_t i0 = beg + (threadIdx.x & ~63u); i0 < end; i0 += stride, i += stride) {
         const bool valid = i < end;
         TP xn = nx_, yn = ny_, zn = nz_, un = nu_, vn = nv_, wn = nw_;
         const TP qp = nq_;
+        const int64_t idp = nid_;
         const uint32_t inext = i + stride;
         if (inext < end) {  // prefetch the next particle while this one is moved
             const uint32_t o = inext * ES;
             nx_ = ld32(pin.x, o); ny_ = ld32(pin.y, o); nz_ = ld32(pin.z, o);
             nu_ = ld32(pin.u, o); nv_ = ld32(pin.v, o); nw_ = ld32(pin.w, o); nq_ = ld32(pin.q, o);
+            if (copy_id) nid_ = pin.id[inext];
         }
         bool enq = false;
         if (valid) {
@@ -510,6 +658,7 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
                         }
                     } else {
                         gather_cell_global(f, c, F);
+                        settle(*(TP(*)[6])F);
                     }
                 },
                 xn, yn, zn, un, vn, wn);
@@ -518,10 +667,10 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
             st32(p.u, o, un); st32(p.v, o, vn); st32(p.w, o, wn);
             if (J.copy_rest) {  // reading the sort's copy: q and id move too
                 st32(p.q, o, qp);
-                if (pin.id) p.id[i] = pin.id[i];
+                if (copy_id) p.id[i] = idp;
             }
 
-            if (mom) {
+            if (!SPLIT && mom) {
                 // deposit of the new state in the accumulation precision
                 const TA qa = (TA)qp;
                 const TA ua = (TA)un, va = (TA)vn, wa = (TA)wn;
@@ -543,6 +692,27 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
                     } else {
                         enq = true;  // another cell, or outside the region
                     }
+                } else if constexpr (LANE) {
+                    // cell and weights from the position in the accumulation
+                    // precision (the cell-relative coordinate of an FP32
+                    // position loses ~ulp(x)/dx in FP32), the weighted charge
+                    // then rounded once to the particle precision
+                    int rb;
+                    Cell<TA> c;
+                    const bool in = region_locate(J.ga, tg, ox, oy, oz, (TA)xn, (TA)yn, (TA)zn, rb, c);
+                    if (in && rb == lcell) {
+                        TA wt8[8];
+                        pweights(c.fx, c.fy, c.fz, wt8);
+                        const TP val[10] = {TP(1), un, vn, wn, un * un, un * vn, un * wn, vn * vn, vn * wn, wn * wn};
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) {
+                            const TP qw = (TP)(qa * wt8[k]);
+#pragma unroll
+                            for (int m = 0; m < 10; ++m) lacc[(k * 10 + m) % (LANE ? 80 : 1)] += qw * val[m];
+                        }
+                    } else {
+                        enq = true;
+                    }
                 } else if constexpr (!BAL && !SEG) {
                     deposit_one<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, (TA)xn, (TA)yn, (TA)zn, qa, ua, va, wa);
                 }
@@ -557,6 +727,35 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
             if (mom)
                 deposit_segmented<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, lane, valid, (TA)xn, (TA)yn, (TA)zn,
                                            (TA)qp, (TA)un, (TA)vn, (TA)wn);
+        }
+        if constexpr (LANE) {
+            // queue the particles that left their lane's cell; whenever 64
+            // wait, deposit them with every lane active.  The queue holds
+            // 64: lanes past it wait until the full queue has been read.
+            const unsigned long long vote = __ballot(enq);
+            if (vote) {
+                const int cnt = __popcll(vote);
+                const int pos = qn + __popcll(vote & ((1ull << lane) - 1ull));
+                const TP rec[7] = {xn, yn, zn, un, vn, wn, qp};
+                if (enq && pos < 64)
+#pragma unroll
+                    for (int a = 0; a < 7; ++a) lq[a * 64 + pos] = rec[a];
+                if (qn + cnt >= 64) {
+                    wave_sync();
+                    TP r[7];
+#pragma unroll
+                    for (int a = 0; a < 7; ++a) r[a] = lq[a * 64 + lane];
+                    wave_sync();
+                    if (enq && pos >= 64)
+#pragma unroll
+                        for (int a = 0; a < 7; ++a) lq[a * 64 + pos - 64] = rec[a];
+                    deposit_lean<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, (TA)r[0], (TA)r[1], (TA)r[2], (TA)r[6],
+                                         (TA)r[3], (TA)r[4], (TA)r[5]);
+                    qn += cnt - 64;
+                } else {
+                    qn += cnt;
+                }
+            }
         }
         if constexpr (HOME) {
             // queue the drifted particles of this iteration; once 64 wait,
@@ -584,6 +783,109 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
         }
     }
     if (!mom) return;
+    if constexpr (SPLIT) {
+        // second pass: each thread re-reads the particles it moved (its own
+        // stores, same indices), so no barrier is needed; the mover's
+        // registers are dead here, leaving room for the 80 lane-cell sums
+        const int lc = lane_cell(tg, g.nx, g.ny, g.nz, txi, tyi, tzi, lane);
+        TP sacc[SPLIT ? 80 : 1];
+#pragma unroll
+        for (int q = 0; q < (SPLIT ? 80 : 1); ++q) sacc[q] = TP(0);
+        TP *sq = (TP *)wstage + (threadIdx.x >> 6) * (7 * 64);
+        int sqn = 0;
+        uint32_t ii = beg + threadIdx.x;
+        for (uint32_t i0 = beg + (threadIdx.x & ~63u); i0 < end; i0 += stride, ii += stride) {
+            const bool valid = ii < end;
+            bool enq = false;
+            TP rec[7] = {TP(0), TP(0), TP(0), TP(0), TP(0), TP(0), TP(0)};  // x y z u v w q
+            if (valid) {
+                const uint32_t o = ii * ES;
+                rec[0] = ld32(p.x, o); rec[1] = ld32(p.y, o); rec[2] = ld32(p.z, o);
+                rec[3] = ld32(p.u, o); rec[4] = ld32(p.v, o); rec[5] = ld32(p.w, o); rec[6] = ld32(p.q, o);
+                // cell and weights in the accumulation precision, as in
+                // variant 5
+                int rb;
+                Cell<TA> c;
+                const bool in = region_locate(J.ga, tg, ox, oy, oz, (TA)rec[0], (TA)rec[1], (TA)rec[2], rb, c);
+                if (in && rb == lc) {
+                    TA wt8[8];
+                    pweights(c.fx, c.fy, c.fz, wt8);
+                    const TP u = rec[3], v = rec[4], w = rec[5];
+                    const TP val[10] = {TP(1), u, v, w, u * u, u * v, u * w, v * v, v * w, w * w};
+                    const TA qa6 = (TA)rec[6];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const TP qw = (TP)(qa6 * wt8[k]);
+#pragma unroll
+                        for (int m = 0; m < 10; ++m) sacc[(k * 10 + m) % (SPLIT ? 80 : 1)] += qw * val[m];
+                    }
+                } else {
+                    enq = true;
+                }
+            }
+            const unsigned long long vote = __ballot(enq);
+            if (vote) {
+                const int cnt = __popcll(vote);
+                const int pos = sqn + __popcll(vote & ((1ull << lane) - 1ull));
+                if (enq && pos < 64)
+#pragma unroll
+                    for (int a = 0; a < 7; ++a) sq[a * 64 + pos] = rec[a];
+                if (sqn + cnt >= 64) {
+                    wave_sync();
+                    TP r[7];
+#pragma unroll
+                    for (int a = 0; a < 7; ++a) r[a] = sq[a * 64 + lane];
+                    wave_sync();
+                    if (enq && pos >= 64)
+#pragma unroll
+                        for (int a = 0; a < 7; ++a) sq[a * 64 + pos - 64] = rec[a];
+                    deposit_tight<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, (TA)r[0], (TA)r[1], (TA)r[2],
+                                          (TA)r[6], (TA)r[3], (TA)r[4], (TA)r[5]);
+                    sqn += cnt - 64;
+                } else {
+                    sqn += cnt;
+                }
+            }
+        }
+        wave_sync();
+        if (lane < sqn) {
+            TP r[7];
+#pragma unroll
+            for (int a = 0; a < 7; ++a) r[a] = sq[a * 64 + lane];
+            deposit_tight<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, (TA)r[0], (TA)r[1], (TA)r[2], (TA)r[6],
+                                  (TA)r[3], (TA)r[4], (TA)r[5]);
+        }
+        // the sums stay in the particle precision until here (without the
+        // barrier the compiler widens them early on the zero-trip path)
+        settle(sacc);
+        if (lc >= 0) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                TA *dst = ml + lc + coff[k];
+#pragma unroll
+                for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, (TA)sacc[(k * 10 + m) % (SPLIT ? 80 : 1)]);
+            }
+        }
+    }
+    if constexpr (LANE) {
+        wave_sync();
+        if (lane < qn) {
+            TP r[7];
+#pragma unroll
+            for (int a = 0; a < 7; ++a) r[a] = lq[a * 64 + lane];
+            deposit_lean<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, (TA)r[0], (TA)r[1], (TA)r[2], (TA)r[6], (TA)r[3],
+                                 (TA)r[4], (TA)r[5]);
+        }
+        settle(lacc);
+        if (lcell >= 0) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                TA *dst = ml + lcell + coff[k];
+#pragma unroll
+                for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, (TA)lacc[(k * 10 + m) % (LANE ? 80 : 1)]);
+            }
+        }
+    }
     if constexpr (HOME) {
         wave_sync();
         if (lane < qn) {
@@ -622,13 +924,14 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
 //      atomics for drifted particles; <= 256 VGPRs, 2 waves/SIMD
 //   3  as 0, with the bank-balanced deposit (per-wave staging in LDS)
 //   4  segmented wave pre-reduction of the deposit (cell-major sort order)
-template <int VAR>
+template <int VAR, typename TP>
 struct VariantWaves {
-    static constexpr int value = (VAR == 0 || VAR == 3 || VAR == 4) ? 4 : (VAR == 1 ? 3 : 2);
+    static constexpr int value =
+        (VAR == 0 || VAR == 3 || VAR == 4) ? 4 : (VAR == 1 || ((VAR == 5 || VAR == 6) && sizeof(TP) == 4)) ? 3 : 2;
 };
 
 template <typename TP, typename TF, typename TA, int VAR, class GEO>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VariantWaves<VAR>::value)))
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VariantWaves<VAR, TP>::value)))
 k_fused_tiled(TileJob<TP, TF, TA> J, int chunk) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int b = blockIdx.x;
@@ -641,7 +944,7 @@ k_fused_tiled(TileJob<TP, TF, TA> J, int chunk) {
 // atomic counter until the list is drained; every workgroup exits once the
 // counter passes nitems.  The counter must be zero at launch.
 template <typename TP, typename TF, typename TA, int VAR, class GEO>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VariantWaves<VAR>::value)))
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VariantWaves<VAR, TP>::value)))
 k_worklist(const TileJob<TP, TF, TA> *__restrict__ jobs, const uint2 *__restrict__ items, int nitems,
            unsigned *__restrict__ counter) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -689,6 +992,8 @@ static void tiled_variant(const TileJob<TP, TF, TA> &job, int chunk, size_t lds,
         case 2: tiled_launch<TP, TF, TA, 2, GEO>(job, chunk, lds, cfg.tile_block, s); break;
         case 3: tiled_launch<TP, TF, TA, 3, GEO>(job, chunk, lds, cfg.tile_block, s); break;
         case 4: tiled_launch<TP, TF, TA, 4, GEO>(job, chunk, lds, cfg.tile_block, s); break;
+        case 5: tiled_launch<TP, TF, TA, 5, GEO>(job, chunk, lds, cfg.tile_block, s); break;
+        case 6: tiled_launch<TP, TF, TA, 6, GEO>(job, chunk, lds, cfg.tile_block, s); break;
         default: tiled_launch<TP, TF, TA, 0, GEO>(job, chunk, lds, cfg.tile_block, s);
     }
 }
@@ -701,6 +1006,10 @@ static void tiled_t(const spic_grid &g, const spic_params &prm, const spic_field
                                        sizeof(TA) == 8 ? SPIC_F64 : SPIC_F32, cfg.variant, cfg.tile_block);
     const auto job = make_tile_job<TP, TF, TA>(g, prm, f, w, tg, tile_off);
     if (geo_is_default(tg) && cfg.fixed_geo) tiled_variant<TP, TF, TA, GeoDefault>(job, chunk, lds, cfg, s);
+    else if (geo_is<GeoDense>(tg) && cfg.fixed_geo && (cfg.variant == 5 || cfg.variant == 6)) {
+        if (cfg.variant == 5) tiled_launch<TP, TF, TA, 5, GeoDense>(job, chunk, lds, cfg.tile_block, s);
+        else tiled_launch<TP, TF, TA, 6, GeoDense>(job, chunk, lds, cfg.tile_block, s);
+    }
     else tiled_variant<TP, TF, TA, GeoRuntime>(job, chunk, lds, cfg, s);
 }
 
@@ -782,6 +1091,8 @@ static int worklist_groups_v(int variant, size_t lds, int block, int nitems, int
         case 2: return worklist_groups_t<TP, TF, TA, 2, GEO>(lds, block, nitems, max_groups);
         case 3: return worklist_groups_t<TP, TF, TA, 3, GEO>(lds, block, nitems, max_groups);
         case 4: return worklist_groups_t<TP, TF, TA, 4, GEO>(lds, block, nitems, max_groups);
+        case 5: return worklist_groups_t<TP, TF, TA, 5, GEO>(lds, block, nitems, max_groups);
+        case 6: return worklist_groups_t<TP, TF, TA, 6, GEO>(lds, block, nitems, max_groups);
         default: return worklist_groups_t<TP, TF, TA, 0, GEO>(lds, block, nitems, max_groups);
     }
 }
@@ -816,6 +1127,8 @@ static hipError_t worklist_v(int variant, const void *jobs, const uint2 *items, 
         case 2: return worklist_t<TP, TF, TA, 2, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
         case 3: return worklist_t<TP, TF, TA, 3, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
         case 4: return worklist_t<TP, TF, TA, 4, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
+        case 5: return worklist_t<TP, TF, TA, 5, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
+        case 6: return worklist_t<TP, TF, TA, 6, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
         default: return worklist_t<TP, TF, TA, 0, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
     }
 }

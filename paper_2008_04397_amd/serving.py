@@ -13,7 +13,10 @@ Latency of a request = completion time (results back in host memory) -
 arrival time in the trace, so time spent queued behind earlier requests
 (and any delay of the client itself) counts in both modes.  The client
 prepares each request's inputs (fields on the device, particles in pinned
-host memory) just before waiting for its arrival time.
+host memory) just before waiting for its arrival time.  Pinned host memory
+is finite: while the requests in flight hold more than `max_pinned_bytes`,
+the client waits for completions before preparing the next one (that wait
+counts in the latency of the requests it delays).
 """
 from __future__ import annotations
 
@@ -58,8 +61,16 @@ def make_request_run(req: W.Request, dtype=None, sort_every: int = 4, device="cu
     return spic.Run(h.grid, prm, f, species, h.qoms, moms, req.steps)
 
 
+def pinned_bytes(req: W.Request, dtype=None) -> int:
+    """Pinned host bytes of one request's particles (7 arrays + int64 ids)."""
+    import torch
+    elem = 8 if dtype == torch.float64 else 4
+    return int(req.box.n_total) * (7 * elem + 8)
+
+
 def serve(ctx: "spic.Context", requests: Sequence[W.Request], mode: str = "continuous",
-          dtype=None, sort_every: int = 4, time_scale: float = 1.0, log=None, keep=None) -> List[Done]:
+          dtype=None, sort_every: int = 4, time_scale: float = 1.0, log=None, keep=None,
+          max_pinned_bytes: int = 16 << 30) -> List[Done]:
     """Replay the arrival trace (arrival times multiplied by time_scale).
     When `keep` is a dict, keep[rid] receives each request's finished run
     (its species and moments hold the results)."""
@@ -75,12 +86,16 @@ def serve(ctx: "spic.Context", requests: Sequence[W.Request], mode: str = "conti
         for tk in list(inflight):
             if block or spic.spic_poll(ctx, tk):
                 secs = spic.spic_wait(ctx, tk)
-                req, arr, sub = inflight.pop(tk)
+                req, arr, sub, _ = inflight.pop(tk)
                 done.append(Done(req.rid, arr, sub, now(), req.box.n_total, req.steps, secs))
                 if block:
                     return
 
     for k, req in enumerate(order):
+        need = pinned_bytes(req, dtype)
+        while inflight and sum(v[3] for v in inflight.values()) + need > max_pinned_bytes:
+            poll_all()
+            time.sleep(0.0005)
         run = make_request_run(req, dtype, sort_every)
         torch.cuda.current_stream().synchronize()
         arrival = req.arrival * time_scale
@@ -91,7 +106,7 @@ def serve(ctx: "spic.Context", requests: Sequence[W.Request], mode: str = "conti
             while inflight:
                 poll_all(block=True)
         tk = spic.spic_batch_submit(ctx, [run])[0]
-        inflight[tk] = (req, arrival, now())
+        inflight[tk] = (req, arrival, now(), need)
         if keep is not None:
             keep[req.rid] = run
         if log and k % 20 == 0:

@@ -209,3 +209,49 @@ def test_ticks_step_the_shortest_runs_first(spic):
             P.assert_state(got[s], st[s], h.grid, P.POS64, P.VEL64)
             P.assert_moments(run.moments[s].cpu().numpy(), ms[s], P.MOM64)
     ctx.close()
+
+
+
+def _completion_order(spic, ctx, tickets, limit_s=120.0):
+    import time
+    order, t0 = [], time.monotonic()
+    while len(order) < len(tickets) and time.monotonic() - t0 < limit_s:
+        for t in tickets:
+            if t not in order and spic.spic_poll(ctx, t):
+                order.append(t)
+    for t in tickets:
+        spic.spic_wait(ctx, t)
+    return order
+
+
+@pytest.mark.parametrize("aging", [0, 1 << 40])
+def test_aging_credit_bounds_how_long_a_run_waits(spic, aging):
+    """A long run is already stepping when short runs arrive.  Without aging
+    credit (pure least-remaining-work) the newcomers overtake it; with a very
+    large credit rate the run that has waited longer keeps the GPU and
+    finishes first.  Results match the oracle either way."""
+    import time
+    ctx = spic.Context(0)
+    ctx.set_option("tick_items", 1)
+    ctx.set_option("srpt_aging", aging)
+    big = W.Harris(W.Grid(32, 16, 8), ppc=27, seed=21)
+    small = _boxes()[:2]
+    long_run, _ = _run_of(spic, big, 200, dtype=torch.float32)
+    shorts = [_run_of(spic, h, 10) for h in small]
+    _say("case batch aging %d: 1 long run (200 steps) then 2 short runs (10 steps), tick_items 1" % aging)
+    first = spic.spic_batch_submit(ctx, [long_run])
+    time.sleep(0.005)
+    later = spic.spic_batch_submit(ctx, [r for r, _ in shorts])
+    order = _completion_order(spic, ctx, first + later)
+    assert len(order) == 3
+    if aging:
+        assert order[0] == first[0], "the waiting long run was overtaken"
+    else:
+        assert order[-1] == first[0], "the short newcomers did not overtake the long run"
+    for h, (run, sps) in zip(small, shorts):
+        st, ms = _oracle(h, sps, 10)
+        got = _host(run)
+        for s in range(4):
+            P.assert_state(got[s], st[s], h.grid, P.POS64, P.VEL64)
+            P.assert_moments(run.moments[s].cpu().numpy(), ms[s], P.MOM64)
+    ctx.close()
