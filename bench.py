@@ -120,11 +120,7 @@ def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: 
         sort_every = 4
     if variant >= 0:
         ctx.set_option("tile_variant", variant)
-    launch = {k: ctx.get_option(k) for k in ("tile_variant", "tile_block", "bank_align", "sort_ordered", "halo")}
-    # unset options take the library defaults
-    dflt = {"tile_variant": 0, "tile_block": 512, "bank_align": 1 if dtype_name == "f32" else 0,
-            "sort_ordered": 1, "halo": 1}
-    launch = {k: (v if v >= 0 else dflt[k]) for k, v in launch.items()}
+    launch = spic.resolved_launch(ctx, "f32" if dtype_name == "f32" else "f64", "f64")
     launch["sort_every"] = sort_every
 
     def step(k, ev=None):

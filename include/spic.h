@@ -169,17 +169,20 @@ int spic_version(void);
  *   block          threads per block of the unsorted-path kernels (64..1024, x64)
  *   grid_cap       cap on blocks of grid-stride kernels
  *   path           0 = tiled kernel for sorted species, 1 = unsorted path only
- *   tile_block     threads per block of the tiled kernel (64..512, x64; 512)
+ *   tile_block     threads per block of the tiled kernel (64..512, x64; -1 =
+ *                  by variant: 256 for variants 5 and 6, else 512)
  *   tile_x/y/z     sort tile shape in cells (product <= 64)
  *   halo           cells of halo staged around a tile in LDS (0..8)
  *   lds_max        read only: LDS bytes a workgroup may use on the device
- *   tile_variant   tiled-kernel variant (0..4; see spic_tiled.hip)
+ *   tile_variant   tiled-kernel variant (0..6; see spic_tiled.hip; -1 = by
+ *                  precision: 5 for FP32 particles with FP64 moments, else 0)
  *   fixed_geo      1 = kernels compiled for 4x4x4 tiles with halo 1 are used
  *                  when that tiling is in effect
  *   bank_align     1 = LDS region layout that keeps a particle's bank pair
  *                  when it drifts along the most-crossed axis (more LDS);
- *                  0 = the most compact conflict-free layout (default: 1
- *                  for FP32 particles, 0 for FP64)
+ *                  0 = the most compact conflict-free layout; 2 = dense,
+ *                  no padding (default: 2 for variant 6, else 1 for FP32
+ *                  particles and 0 for FP64)
  *   sort_ordered   1 = a re-sort walks each tile of the current order in
  *                  order, so ranks inside a cell keep that order (0/1)
  *   graph          batch engine: replay unchanged ticks as a hipGraph (0/1)

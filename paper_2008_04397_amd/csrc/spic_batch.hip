@@ -150,7 +150,7 @@ struct BatchEngine {
     std::vector<uint64_t> graph_key;
 
     // tuning, read from the ctx options when the engine starts
-    int tile_block = 512, variant = 0, use_graph = 1, max_groups = 0, fixed_geo = 1, sort_ordered = 1;
+    int tile_block = -1, variant = -1, use_graph = 1, max_groups = 0, fixed_geo = 1, sort_ordered = 1;
     int64_t tick_items = 4096;  // 0: every active run steps at every tick
     double srpt_aging = 1e10;   // particle-steps of credit per second waited
     int64_t batch_particles = (int64_t)1 << 26;
@@ -215,7 +215,7 @@ struct BatchEngine {
                 const int acc = R.moments ? R.moments[s].acc_dtype : SPIC_F64;
                 sl.combo = job_combo(sl.user.dtype, R.fields.dtype, acc);
                 if (sl.combo < 0) return ctx->fail(SPIC_E_UNSUPPORTED, "run %d species %d: dtype combination", r, s);
-                if (tiled_lds_bytes(st->tg, sl.user.dtype, acc, 0, tile_block) > ctx->lds_max)
+                if (tiled_lds_bytes(st->tg, sl.user.dtype, acc, 0, 64) > ctx->lds_max)
                     return ctx->fail(SPIC_E_UNSUPPORTED,
                                      "run %d species %d: the tile region (tile_x/y/z, halo) does not fit in LDS", r, s);
                 const bool big = !tiled_fits(sl.user.n, sl.user.dtype);
@@ -449,7 +449,7 @@ struct BatchEngine {
             std::vector<unsigned char> jobs;
             std::vector<uint2> items;
             size_t lds = 0, lds0 = 0;  // LDS with the configured variant, with variant 0
-            int var = 0;
+            int var = 0, var_cfg = -1, block = 512;
         };
         std::map<int, Combo> combos;
         std::vector<void *> mptr[2];
@@ -468,6 +468,15 @@ struct BatchEngine {
                 if (sl.dev.n == 0) continue;
                 // launch key: precision combination, +8 for the compile-time default tiling
                 Combo &c = combos[sl.combo + (fixed_geo && geo_is_default(r.tg) ? 8 : 0)];
+                const int acc = m ? m->acc_dtype : SPIC_F64;
+                if (c.var_cfg < 0) {  // variant and block of this precision combination
+                    LaunchCfg rc = lcfg;
+                    rc.variant = variant;
+                    rc.tile_block = tile_block;
+                    rc = resolve_cfg(rc, sl.dev.dtype, acc);
+                    c.var_cfg = rc.variant;
+                    c.block = rc.tile_block;
+                }
                 const size_t jb = tile_job_bytes(sl.combo);
                 const uint32_t jidx = (uint32_t)(c.jobs.size() / jb);
                 c.jobs.resize(c.jobs.size() + jb);
@@ -475,9 +484,8 @@ struct BatchEngine {
                 write_tile_job(sl.combo, c.jobs.data() + jidx * jb, r.grid, prm, r.fields, work_of(sl.dev, m), r.tg,
                                sl.tile_off);
                 for (int t = 0; t < r.tg.ntiles; ++t) c.items.push_back(make_uint2(jidx, (uint32_t)t));
-                const int acc = m ? m->acc_dtype : SPIC_F64;
-                c.lds = std::max(c.lds, tiled_lds_bytes(r.tg, sl.dev.dtype, acc, variant, tile_block));
-                c.lds0 = std::max(c.lds0, tiled_lds_bytes(r.tg, sl.dev.dtype, acc, 0, tile_block));
+                c.lds = std::max(c.lds, tiled_lds_bytes(r.tg, sl.dev.dtype, acc, c.var_cfg, c.block));
+                c.lds0 = std::max(c.lds0, tiled_lds_bytes(r.tg, sl.dev.dtype, acc, 0, c.block));
             }
         }
         // layout of the device table: [ptrs f64][cnt f64][ptrs f32][cnt f32][counters x16] then per launch key jobs, items
@@ -524,9 +532,9 @@ struct BatchEngine {
         for (auto &kv : combos) {
             // a variant whose extra LDS does not fit falls back to variant 0
             Combo &c = kv.second;
-            c.var = c.lds <= ctx->lds_max ? variant : 0;
-            if (c.var != variant) c.lds = c.lds0;
-            groups[kv.first] = worklist_groups(kv.first & 7, kv.first >= 8, c.var, c.lds, tile_block,
+            c.var = c.lds <= ctx->lds_max ? c.var_cfg : 0;
+            if (c.var != c.var_cfg) c.lds = c.lds0;
+            groups[kv.first] = worklist_groups(kv.first & 7, kv.first >= 8, c.var, c.lds, c.block,
                                                (int)c.items.size(), max_groups);
         }
         bool capturing = false;
@@ -542,7 +550,7 @@ struct BatchEngine {
             if (e != hipSuccess) break;
             e = launch_worklist(kv.first & 7, kv.first >= 8, kv.second.var, d + co[kv.first].first,
                                 (const uint2 *)(d + co[kv.first].second), (int)kv.second.items.size(),
-                                (unsigned *)(d + o_ctr) + ci++, kv.second.lds, tile_block, groups[kv.first], cs);
+                                (unsigned *)(d + o_ctr) + ci++, kv.second.lds, kv.second.block, groups[kv.first], cs);
         }
         if (capturing) {
             hipGraph_t g = nullptr;
@@ -796,7 +804,8 @@ void BatchEngine::stream_run(RunState &r) {
                     if (sort_due &&
                         (e = launch_sort(r.grid, w, r.tg, sort_scr, toff, sort_ordered && step > 0, cs)) != hipSuccess)
                         fail_run(r, e, "batch sort");
-                    LaunchCfg bcfg = lcfg;  // variant 0 when the configured one's LDS does not fit
+                    // variant 0 when the configured one's LDS does not fit
+                    LaunchCfg bcfg = resolve_cfg(lcfg, w.dtype, w.mom ? w.acc_dtype : SPIC_F64);
                     if (tiled_lds_bytes(r.tg, w.dtype, w.acc_dtype, bcfg.variant, bcfg.tile_block) > ctx->lds_max)
                         bcfg.variant = 0;
                     if ((e = launch_fused_tiled(r.grid, prm, r.fields, w, r.tg, toff, bcfg, cs)) != hipSuccess)
@@ -845,8 +854,8 @@ int spic_ctx_s::batch_submit(const spic_run *runs, int32_t nruns, uint64_t *tick
     if (nruns == 0) return SPIC_OK;
     if (!batch) {
         batch.reset(new BatchEngine(this));
-        batch->tile_block = (int)opt("tile_block", 512);
-        batch->variant = (int)opt("tile_variant", 0);
+        batch->tile_block = (int)opt("tile_block", -1);
+        batch->variant = (int)opt("tile_variant", -1);
         batch->fixed_geo = (int)opt("fixed_geo", 1);
         batch->sort_ordered = (int)opt("sort_ordered", 1);
         batch->use_graph = (int)opt("graph", 1);

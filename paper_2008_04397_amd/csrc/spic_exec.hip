@@ -38,7 +38,7 @@ std::string spic_ctx_s::layout_key(const spic_grid &g, const spic_species &s) co
 // two-phase variant deposits mostly from registers and takes the dense
 // layout (the smallest LDS footprint, more workgroups per CU).
 TileGeom spic_ctx_s::tile_geom(const spic_grid &g, int dtype) const {
-    const int var = (int)opt("tile_variant", 0);
+    const int var = (int)opt("tile_variant", -1);
     const bool cm = var == 4;
     const int dflt = var == 6 ? 2 : (dtype == SPIC_F64 || cm) ? 0 : 1;
     return make_tile_geom(g, (int)opt("tile_x", 4), (int)opt("tile_y", 4), (int)opt("tile_z", 4),
@@ -65,7 +65,7 @@ int spic_ctx_s::mover(const spic_grid &g, const spic_params &p, const spic_field
         }
         // the tiled kernel runs for a sorted species whose region fits in LDS;
         // a variant whose extra LDS does not fit falls back to variant 0
-        LaunchCfg tcfg = cfg;
+        LaunchCfg tcfg = resolve_cfg(cfg, w.dtype, w.mom ? w.acc_dtype : SPIC_F64);
         auto tiled_ok = [&](const TileGeom &tg) {
             if (generic_only || !tiled_fits(w.n, w.dtype)) return false;
             if (tiled_lds_bytes(tg, w.dtype, w.acc_dtype, tcfg.variant, tcfg.tile_block) > lds_max) tcfg.variant = 0;

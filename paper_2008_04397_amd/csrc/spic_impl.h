@@ -57,10 +57,22 @@ struct SpeciesWork {
 struct LaunchCfg {
     int block = 256;        // generic kernels
     int grid_cap = 1 << 20;
-    int tile_block = 512;   // tiled fused kernel
-    int variant = 0;        // tiled kernel variant (see spic_tiled.hip)
+    int tile_block = -1;    // tiled fused kernel (-1: by variant)
+    int variant = -1;       // tiled kernel variant (see spic_tiled.hip; -1: by precision)
     int fixed_geo = 1;      // compile-time region geometry for the default tiling
 };
+
+// Tiled-kernel variant and workgroup size when the options leave them to
+// the library: FP32 particles with FP64 moments take the lane-cell register
+// deposit at 256 threads (measured fastest on the Harris boxes), every
+// other precision combination the LDS-atomic deposit at 512.
+inline int auto_variant(int dtype, int acc_dtype) { return (dtype == SPIC_F32 && acc_dtype == SPIC_F64) ? 5 : 0; }
+inline int auto_tile_block(int variant) { return (variant == 5 || variant == 6) ? 256 : 512; }
+inline LaunchCfg resolve_cfg(LaunchCfg c, int dtype, int acc_dtype) {
+    if (c.variant < 0) c.variant = auto_variant(dtype, acc_dtype);
+    if (c.tile_block < 0) c.tile_block = auto_tile_block(c.variant);
+    return c;
+}
 
 // Tiles of tx x ty x tz cells (at most 64 cells) cover the grid; ntx.. are
 // tile counts per axis (edge tiles may be partial).  The tiled kernel stages

@@ -210,8 +210,8 @@ LaunchCfg spic_ctx_s::launch_cfg() const {
     LaunchCfg c;
     c.block = (int)opt("block", 256);
     c.grid_cap = (int)opt("grid_cap", 1 << 20);
-    c.tile_block = (int)opt("tile_block", 512);
-    c.variant = (int)opt("tile_variant", 0);
+    c.tile_block = (int)opt("tile_block", -1);
+    c.variant = (int)opt("tile_variant", -1);
     c.fixed_geo = (int)opt("fixed_geo", 1);
     return c;
 }
@@ -280,13 +280,13 @@ int spic_set_option(spic_ctx ctx, const char *key, int64_t value) {
                 return ctx->fail(SPIC_E_ARG, "grid_cap must be in [1, 2^24]");
             if (!strcmp(key, "path") && (value < 0 || value > 1))
                 return ctx->fail(SPIC_E_ARG, "path must be 0 (auto) or 1 (generic)");
-            if (!strcmp(key, "tile_block") && (value < 64 || value > 512 || value % 64))
-                return ctx->fail(SPIC_E_ARG, "tile_block must be a multiple of 64 in [64, 512]");
+            if (!strcmp(key, "tile_block") && value != -1 && (value < 64 || value > 512 || value % 64))
+                return ctx->fail(SPIC_E_ARG, "tile_block must be -1 or a multiple of 64 in [64, 512]");
             if ((!strcmp(key, "tile_x") || !strcmp(key, "tile_y") || !strcmp(key, "tile_z")) &&
                 (value < 1 || value > 64))
                 return ctx->fail(SPIC_E_ARG, "tile sizes must be in [1, 64]");
-            if (!strcmp(key, "tile_variant") && (value < 0 || value > 6))
-                return ctx->fail(SPIC_E_ARG, "tile_variant must be in 0..6");
+            if (!strcmp(key, "tile_variant") && (value < -1 || value > 6))
+                return ctx->fail(SPIC_E_ARG, "tile_variant must be -1 or in 0..6");
             if (!strcmp(key, "batch_particles") && (value < 1024 || value > ((int64_t)1 << 29)))
                 return ctx->fail(SPIC_E_ARG, "batch_particles must be in [1024, 2^29]");
             if (!strcmp(key, "tick_items") && (value < 0 || value > ((int64_t)1 << 30)))

@@ -257,6 +257,27 @@ def spic_poll(ctx: Context, ticket: int) -> bool:
     return bool(done.value)
 
 
+def resolved_launch(ctx: Context, dtype: str, acc: str = "f64") -> Dict[str, int]:
+    """The tiled-kernel launch settings the library uses for species of the
+    given particle and moment precision ("f32"/"f64"): options left at -1
+    resolve as the library resolves them (variant 5 at 256 threads for FP32
+    particles with FP64 moments, otherwise variant 0 at 512; layout 1 for
+    FP32 particles, 0 for FP64, 2 for the two-phase variant)."""
+    var = ctx.get_option("tile_variant")
+    if var < 0:
+        var = 5 if (dtype == "f32" and acc == "f64") else 0
+    blk = ctx.get_option("tile_block")
+    if blk < 0:
+        blk = 256 if var in (5, 6) else 512
+    al = ctx.get_option("bank_align")
+    if al < 0:
+        al = 2 if var == 6 else (0 if (dtype == "f64" or var == 4) else 1)
+    so = ctx.get_option("sort_ordered")
+    halo = ctx.get_option("halo")
+    return {"tile_variant": var, "tile_block": blk, "bank_align": al, "sort_ordered": 1 if so < 0 else so,
+            "halo": 1 if halo < 0 else halo}
+
+
 # --------------------------------------------------------- tensor helpers
 
 def to_device(arrs: Dict[str, np.ndarray], dtype, device="cuda") -> Dict[str, "object"]:

@@ -144,7 +144,11 @@ def test_streamed_run_equals_resident_run(spic, dtype):
         a, b = P.by_id(spic_to_host(res.species[s])), P.by_id(spic_to_host(stm.species[s]))
         for k in ("x", "y", "z", "u", "v", "w"):
             assert np.array_equal(a[k], b[k]), k
-        tol = 1e-13 if dtype == torch.float64 else 1e-12
+        # FP32 particles: the lane-cell deposit forms FP32 partial sums over
+        # the particles one thread holds, and a streamed batch is sorted and
+        # tiled on its own, so the grouping differs: FP32 rounding (the
+        # oracle bound for FP32 moments), not the FP64 accumulation order
+        tol = 1e-13 if dtype == torch.float64 else P.MOM32
         P.assert_moments(stm.moments[s].cpu().numpy(), res.moments[s].cpu().numpy(), tol)
     ctx_r.close()
     ctx_s.close()

@@ -2,7 +2,12 @@
 engine with continuous batching; every request's result must equal the
 same request run alone (particles bitwise by position in the sorted order
 of ids is not available here -- the inputs carry no ids -- so particles are
-compared as sorted multisets per component, moments within 1e-12)."""
+compared as sorted multisets per component).  Moments agree within 1e-12
+with the LDS-atomic deposit (variant 0: FP64 terms, only the order of FP64
+additions differs); with the default lane-cell deposit of FP32 particles
+(variant 5) the FP32 partial sums depend on which particles share a
+thread, and the order of particles inside a cell after a sort is not
+fixed, so they agree within the FP32 moment tolerance (rel 1e-6)."""
 import sys
 
 import numpy as np
@@ -22,12 +27,14 @@ def _stream():
     return W.serving_stream(8, rate=40.0, seed=9, max_nx=32, steps_range=(3, 9))
 
 
-def test_each_request_alone_equals_continuous_mix():
+@pytest.mark.parametrize("variant,tol", [(-1, 1e-6), (0, 1e-12)])
+def test_each_request_alone_equals_continuous_mix(variant, tol):
     from paper_2008_04397_amd import serving, spic
     reqs = _stream()
     ctx = spic.Context(0, hbm_budget_bytes=256 << 20)
+    ctx.set_option("tile_variant", variant)
     mixed = {}
-    _say("case serving continuous 8 requests")
+    _say("case serving continuous 8 requests, tile_variant %d" % variant)
     done = serving.serve(ctx, reqs, mode="continuous", keep=mixed)
     assert len(done) == len(reqs)
     s = serving.summarize(done)
@@ -45,7 +52,7 @@ def test_each_request_alone_equals_continuous_mix():
             a, b = ma.cpu().numpy(), mb.cpu().numpy()
             for c in range(10):
                 nb = np.linalg.norm(a[c])
-                assert np.linalg.norm(a[c] - b[c]) <= 1e-12 * max(nb, 1e-300)
+                assert np.linalg.norm(a[c] - b[c]) <= tol * max(nb, 1e-300)
     ctx.close()
 
 
