@@ -363,6 +363,8 @@ def bench_serving(args):
     res = {}
     for mode in ("continuous", "serial"):
         ctx = _engine_ctx(budget=64 * (1 << 30))
+        if args.srpt_aging >= 0:
+            ctx.set_option("srpt_aging", args.srpt_aging)
         # warm the engine and the kernels once
         warm = serving.make_request_run(reqs[0])
         warm.nsteps = 1
@@ -376,7 +378,8 @@ def bench_serving(args):
     return {"metric": METRIC, "mode": "serving", "value": c["throughput"], "unit": "particle-steps/s", "n_gpus": 1,
             "higher_is_better": True, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "poisson_20_per_s_harris_runs", "requests": len(reqs),
-                       "precision": "f32 particles, f64 moments", "hbm_budget_bytes": 64 * (1 << 30)},
+                       "precision": "f32 particles, f64 moments", "hbm_budget_bytes": 64 * (1 << 30),
+                       "srpt_aging_M_per_s": args.srpt_aging if args.srpt_aging >= 0 else 10000},
             "p50_s": c["p50_s"], "p99_s": c["p99_s"], "continuous": c, "serial": res["serial"]}
 
 
@@ -389,6 +392,8 @@ def main():
     ap.add_argument("--mode", default="main", choices=("main", "ensemble", "streamed", "serving", "cadence"))
     ap.add_argument("--fraction", type=float, default=1.0)
     ap.add_argument("--requests", type=int, default=120)
+    ap.add_argument("--srpt-aging", type=int, default=-1,
+                    help="serving: engine aging credit in M particle-steps/s (-1: library default)")
     ap.add_argument("--tune", action="store_true",
                     help="autotune block size, variant, layout and cadence first (cached per workload class); "
                          "the default uses the library defaults, which are the measured best on MI355X")

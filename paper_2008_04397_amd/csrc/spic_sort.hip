@@ -317,6 +317,88 @@ k_sort_gather(PartPtrs<T> src, PartPtrs<T> dst, int64_t n, const uint32_t *__res
     }
 }
 
+// The same gather for a re-sort with the same tiling, one workgroup per new
+// tile: most of a tile's particles were in the same tile at the previous
+// sort, so each array's old tile range is staged in LDS with coalesced
+// reads, the new order is gathered from LDS and written coalesced; a
+// particle that came from another tile (or lies past the staging capacity)
+// is read from global memory.  old_off holds the previous sort's tile
+// ranges, offsets the new per-cell offsets.
+constexpr int kGatherLdsBytes = 32768;
+
+template <typename T, typename V>
+__device__ __forceinline__ void gather_tile_array(const V *__restrict__ sa, V *__restrict__ da, V *stage, uint32_t ob,
+                                                  uint32_t ocap, uint32_t nb, uint32_t ne, int64_t n,
+                                                  const uint32_t *__restrict__ srcidx) {
+    // batches of 8 elements per thread keep 8 loads in flight
+    constexpr int U = 8;
+    const uint32_t B = blockDim.x;
+    for (uint32_t j0 = threadIdx.x; j0 < ocap; j0 += U * B) {
+        V v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t j = j0 + u * B;
+            if (j < ocap) v[u] = sa[ob + j];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t j = j0 + u * B;
+            if (j < ocap) stage[j] = v[u];
+        }
+    }
+    __syncthreads();
+    for (uint32_t d0 = nb + threadIdx.x; d0 < ne; d0 += U * B) {
+        uint32_t p[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t d = d0 + u * B;
+            p[u] = d < ne ? srcidx[d] : 0u;
+        }
+        V v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t d = d0 + u * B;
+            const uint32_t r = p[u] - ob;  // wraps past ocap when p < ob
+            if (d < ne) {
+                if (r < ocap) v[u] = stage[r];
+                else if (p[u] < (uint64_t)n) v[u] = sa[p[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t d = d0 + u * B;
+            const uint32_t r = p[u] - ob;
+            if (d < ne && (r < ocap || p[u] < (uint64_t)n)) da[d] = v[u];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_sort_gather_tiled(PartPtrs<T> src, PartPtrs<T> dst, int64_t n, const uint32_t *__restrict__ srcidx,
+                    const uint32_t *__restrict__ old_off, const uint32_t *__restrict__ offsets, int cells,
+                    int ntiles) {
+    __shared__ __align__(16) unsigned char lds[kGatherLdsBytes];
+    const int t = blockIdx.x;
+    if (t >= ntiles) return;
+    const uint32_t nb = offsets[(uint32_t)t * (uint32_t)cells], ne = offsets[(uint32_t)(t + 1) * (uint32_t)cells];
+    // clamped to [0, n] so that stale ranges cannot send a read out of bounds
+    const uint32_t nn32 = (uint32_t)n;
+    const uint32_t ob = min(old_off[t], nn32), oe = min(old_off[t + 1], nn32);
+    const uint32_t span = oe > ob ? oe - ob : 0u;
+    const uint32_t capT = kGatherLdsBytes / sizeof(T), cap8 = kGatherLdsBytes / 8;
+    const uint32_t oc = span < capT ? span : capT;
+    T *st = (T *)lds;
+    const T *sa[7] = {src.x, src.y, src.z, src.u, src.v, src.w, src.q};
+    T *da[7] = {dst.x, dst.y, dst.z, dst.u, dst.v, dst.w, dst.q};
+#pragma unroll
+    for (int a = 0; a < 7; ++a) gather_tile_array<T, T>(sa[a], da[a], st, ob, oc, nb, ne, n, srcidx);
+    if (src.id)
+        gather_tile_array<T, int64_t>(src.id, dst.id, (int64_t *)lds, ob, span < cap8 ? span : cap8, nb, ne, n,
+                                      srcidx);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_copy_parts(PartPtrs<T> src, PartPtrs<T> dst, int64_t n) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
@@ -451,7 +533,11 @@ static hipError_t sort_t(const spic_grid &g, const SpeciesWork &w, const TileGeo
         hipLaunchKernelGGL(k_sort_slots, dim3(gp > 0 ? gp : 1), dim3(256), 0, s, n, keyrank, offsets, tab_off, tab,
                            tg.cells, prev ? (const uint32_t *)own : nullptr, srcidx);
     }
-    hipLaunchKernelGGL((k_sort_gather<T>), dim3(gp > 0 ? gp : 1), dim3(256), 0, s, src, tmp, n, srcidx);
+    if (prev)  // tile_off still holds the previous sort's tile ranges
+        hipLaunchKernelGGL((k_sort_gather_tiled<T>), dim3(tg.ntiles), dim3(256), 0, s, src, tmp, n, srcidx,
+                           (const uint32_t *)tile_off, offsets, tg.cells, tg.ntiles);
+    else
+        hipLaunchKernelGGL((k_sort_gather<T>), dim3(gp > 0 ? gp : 1), dim3(256), 0, s, src, tmp, n, srcidx);
     if (sorted_out) {  // the next kernel reads the reordered copy and writes w's arrays
         *sorted_out = w;
         sorted_out->from_src = true;

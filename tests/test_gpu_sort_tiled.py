@@ -234,6 +234,36 @@ def test_lane_cell_variant_with_each_slow_axis(spic, ctx, L, variant):
             P.assert_moments(ms[s], oms[s], P.MOM64)
 
 
+def test_resort_of_a_crowded_tile(spic, ctx):
+    """A re-sort stages each array's old tile range in LDS up to a fixed
+    capacity (8192 FP32 or 4096 FP64 values) and reads the rest of the tile
+    from global memory: one 4x4x4 tile holding 40,000 particles, FP64 steps
+    sorted every step against the oracle, and FP32 steps sorted every step
+    equal (by id, bitwise) to FP32 steps never sorted."""
+    h = W.Harris(W.Grid(4, 4, 4, 2.0, 2.0, 2.0), ppc=8)
+    g = h.grid
+    f = W.make_fields(h)
+    sps = [W.random_particles(g, 40000, 0.5, seed=3), W.random_particles(g, 30000, 0.1, seed=4)]
+    qoms = [-64.0, 1.0]
+    _say("case crowded tile fp64 (40000 + 30000 particles, 1 tile)")
+    st, ms = _gpu_steps(spic, ctx, h, f, sps, qoms, 3, sort_every=1)
+    ora, oms = _oracle_steps(h, f, sps, qoms, 3)
+    for s in range(2):
+        P.assert_state(st[s], ora[s], g, P.POS64, P.VEL64)
+        P.assert_moments(ms[s], oms[s], P.MOM64)
+    _say("case crowded tile fp32 sorted vs unsorted")
+    f32 = {k: v.astype(np.float32) for k, v in f.items()}
+    s32 = [W.round_state(x, np.float32) for x in sps]
+    a_st, _ = _gpu_steps(spic, ctx, h, f32, s32, qoms, 3, dtype=torch.float32, sort_every=1)
+    ctx2 = spic.Context(0)
+    b_st, _ = _gpu_steps(spic, ctx2, h, f32, s32, qoms, 3, dtype=torch.float32, sort_every=0)
+    ctx2.close()
+    for s in range(2):
+        a, b = P.by_id(a_st[s]), P.by_id(b_st[s])
+        for k in ("x", "y", "z", "u", "v", "w", "q"):
+            assert np.array_equal(a[k], b[k]), k
+
+
 def test_sorted_and_unsorted_runs_agree(spic, ctx):
     """Sorting only reorders: the same particles (by id) and the same moments
     up to summation order."""
