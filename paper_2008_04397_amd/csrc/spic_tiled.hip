@@ -486,7 +486,7 @@ inline size_t stage_lds_bytes(int variant, int block, int dtype) {
     const size_t rec = 8 * (dtype == SPIC_F64 ? 8 : 4);
     if (variant == 2) return (size_t)(block / 64) * kQueueCap * rec;
     if (variant == 3) return (size_t)(block / 64) * (64 * rec + sizeof(BalanceLds));
-    if (variant == 5 || variant == 6) return (size_t)(block / 64) * 64 * 7 * (dtype == SPIC_F64 ? 8 : 4);
+    if (variant >= 5) return (size_t)(block / 64) * 64 * 7 * (dtype == SPIC_F64 ? 8 : 4);
     return 0;
 }
 
@@ -501,7 +501,8 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
     constexpr bool CACHE = VAR == 1;  // field corners of the last cell in registers
     constexpr bool BAL = VAR == 3;    // bank-balanced deposit
     constexpr bool SEG = VAR == 4;    // segmented wave pre-reduction of the deposit
-    constexpr bool LANE = VAR == 5;   // lane-cell registers in particle precision + compact queue
+    constexpr bool LANE = VAR == 5 || VAR == 7;  // lane-cell registers in particle precision + compact queue
+    constexpr bool AUX = VAR == 7;    // + a second register set for the first cell a lane's particles drift to
     constexpr bool SPLIT = VAR == 6;  // as 5, with the deposit in a second pass over the moved particles
     const GridT<TP> &g = J.g;
     TileGeom tg = J.tg;
@@ -570,6 +571,14 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
 #pragma unroll
     for (int q = 0; q < (LANE ? 80 : 1); ++q) lacc[q] = TP(0);
     int lcell = -1;
+    // variant 7: the sheet species drift coherently across one face of
+    // their cells, so a lane's drifted particles mostly share one cell: the
+    // first one names it (acell) and those that follow it accumulate in a
+    // second register set
+    TP xacc[AUX ? 80 : 1];
+#pragma unroll
+    for (int q = 0; q < (AUX ? 80 : 1); ++q) xacc[q] = TP(0);
+    int acell = -1;
     TP *lq = nullptr;  // per-wave queue, 7 arrays of 64 (x y z u v w q)
     if constexpr (LANE) {
         lq = (TP *)wstage + (threadIdx.x >> 6) * (7 * 64);
@@ -700,6 +709,7 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
                     int rb;
                     Cell<TA> c;
                     const bool in = region_locate(J.ga, tg, ox, oy, oz, (TA)xn, (TA)yn, (TA)zn, rb, c);
+                    if (AUX && in && lcell >= 0 && rb != lcell && acell < 0) acell = rb;
                     if (in && rb == lcell) {
                         TA wt8[8];
                         pweights(c.fx, c.fy, c.fz, wt8);
@@ -709,6 +719,16 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
                             const TP qw = (TP)(qa * wt8[k]);
 #pragma unroll
                             for (int m = 0; m < 10; ++m) lacc[(k * 10 + m) % (LANE ? 80 : 1)] += qw * val[m];
+                        }
+                    } else if (AUX && in && rb == acell) {
+                        TA wt8[8];
+                        pweights(c.fx, c.fy, c.fz, wt8);
+                        const TP val[10] = {TP(1), un, vn, wn, un * un, un * vn, un * wn, vn * vn, vn * wn, wn * wn};
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) {
+                            const TP qw = (TP)(qa * wt8[k]);
+#pragma unroll
+                            for (int m = 0; m < 10; ++m) xacc[(k * 10 + m) % (AUX ? 80 : 1)] += qw * val[m];
                         }
                     } else {
                         enq = true;
@@ -885,6 +905,17 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
                 for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, (TA)lacc[(k * 10 + m) % (LANE ? 80 : 1)]);
             }
         }
+        if constexpr (AUX) {
+            settle(xacc);
+            if (acell >= 0) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    TA *dst = ml + acell + coff[k];
+#pragma unroll
+                    for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, (TA)xacc[(k * 10 + m) % (AUX ? 80 : 1)]);
+                }
+            }
+        }
     }
     if constexpr (HOME) {
         wave_sync();
@@ -994,6 +1025,7 @@ static void tiled_variant(const TileJob<TP, TF, TA> &job, int chunk, size_t lds,
         case 4: tiled_launch<TP, TF, TA, 4, GEO>(job, chunk, lds, cfg.tile_block, s); break;
         case 5: tiled_launch<TP, TF, TA, 5, GEO>(job, chunk, lds, cfg.tile_block, s); break;
         case 6: tiled_launch<TP, TF, TA, 6, GEO>(job, chunk, lds, cfg.tile_block, s); break;
+        case 7: tiled_launch<TP, TF, TA, 7, GEO>(job, chunk, lds, cfg.tile_block, s); break;
         default: tiled_launch<TP, TF, TA, 0, GEO>(job, chunk, lds, cfg.tile_block, s);
     }
 }
@@ -1093,6 +1125,7 @@ static int worklist_groups_v(int variant, size_t lds, int block, int nitems, int
         case 4: return worklist_groups_t<TP, TF, TA, 4, GEO>(lds, block, nitems, max_groups);
         case 5: return worklist_groups_t<TP, TF, TA, 5, GEO>(lds, block, nitems, max_groups);
         case 6: return worklist_groups_t<TP, TF, TA, 6, GEO>(lds, block, nitems, max_groups);
+        case 7: return worklist_groups_t<TP, TF, TA, 7, GEO>(lds, block, nitems, max_groups);
         default: return worklist_groups_t<TP, TF, TA, 0, GEO>(lds, block, nitems, max_groups);
     }
 }
@@ -1129,6 +1162,7 @@ static hipError_t worklist_v(int variant, const void *jobs, const uint2 *items, 
         case 4: return worklist_t<TP, TF, TA, 4, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
         case 5: return worklist_t<TP, TF, TA, 5, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
         case 6: return worklist_t<TP, TF, TA, 6, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
+        case 7: return worklist_t<TP, TF, TA, 7, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
         default: return worklist_t<TP, TF, TA, 0, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
     }
 }

@@ -268,7 +268,7 @@ def resolved_launch(ctx: Context, dtype: str, acc: str = "f64") -> Dict[str, int
         var = 5 if (dtype == "f32" and acc == "f64") else 0
     blk = ctx.get_option("tile_block")
     if blk < 0:
-        blk = 256 if var in (5, 6) else 512
+        blk = 256 if var >= 5 else 512
     al = ctx.get_option("bank_align")
     if al < 0:
         al = 2 if var == 6 else (0 if (dtype == "f64" or var == 4) else 1)
