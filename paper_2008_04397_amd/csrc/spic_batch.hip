@@ -474,6 +474,7 @@ struct BatchEngine {
                     rc.variant = variant;
                     rc.tile_block = tile_block;
                     rc = resolve_cfg(rc, sl.dev.dtype, acc);
+                    if (rc.variant == 8) rc.variant = 5;  // the split variant has no work-list form
                     c.var_cfg = rc.variant;
                     c.block = rc.tile_block;
                 }

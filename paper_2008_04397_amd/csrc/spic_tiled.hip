@@ -189,37 +189,9 @@ __device__ __forceinline__ void deposit_one(const GridT<TA> &ga, const TileGeom 
     }
 }
 
-// deposit_one with the corner loop rolled (each corner's weight formed in
-// the loop, the same products as pweights): few live registers, for the
-// variant whose 80 register sums stay live across it.
-template <typename TA, class GEO>
-__device__ __forceinline__ void deposit_lean(const GridT<TA> &ga, const TileGeom &tg, int ox, int oy, int oz,
-                                             TA *__restrict__ ml, TA *__restrict__ mom, int nn, TA x, TA y, TA z,
-                                             TA qa, TA ua, TA va, TA wa) {
-    const int RNP = tg.rnp, sx = tg.sx, sy = tg.sy, sz = tg.sz;
-    int rb;
-    Cell<TA> c;
-    const bool in = region_locate(ga, tg, ox, oy, oz, x, y, z, rb, c);
-    const TA val[10] = {TA(1), ua, va, wa, ua * ua, ua * va, ua * wa, va * va, va * wa, wa * wa};
-    if (in) {
-#pragma unroll 1
-        for (int k = 0; k < 8; ++k) {
-            const TA wx = (k & 1) ? c.fx : TA(1) - c.fx;
-            const TA wy = (k & 2) ? c.fy : TA(1) - c.fy;
-            const TA wz = (k & 4) ? c.fz : TA(1) - c.fz;
-            const TA qw = qa * ((wx * wy) * wz);
-            TA *dst = ml + rb + (k & 1) * sx + ((k >> 1) & 1) * sy + (k >> 2) * sz;
-#pragma unroll
-            for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, qw * val[m]);
-        }
-    } else {
-        deposit_global_cell(c, mom, nn, qa, val);
-    }
-}
-
-// deposit_lean with the velocity products formed per corner instead of
-// held for all ten moments: fewer live registers still (the second pass of
-// the two-phase variant keeps 80 sums live across it at 4 waves per SIMD).
+// deposit_one with the corner loop rolled and the velocity products formed
+// per corner instead of held for all ten moments: few live registers (the
+// second pass of the two-phase variants keeps 80 sums live across it).
 template <typename TA, class GEO>
 __device__ __forceinline__ void deposit_tight(const GridT<TA> &ga, const TileGeom &tg, int ox, int oy, int oz,
                                               TA *__restrict__ ml, TA *__restrict__ mom, int nn, TA x, TA y, TA z,
@@ -253,7 +225,7 @@ __device__ __forceinline__ void deposit_tight(const GridT<TA> &ga, const TileGeo
     }
 }
 
-// deposit_lean with the terms formed in the particle precision T (FP32
+// deposit_tight with the terms formed in the particle precision T (FP32
 // particles: FP32 weights and products, as the register sums of the lane
 // cells) and added to the accumulation type TA.
 template <typename T, typename TA, class GEO>
@@ -486,7 +458,9 @@ inline size_t stage_lds_bytes(int variant, int block, int dtype) {
     const size_t rec = 8 * (dtype == SPIC_F64 ? 8 : 4);
     if (variant == 2) return (size_t)(block / 64) * kQueueCap * rec;
     if (variant == 3) return (size_t)(block / 64) * (64 * rec + sizeof(BalanceLds));
-    if (variant >= 5) return (size_t)(block / 64) * 64 * 7 * (dtype == SPIC_F64 ? 8 : 4);
+    if (variant == 5 || variant == 7)  // queue, reused as the balancing stage when it is flushed
+        return (size_t)(block / 64) * (64 * rec + sizeof(BalanceLds));
+    if (variant == 6 || variant == 8) return (size_t)(block / 64) * 64 * 7 * (dtype == SPIC_F64 ? 8 : 4);
     return 0;
 }
 
@@ -580,8 +554,13 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
     for (int q = 0; q < (AUX ? 80 : 1); ++q) xacc[q] = TP(0);
     int acell = -1;
     TP *lq = nullptr;  // per-wave queue, 7 arrays of 64 (x y z u v w q)
+    StagedParticle<TP> *lstage = nullptr;  // the same bytes while the queue is deposited
+    BalanceLds *lbal = nullptr;
     if constexpr (LANE) {
-        lq = (TP *)wstage + (threadIdx.x >> 6) * (7 * 64);
+        unsigned char *mine = wstage + (threadIdx.x >> 6) * (64 * sizeof(StagedParticle<TP>) + sizeof(BalanceLds));
+        lq = (TP *)mine;
+        lstage = (StagedParticle<TP> *)mine;
+        lbal = (BalanceLds *)(mine + 64 * sizeof(StagedParticle<TP>));
         lcell = lane_cell(tg, g.nx, g.ny, g.nz, txi, tyi, tzi, lane);
     }
 
@@ -761,16 +740,20 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
 #pragma unroll
                     for (int a = 0; a < 7; ++a) lq[a * 64 + pos] = rec[a];
                 if (qn + cnt >= 64) {
+                    // deposit the 64 queued particles re-placed across the
+                    // lanes so that each 16-lane group hits distinct bank
+                    // pairs (they sit in arbitrary cells), then queue the
+                    // lanes that did not fit
                     wave_sync();
                     TP r[7];
 #pragma unroll
                     for (int a = 0; a < 7; ++a) r[a] = lq[a * 64 + lane];
                     wave_sync();
+                    deposit_balanced<TP, TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, lstage, lbal, lane, true,
+                                                        r[0], r[1], r[2], r[3], r[4], r[5], r[6]);
                     if (enq && pos >= 64)
 #pragma unroll
                         for (int a = 0; a < 7; ++a) lq[a * 64 + pos - 64] = rec[a];
-                    deposit_lean<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, (TA)r[0], (TA)r[1], (TA)r[2], (TA)r[6],
-                                         (TA)r[3], (TA)r[4], (TA)r[5]);
                     qn += cnt - 64;
                 } else {
                     qn += cnt;
@@ -889,13 +872,14 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
     }
     if constexpr (LANE) {
         wave_sync();
-        if (lane < qn) {
-            TP r[7];
+        TP r[7] = {TP(0), TP(0), TP(0), TP(0), TP(0), TP(0), TP(0)};
+        if (lane < qn)
 #pragma unroll
             for (int a = 0; a < 7; ++a) r[a] = lq[a * 64 + lane];
-            deposit_lean<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, (TA)r[0], (TA)r[1], (TA)r[2], (TA)r[6], (TA)r[3],
-                                 (TA)r[4], (TA)r[5]);
-        }
+        wave_sync();
+        if (qn > 0)  // uniform
+            deposit_balanced<TP, TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, lstage, lbal, lane, lane < qn, r[0],
+                                                r[1], r[2], r[3], r[4], r[5], r[6]);
         settle(lacc);
         if (lcell >= 0) {
 #pragma unroll
@@ -947,6 +931,157 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
     }
 }
 
+// Deposit of a tile whose particles a mover-only launch has just moved
+// (variant 8, the second of its two kernels): the lane-cell register sums
+// and the compact queue of variant 5, with only the 80 sums and one
+// particle live; LDS holds the FP64 region moments (dense layout) and the
+// queues only (no fields), three workgroups of 256 per CU.
+template <typename TP, typename TF, typename TA, class GEO>
+__device__ __forceinline__ void deposit_body(const TileJob<TP, TF, TA> &J, int t, unsigned char *smem) {
+    TileGeom tg = J.tg;
+    if constexpr (GEO::fixed) {
+        tg.tx = GEO::tx; tg.ty = GEO::ty; tg.tz = GEO::tz; tg.halo = GEO::halo;
+        tg.rx = GEO::rx; tg.ry = GEO::ry; tg.rz = GEO::rz;
+        tg.slow = GEO::slow; tg.mid = GEO::mid; tg.fast = GEO::fast;
+        tg.sx = GEO::sx; tg.sy = GEO::sy; tg.sz = GEO::sz; tg.rnp = GEO::rnp;
+    }
+    const GridT<TP> &g = J.g;
+    const PartPtrs<TP> &p = J.p;
+    TA *__restrict__ mom = J.mom;
+    const int nn = J.nn;
+    const uint32_t beg = J.tile_off[t], end = J.tile_off[t + 1];
+    if (beg == end) return;
+    const int RNP = tg.rnp;
+    TA *ml = (TA *)smem;
+    TP *sq = (TP *)(smem + (((size_t)10 * RNP * sizeof(TA) + 15) & ~(size_t)15)) + (threadIdx.x >> 6) * (7 * 64);
+    const int tzi = t % tg.ntz, tyi = (t / tg.ntz) % tg.nty, txi = t / (tg.ntz * tg.nty);
+    int ox = (txi * tg.tx - tg.halo) % g.nx; ox += ox < 0 ? g.nx : 0;
+    int oy = (tyi * tg.ty - tg.halo) % g.ny; oy += oy < 0 ? g.ny : 0;
+    int oz = (tzi * tg.tz - tg.halo) % g.nz; oz += oz < 0 ? g.nz : 0;
+    const int RL = tg.rx * tg.ry * tg.rz;
+    const int sx = tg.sx, sy = tg.sy, sz = tg.sz;
+    for (int q = threadIdx.x; q < 10 * RNP; q += blockDim.x) ml[q] = TA(0);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int lc = lane_cell(tg, g.nx, g.ny, g.nz, txi, tyi, tzi, lane);
+    const int coff[8] = {0, sx, sy, sx + sy, sz, sx + sz, sy + sz, sx + sy + sz};
+    TP sacc[80];
+#pragma unroll
+    for (int q = 0; q < 80; ++q) sacc[q] = TP(0);
+    int sqn = 0;
+    const uint32_t stride = blockDim.x;
+    constexpr uint32_t ES = sizeof(TP);
+    uint32_t ii = beg + threadIdx.x;
+    TP nrec[7] = {TP(0), TP(0), TP(0), TP(0), TP(0), TP(0), TP(0)};
+    if (ii < end) {
+        const uint32_t o = ii * ES;
+        nrec[0] = ld32(p.x, o); nrec[1] = ld32(p.y, o); nrec[2] = ld32(p.z, o);
+        nrec[3] = ld32(p.u, o); nrec[4] = ld32(p.v, o); nrec[5] = ld32(p.w, o); nrec[6] = ld32(p.q, o);
+    }
+    for (uint32_t i0 = beg + (threadIdx.x & ~63u); i0 < end; i0 += stride, ii += stride) {
+        const bool valid = ii < end;
+        TP rec[7];
+#pragma unroll
+        for (int a = 0; a < 7; ++a) rec[a] = nrec[a];
+        const uint32_t inext = ii + stride;
+        if (inext < end) {  // the next particle loads while this one deposits
+            const uint32_t o = inext * ES;
+            nrec[0] = ld32(p.x, o); nrec[1] = ld32(p.y, o); nrec[2] = ld32(p.z, o);
+            nrec[3] = ld32(p.u, o); nrec[4] = ld32(p.v, o); nrec[5] = ld32(p.w, o); nrec[6] = ld32(p.q, o);
+        }
+        bool enq = false;
+        if (valid) {
+            // the cell from the particle-precision position, the in-cell
+            // offsets of the moved (already wrapped) position in the
+            // accumulation precision, the terms in the particle precision
+            // (as variant 5; at a face the two precisions may pick
+            // neighbouring cells, where the weights agree to rounding)
+            int rb, ijk[3];
+            Cell<TP> c32;
+            const bool in = region_locate(g, tg, ox, oy, oz, rec[0], rec[1], rec[2], rb, c32, ijk);
+            if (in && rb == lc) {
+                const TP u = rec[3], v = rec[4], w = rec[5];
+                const TP val[10] = {TP(1), u, v, w, u * u, u * v, u * w, v * v, v * w, w * w};
+                const TA qa = (TA)rec[6];
+                Cell<TA> c;
+                c.fx = cell_coord((TA)rec[0], J.ga.invd[0]) - (TA)ijk[0];
+                c.fy = cell_coord((TA)rec[1], J.ga.invd[1]) - (TA)ijk[1];
+                c.fz = cell_coord((TA)rec[2], J.ga.invd[2]) - (TA)ijk[2];
+                const TA gx = TA(1) - c.fx, gy = TA(1) - c.fy, gz = TA(1) - c.fz;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    // corner weight formed as pweights forms it, one at a time
+                    const TA wk = (((k & 1) ? c.fx : gx) * ((k & 2) ? c.fy : gy)) * ((k & 4) ? c.fz : gz);
+                    const TP qw = (TP)(qa * wk);
+#pragma unroll
+                    for (int m = 0; m < 10; ++m) sacc[k * 10 + m] += qw * val[m];
+                }
+            } else {
+                enq = true;
+            }
+        }
+        const unsigned long long vote = __ballot(enq);
+        if (vote) {
+            const int cnt = __popcll(vote);
+            const int pos = sqn + __popcll(vote & ((1ull << lane) - 1ull));
+            if (enq && pos < 64)
+#pragma unroll
+                for (int a = 0; a < 7; ++a) sq[a * 64 + pos] = rec[a];
+            if (sqn + cnt >= 64) {
+                wave_sync();
+                TP r[7];
+#pragma unroll
+                for (int a = 0; a < 7; ++a) r[a] = sq[a * 64 + lane];
+                wave_sync();
+                if (enq && pos >= 64)
+#pragma unroll
+                    for (int a = 0; a < 7; ++a) sq[a * 64 + pos - 64] = rec[a];
+                deposit_tight<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, (TA)r[0], (TA)r[1], (TA)r[2], (TA)r[6],
+                                       (TA)r[3], (TA)r[4], (TA)r[5]);
+                sqn += cnt - 64;
+            } else {
+                sqn += cnt;
+            }
+        }
+    }
+    wave_sync();
+    if (lane < sqn) {
+        TP r[7];
+#pragma unroll
+        for (int a = 0; a < 7; ++a) r[a] = sq[a * 64 + lane];
+        deposit_tight<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, (TA)r[0], (TA)r[1], (TA)r[2], (TA)r[6], (TA)r[3],
+                               (TA)r[4], (TA)r[5]);
+    }
+    settle(sacc);
+    if (lc >= 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            TA *dst = ml + lc + coff[k];
+#pragma unroll
+            for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, (TA)sacc[k * 10 + m]);
+        }
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < RL; r += blockDim.x) {
+        const RegionNode rn = region_node(tg, g.nx, g.ny, g.nz, ox, oy, oz, r);
+#pragma unroll
+        for (int m = 0; m < 10; ++m) {
+            const TA val = ml[m * RNP + rn.slot];
+            if (val != TA(0)) atomicAdd(mom + (size_t)m * nn + rn.gnode, val);
+        }
+    }
+}
+
+template <typename TP, typename TF, typename TA, class GEO>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3)))
+k_deposit_tiled(TileJob<TP, TF, TA> J, int chunk) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int b = blockIdx.x;
+    const int t = (b & 7) * chunk + (b >> 3);
+    if (t >= J.tg.ntiles) return;
+    deposit_body<TP, TF, TA, GEO>(J, t, smem);
+}
+
 // Variants (register budget -> waves per SIMD):
 //   0  every deposit is an LDS atomic; <= 128 VGPRs, 4 waves/SIMD
 //   1  as 0, and the 48 field corners of the last cell stay in registers,
@@ -955,10 +1090,15 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
 //      atomics for drifted particles; <= 256 VGPRs, 2 waves/SIMD
 //   3  as 0, with the bank-balanced deposit (per-wave staging in LDS)
 //   4  segmented wave pre-reduction of the deposit (cell-major sort order)
+//   5  lane-cell sums in particle-precision registers + compact queue of
+//      drifted particles, deposited bank-balanced; <= 256 VGPRs (its LDS
+//      keeps it at 2 waves/SIMD at 256 threads anyway)
+//   6  two-phase mover / deposit pass; <= 168 VGPRs (FP32), 3 waves/SIMD
+//   7  as 5 with a second register set for one drift cell; <= 256 VGPRs
 template <int VAR, typename TP>
 struct VariantWaves {
     static constexpr int value =
-        (VAR == 0 || VAR == 3 || VAR == 4) ? 4 : (VAR == 1 || ((VAR == 5 || VAR == 6) && sizeof(TP) == 4)) ? 3 : 2;
+        (VAR == 0 || VAR == 3 || VAR == 4) ? 4 : (VAR == 1 || (VAR == 6 && sizeof(TP) == 4)) ? 3 : 2;
 };
 
 template <typename TP, typename TF, typename TA, int VAR, class GEO>
@@ -1015,10 +1155,41 @@ static void tiled_launch(const TileJob<TP, TF, TA> &job, int chunk, size_t lds, 
     hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, VAR, GEO>), dim3(8 * chunk), dim3(block), lds, s, job, chunk);
 }
 
+// Variant 8: a mover-only launch (variant 0's tile body without moments,
+// LDS for the fields only) and then the deposit kernel over the moved
+// particles (LDS for the moments and queues only).
+template <typename TP, typename TF, typename TA, class GEO>
+static void split_launch(const TileJob<TP, TF, TA> &job, int chunk, const LaunchCfg &cfg, hipStream_t s) {
+    const TileGeom &tg = job.tg;
+    const size_t fl = ((size_t)tg.rnp * sizeof(LdsFieldNode<TP>) + 15) & ~(size_t)15;
+    TileJob<TP, TF, TA> mv = job;
+    mv.mom = nullptr;
+    allow_lds(k_fused_tiled<TP, TF, TA, 0, GEO>, fl);
+    hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, 0, GEO>), dim3(8 * chunk), dim3(512), fl, s, mv, chunk);
+    if (!job.mom) return;
+    // the deposit kernel's region uses the dense layout (smallest LDS: three
+    // workgroups per CU)
+    TileJob<TP, TF, TA> dj = job;
+    const RegionLayout lay = region_layout(tg.tx, tg.ty, tg.tz, tg.halo, tg.slow, tg.mid, tg.fast, 2);
+    dj.tg.sx = lay.sx; dj.tg.sy = lay.sy; dj.tg.sz = lay.sz; dj.tg.rnp = lay.rnp;
+    const size_t dl = (((size_t)10 * lay.rnp * sizeof(TA) + 15) & ~(size_t)15) +
+                      (size_t)(cfg.tile_block / 64) * 64 * 7 * sizeof(TP);
+    if (cfg.fixed_geo && geo_is<GeoDense>(dj.tg)) {
+        allow_lds(k_deposit_tiled<TP, TF, TA, GeoDense>, dl);
+        hipLaunchKernelGGL((k_deposit_tiled<TP, TF, TA, GeoDense>), dim3(8 * chunk), dim3(cfg.tile_block), dl, s, dj,
+                           chunk);
+    } else {
+        allow_lds(k_deposit_tiled<TP, TF, TA, GeoRuntime>, dl);
+        hipLaunchKernelGGL((k_deposit_tiled<TP, TF, TA, GeoRuntime>), dim3(8 * chunk), dim3(cfg.tile_block), dl, s,
+                           dj, chunk);
+    }
+}
+
 template <typename TP, typename TF, typename TA, class GEO>
 static void tiled_variant(const TileJob<TP, TF, TA> &job, int chunk, size_t lds, const LaunchCfg &cfg,
                           hipStream_t s) {
     switch (cfg.variant) {
+        case 8: split_launch<TP, TF, TA, GEO>(job, chunk, cfg, s); break;
         case 1: tiled_launch<TP, TF, TA, 1, GEO>(job, chunk, lds, cfg.tile_block, s); break;
         case 2: tiled_launch<TP, TF, TA, 2, GEO>(job, chunk, lds, cfg.tile_block, s); break;
         case 3: tiled_launch<TP, TF, TA, 3, GEO>(job, chunk, lds, cfg.tile_block, s); break;
