@@ -212,12 +212,14 @@ def cpu_baseline(h, target_s: float = 12.0):
                       "128x64x32 grid, %d fused steps (mover + FP64 deposit), %.1f s" % (n, steps, el)}
 
 
-def _engine_ctx(budget=0, tuned_key=None):
+def _engine_ctx(budget=0, tuned_key=None, variant=-1):
     from paper_2008_04397_amd import autotune, spic
     ctx = spic.Context(0, budget)
     cfg = autotune.load(tuned_key) if tuned_key else None
     if cfg:
         autotune.apply(ctx, cfg)
+    if variant >= 0:
+        ctx.set_option("tile_variant", variant)
     return ctx
 
 
@@ -227,7 +229,7 @@ def bench_ensemble(args):
     from paper_2008_04397_amd import spic
     boxes = W.ensemble_boxes(64)
     nsteps = 50
-    ctx = _engine_ctx()
+    ctx = _engine_ctx(variant=args.variant)
     runs, total, gbytes = [], 0, 0.0
     log("[bench] generating 64 boxes")
     for b, h in enumerate(boxes):
@@ -362,7 +364,7 @@ def bench_serving(args):
     reqs = W.serving_stream(args.requests)
     res = {}
     for mode in ("continuous", "serial"):
-        ctx = _engine_ctx(budget=64 * (1 << 30))
+        ctx = _engine_ctx(budget=64 * (1 << 30), variant=args.variant)
         if args.srpt_aging >= 0:
             ctx.set_option("srpt_aging", args.srpt_aging)
         # warm the engine and the kernels once

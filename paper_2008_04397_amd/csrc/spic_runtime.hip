@@ -285,8 +285,8 @@ int spic_set_option(spic_ctx ctx, const char *key, int64_t value) {
             if ((!strcmp(key, "tile_x") || !strcmp(key, "tile_y") || !strcmp(key, "tile_z")) &&
                 (value < 1 || value > 64))
                 return ctx->fail(SPIC_E_ARG, "tile sizes must be in [1, 64]");
-            if (!strcmp(key, "tile_variant") && (value < -1 || value > 8))
-                return ctx->fail(SPIC_E_ARG, "tile_variant must be -1 or in 0..8");
+            if (!strcmp(key, "tile_variant") && (value < -1 || value > 9))
+                return ctx->fail(SPIC_E_ARG, "tile_variant must be -1 or in 0..9");
             if (!strcmp(key, "batch_particles") && (value < 1024 || value > ((int64_t)1 << 29)))
                 return ctx->fail(SPIC_E_ARG, "batch_particles must be in [1024, 2^29]");
             if (!strcmp(key, "tick_items") && (value < 0 || value > ((int64_t)1 << 30)))

@@ -458,7 +458,7 @@ inline size_t stage_lds_bytes(int variant, int block, int dtype) {
     const size_t rec = 8 * (dtype == SPIC_F64 ? 8 : 4);
     if (variant == 2) return (size_t)(block / 64) * kQueueCap * rec;
     if (variant == 3) return (size_t)(block / 64) * (64 * rec + sizeof(BalanceLds));
-    if (variant == 5 || variant == 7)  // queue, reused as the balancing stage when it is flushed
+    if (variant == 5 || variant == 7 || variant == 9)  // queue, reused as the balancing stage when flushed
         return (size_t)(block / 64) * (64 * rec + sizeof(BalanceLds));
     if (variant == 6 || variant == 8) return (size_t)(block / 64) * 64 * 7 * (dtype == SPIC_F64 ? 8 : 4);
     return 0;
@@ -931,6 +931,289 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
     }
 }
 
+// Variant 9: variant 5 with two particles per thread in flight.  At the two
+// waves per SIMD that variant 5's LDS allows, a lone particle's chain of
+// three dependent LDS gathers leaves the SIMD idle; here each thread moves
+// the particles i and i + B (B threads, the same lane of the next rank
+// block: the same sort cell) together, so the gathers and rotations of the
+// two are interleaved.  Deposit as variant 5 (lane-cell registers, queue
+// deposited bank-balanced).
+template <typename TP>
+struct CellCache {
+    int ijk[3];
+    int rb;
+    bool in;
+    Cell<TP> c;
+};
+
+// Cell of a point for an LDS gather: the cached cell when the point is still
+// inside it (exactly the offsets a fresh locate gives), else a new locate.
+template <typename TP>
+__device__ __forceinline__ bool pair_locate(const GridT<TP> &g, const TileGeom &tg, int ox, int oy, int oz, TP px,
+                                            TP py, TP pz, CellCache<TP> &cc, int &rb, Cell<TP> &c) {
+    const TP tx = cell_coord(px, g.invd[0]) - (TP)cc.ijk[0];
+    const TP ty = cell_coord(py, g.invd[1]) - (TP)cc.ijk[1];
+    const TP tz = cell_coord(pz, g.invd[2]) - (TP)cc.ijk[2];
+    if (cc.ijk[0] >= 0 && px >= TP(0) && px < g.L[0] && py >= TP(0) && py < g.L[1] && pz >= TP(0) &&
+        pz < g.L[2] && tx >= TP(0) && tx < TP(1) && ty >= TP(0) && ty < TP(1) && tz >= TP(0) && tz < TP(1)) {
+        c = cc.c;
+        c.fx = tx;
+        c.fy = ty;
+        c.fz = tz;
+        rb = cc.rb;
+        return cc.in;
+    }
+    const bool in = region_locate(g, tg, ox, oy, oz, px, py, pz, rb, c, cc.ijk);
+    if (in) {
+        c.base = 0; c.ox = 0; c.oy = 0; c.oz = 0;
+    }
+    cc.c = c;
+    cc.rb = rb;
+    cc.in = in;
+    return in;
+}
+
+template <typename TP>
+__device__ __forceinline__ void pair_rotate(const MoveT<TP> &mv, const TP F[6], TP x0, TP y0, TP z0, TP u0, TP v0,
+                                            TP w0, TP &ub, TP &vb, TP &wb, TP &xb, TP &yb, TP &zb) {
+    const TP ut = u0 + mv.beta * F[0];
+    const TP vt = v0 + mv.beta * F[1];
+    const TP wt = w0 + mv.beta * F[2];
+    const TP bx = mv.bc * F[3], by = mv.bc * F[4], bz = mv.bc * F[5];
+    const TP vdb = ut * bx + vt * by + wt * bz;
+    const TP inv = recip_ge1(TP(1) + (bx * bx + by * by + bz * bz));
+    ub = (ut + (vt * bz - wt * by) + vdb * bx) * inv;
+    vb = (vt + (wt * bx - ut * bz) + vdb * by) * inv;
+    wb = (wt + (ut * by - vt * bx) + vdb * bz) * inv;
+    xb = x0 + ub * mv.hdt;
+    yb = y0 + vb * mv.hdt;
+    zb = z0 + wb * mv.hdt;
+}
+
+// The implicit step (same arithmetic as implicit_move) of two particles in
+// lock-step; `s[0..5]` = x y z u v w of each, updated in place.
+template <typename TP, typename TF>
+__device__ __forceinline__ void pair_move(const GridT<TP> &g, const MoveT<TP> &mv, const FieldPtrs<TF> &f,
+                                          const LdsFieldNode<TP> *__restrict__ fl, const TileGeom &tg, int ox,
+                                          int oy, int oz, CellCache<TP> &cca, CellCache<TP> &ccb, TP (&a)[6],
+                                          TP (&b)[6]) {
+    TP ua = a[3], va = a[4], wa = a[5], xa = a[0], ya = a[1], za = a[2];
+    TP ub = b[3], vb = b[4], wb = b[5], xb = b[0], yb = b[1], zb = b[2];
+    for (int it = 0; it < mv.niter; ++it) {
+        TP Fa[6], Fb[6];
+        int rba, rbb;
+        Cell<TP> ca, cb;
+        const bool ina = pair_locate(g, tg, ox, oy, oz, xa, ya, za, cca, rba, ca);
+        const bool inb = pair_locate(g, tg, ox, oy, oz, xb, yb, zb, ccb, rbb, cb);
+        if (ina & inb) {  // the common case: both gathers from LDS, one block
+            gather_lds(fl, tg, rba, ca, Fa);
+            gather_lds(fl, tg, rbb, cb, Fb);
+        } else {
+            if (ina) {
+                gather_lds(fl, tg, rba, ca, Fa);
+            } else {
+                gather_cell_global(f, ca, Fa);
+                settle(Fa);
+            }
+            if (inb) {
+                gather_lds(fl, tg, rbb, cb, Fb);
+            } else {
+                gather_cell_global(f, cb, Fb);
+                settle(Fb);
+            }
+        }
+        pair_rotate(mv, Fa, a[0], a[1], a[2], a[3], a[4], a[5], ua, va, wa, xa, ya, za);
+        pair_rotate(mv, Fb, b[0], b[1], b[2], b[3], b[4], b[5], ub, vb, wb, xb, yb, zb);
+    }
+    a[3] = TP(2) * ua - a[3]; a[4] = TP(2) * va - a[4]; a[5] = TP(2) * wa - a[5];
+    b[3] = TP(2) * ub - b[3]; b[4] = TP(2) * vb - b[4]; b[5] = TP(2) * wb - b[5];
+    a[0] = pwrap(a[0] + ua * mv.dt, g.L[0], g.invL[0]);
+    a[1] = pwrap(a[1] + va * mv.dt, g.L[1], g.invL[1]);
+    a[2] = pwrap(a[2] + wa * mv.dt, g.L[2], g.invL[2]);
+    b[0] = pwrap(b[0] + ub * mv.dt, g.L[0], g.invL[0]);
+    b[1] = pwrap(b[1] + vb * mv.dt, g.L[1], g.invL[1]);
+    b[2] = pwrap(b[2] + wb * mv.dt, g.L[2], g.invL[2]);
+}
+
+template <typename TP, typename TF, typename TA, class GEO>
+__device__ __forceinline__ void tile_body_pair(const TileJob<TP, TF, TA> &J, int t, unsigned char *smem) {
+    const GridT<TP> &g = J.g;
+    TileGeom tg = J.tg;
+    if constexpr (GEO::fixed) {
+        tg.tx = GEO::tx; tg.ty = GEO::ty; tg.tz = GEO::tz; tg.halo = GEO::halo;
+        tg.rx = GEO::rx; tg.ry = GEO::ry; tg.rz = GEO::rz;
+        tg.slow = GEO::slow; tg.mid = GEO::mid; tg.fast = GEO::fast;
+        tg.sx = GEO::sx; tg.sy = GEO::sy; tg.sz = GEO::sz; tg.rnp = GEO::rnp;
+    }
+    const FieldPtrs<TF> &f = J.f;
+    const PartPtrs<TP> &p = J.p;
+    const PartPtrs<TP> &pin = J.in;
+    TA *__restrict__ mom = J.mom;
+    const int nn = J.nn;
+    const uint32_t beg = J.tile_off[t], end = J.tile_off[t + 1];
+    if (beg == end) return;
+    const int RNP = tg.rnp;
+    const size_t fbytes = (RNP * sizeof(LdsFieldNode<TP>) + 15) & ~(size_t)15;
+    LdsFieldNode<TP> *fl = (LdsFieldNode<TP> *)smem;
+    TA *ml = (TA *)(smem + fbytes);
+    unsigned char *wstage = smem + fbytes + (((size_t)10 * RNP * sizeof(TA) + 15) & ~(size_t)15);
+    const int tzi = t % tg.ntz, tyi = (t / tg.ntz) % tg.nty, txi = t / (tg.ntz * tg.nty);
+    int ox = (txi * tg.tx - tg.halo) % g.nx; ox += ox < 0 ? g.nx : 0;
+    int oy = (tyi * tg.ty - tg.halo) % g.ny; oy += oy < 0 ? g.ny : 0;
+    int oz = (tzi * tg.tz - tg.halo) % g.nz; oz += oz < 0 ? g.nz : 0;
+    const int RL = tg.rx * tg.ry * tg.rz;
+    const int sx = tg.sx, sy = tg.sy, sz = tg.sz;
+    for (int r = threadIdx.x; r < RL; r += blockDim.x) {
+        const RegionNode rn = region_node(tg, g.nx, g.ny, g.nz, ox, oy, oz, r);
+        LdsFieldNode<TP> fn;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) fn.v[m] = (TP)f.f[m][rn.gnode];
+        fl[rn.slot] = fn;
+    }
+    if (mom)
+        for (int q = threadIdx.x; q < 10 * RNP; q += blockDim.x) ml[q] = TA(0);
+    __syncthreads();
+
+    const int coff[8] = {0, sx, sy, sx + sy, sz, sx + sz, sy + sz, sx + sy + sz};
+    const int lane = threadIdx.x & 63;
+    const int lcell = lane_cell(tg, g.nx, g.ny, g.nz, txi, tyi, tzi, lane);
+    TP lacc[80];
+#pragma unroll
+    for (int q = 0; q < 80; ++q) lacc[q] = TP(0);
+    unsigned char *mine = wstage + (threadIdx.x >> 6) * (64 * sizeof(StagedParticle<TP>) + sizeof(BalanceLds));
+    TP *lq = (TP *)mine;
+    StagedParticle<TP> *lstage = (StagedParticle<TP> *)mine;
+    BalanceLds *lbal = (BalanceLds *)(mine + 64 * sizeof(StagedParticle<TP>));
+    int qn = 0;
+    CellCache<TP> cca, ccb;
+    cca.ijk[0] = -1; ccb.ijk[0] = -1;
+    cca.rb = ccb.rb = 0;
+    cca.in = ccb.in = false;
+    cca.ijk[1] = cca.ijk[2] = ccb.ijk[1] = ccb.ijk[2] = 0;
+    const bool copy_id = J.copy_rest && pin.id;
+    const uint32_t B = blockDim.x;
+    constexpr uint32_t ES = sizeof(TP);
+
+    // one particle's deposit: lane-cell registers or the queue
+    auto deposit = [&](bool valid, const TP (&s)[6], TP q) {
+        bool enq = false;
+        if (valid && mom) {
+            int rb;
+            Cell<TA> c;
+            const bool in = region_locate(J.ga, tg, ox, oy, oz, (TA)s[0], (TA)s[1], (TA)s[2], rb, c);
+            if (in && rb == lcell) {
+                TA wt8[8];
+                pweights(c.fx, c.fy, c.fz, wt8);
+                const TP u = s[3], v = s[4], w = s[5];
+                const TP val[10] = {TP(1), u, v, w, u * u, u * v, u * w, v * v, v * w, w * w};
+                const TA qa = (TA)q;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const TP qw = (TP)(qa * wt8[k]);
+#pragma unroll
+                    for (int m = 0; m < 10; ++m) lacc[k * 10 + m] += qw * val[m];
+                }
+            } else {
+                enq = true;
+            }
+        }
+        const unsigned long long vote = __ballot(enq);
+        if (vote) {
+            const int cnt = __popcll(vote);
+            const int pos = qn + __popcll(vote & ((1ull << lane) - 1ull));
+            const TP rec[7] = {s[0], s[1], s[2], s[3], s[4], s[5], q};
+            if (enq && pos < 64)
+#pragma unroll
+                for (int a = 0; a < 7; ++a) lq[a * 64 + pos] = rec[a];
+            if (qn + cnt >= 64) {
+                wave_sync();
+                TP r[7];
+#pragma unroll
+                for (int a = 0; a < 7; ++a) r[a] = lq[a * 64 + lane];
+                wave_sync();
+                deposit_balanced<TP, TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, lstage, lbal, lane, true, r[0], r[1],
+                                              r[2], r[3], r[4], r[5], r[6]);
+                if (enq && pos >= 64)
+#pragma unroll
+                    for (int a = 0; a < 7; ++a) lq[a * 64 + pos - 64] = rec[a];
+                qn += cnt - 64;
+            } else {
+                qn += cnt;
+            }
+        }
+    };
+
+    // lane l takes particles beg + l' + 2kB and beg + l' + (2k+1)B (l' = thread index)
+    for (uint32_t i0 = beg + (threadIdx.x & ~63u); i0 < end; i0 += 2 * B) {
+        const uint32_t ia = i0 + lane, ib = ia + B;
+        const bool va = ia < end, vb = ib < end;
+        TP a[6] = {TP(0), TP(0), TP(0), TP(0), TP(0), TP(0)}, b[6] = {TP(0), TP(0), TP(0), TP(0), TP(0), TP(0)};
+        TP qa = TP(0), qb = TP(0);
+        int64_t ida = 0, idb = 0;
+        if (va) {
+            const uint32_t o = ia * ES;
+            a[0] = ld32(pin.x, o); a[1] = ld32(pin.y, o); a[2] = ld32(pin.z, o);
+            a[3] = ld32(pin.u, o); a[4] = ld32(pin.v, o); a[5] = ld32(pin.w, o); qa = ld32(pin.q, o);
+            if (copy_id) ida = pin.id[ia];
+        }
+        if (vb) {
+            const uint32_t o = ib * ES;
+            b[0] = ld32(pin.x, o); b[1] = ld32(pin.y, o); b[2] = ld32(pin.z, o);
+            b[3] = ld32(pin.u, o); b[4] = ld32(pin.v, o); b[5] = ld32(pin.w, o); qb = ld32(pin.q, o);
+            if (copy_id) idb = pin.id[ib];
+        }
+        if (va) {  // a lane past the end moves its zero slot harmlessly and stores nothing
+            pair_move(g, J.mv, f, fl, tg, ox, oy, oz, cca, ccb, a, b);
+            const uint32_t o = ia * ES;
+            st32(p.x, o, a[0]); st32(p.y, o, a[1]); st32(p.z, o, a[2]);
+            st32(p.u, o, a[3]); st32(p.v, o, a[4]); st32(p.w, o, a[5]);
+            if (J.copy_rest) {
+                st32(p.q, o, qa);
+                if (copy_id) p.id[ia] = ida;
+            }
+            if (vb) {
+                const uint32_t ob = ib * ES;
+                st32(p.x, ob, b[0]); st32(p.y, ob, b[1]); st32(p.z, ob, b[2]);
+                st32(p.u, ob, b[3]); st32(p.v, ob, b[4]); st32(p.w, ob, b[5]);
+                if (J.copy_rest) {
+                    st32(p.q, ob, qb);
+                    if (copy_id) p.id[ib] = idb;
+                }
+            }
+        }
+        deposit(va, a, qa);
+        deposit(vb, b, qb);
+    }
+    if (!mom) return;
+    wave_sync();
+    TP r[7] = {TP(0), TP(0), TP(0), TP(0), TP(0), TP(0), TP(0)};
+    if (lane < qn)
+#pragma unroll
+        for (int a = 0; a < 7; ++a) r[a] = lq[a * 64 + lane];
+    wave_sync();
+    if (qn > 0)
+        deposit_balanced<TP, TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, lstage, lbal, lane, lane < qn, r[0], r[1],
+                                      r[2], r[3], r[4], r[5], r[6]);
+    settle(lacc);
+    if (lcell >= 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            TA *dst = ml + lcell + coff[k];
+#pragma unroll
+            for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, (TA)lacc[k * 10 + m]);
+        }
+    }
+    __syncthreads();
+    for (int r2 = threadIdx.x; r2 < RL; r2 += blockDim.x) {
+        const RegionNode rn = region_node(tg, g.nx, g.ny, g.nz, ox, oy, oz, r2);
+#pragma unroll
+        for (int m = 0; m < 10; ++m) {
+            const TA val = ml[m * RNP + rn.slot];
+            if (val != TA(0)) atomicAdd(mom + (size_t)m * nn + rn.gnode, val);
+        }
+    }
+}
+
 // Deposit of a tile whose particles a mover-only launch has just moved
 // (variant 8, the second of its two kernels): the lane-cell register sums
 // and the compact queue of variant 5, with only the 80 sums and one
@@ -1095,6 +1378,9 @@ k_deposit_tiled(TileJob<TP, TF, TA> J, int chunk) {
 //      keeps it at 2 waves/SIMD at 256 threads anyway)
 //   6  two-phase mover / deposit pass; <= 168 VGPRs (FP32), 3 waves/SIMD
 //   7  as 5 with a second register set for one drift cell; <= 256 VGPRs
+//   8  two launches: mover only (variant 0 without moments), then the
+//      lane-cell deposit kernel over the moved particles
+//   9  as 5 with two particles per thread in flight; <= 256 VGPRs
 template <int VAR, typename TP>
 struct VariantWaves {
     static constexpr int value =
@@ -1108,7 +1394,8 @@ k_fused_tiled(TileJob<TP, TF, TA> J, int chunk) {
     const int b = blockIdx.x;
     const int t = (b & 7) * chunk + (b >> 3);
     if (t >= J.tg.ntiles) return;
-    tile_body<TP, TF, TA, VAR, GEO>(J, t, smem);
+    if constexpr (VAR == 9) tile_body_pair<TP, TF, TA, GEO>(J, t, smem);
+    else tile_body<TP, TF, TA, VAR, GEO>(J, t, smem);
 }
 
 // Persistent work-list kernel: workgroups take (job, tile) items from an
@@ -1128,7 +1415,8 @@ k_worklist(const TileJob<TP, TF, TA> *__restrict__ jobs, const uint2 *__restrict
         if (it >= nitems) break;
         const uint2 item = items[it];
         const TileJob<TP, TF, TA> J = jobs[item.x];
-        tile_body<TP, TF, TA, VAR, GEO>(J, (int)item.y, smem);
+        if constexpr (VAR == 9) tile_body_pair<TP, TF, TA, GEO>(J, (int)item.y, smem);
+        else tile_body<TP, TF, TA, VAR, GEO>(J, (int)item.y, smem);
     }
 }
 
@@ -1197,6 +1485,7 @@ static void tiled_variant(const TileJob<TP, TF, TA> &job, int chunk, size_t lds,
         case 5: tiled_launch<TP, TF, TA, 5, GEO>(job, chunk, lds, cfg.tile_block, s); break;
         case 6: tiled_launch<TP, TF, TA, 6, GEO>(job, chunk, lds, cfg.tile_block, s); break;
         case 7: tiled_launch<TP, TF, TA, 7, GEO>(job, chunk, lds, cfg.tile_block, s); break;
+        case 9: tiled_launch<TP, TF, TA, 9, GEO>(job, chunk, lds, cfg.tile_block, s); break;
         default: tiled_launch<TP, TF, TA, 0, GEO>(job, chunk, lds, cfg.tile_block, s);
     }
 }
@@ -1297,6 +1586,7 @@ static int worklist_groups_v(int variant, size_t lds, int block, int nitems, int
         case 5: return worklist_groups_t<TP, TF, TA, 5, GEO>(lds, block, nitems, max_groups);
         case 6: return worklist_groups_t<TP, TF, TA, 6, GEO>(lds, block, nitems, max_groups);
         case 7: return worklist_groups_t<TP, TF, TA, 7, GEO>(lds, block, nitems, max_groups);
+        case 9: return worklist_groups_t<TP, TF, TA, 9, GEO>(lds, block, nitems, max_groups);
         default: return worklist_groups_t<TP, TF, TA, 0, GEO>(lds, block, nitems, max_groups);
     }
 }
@@ -1334,6 +1624,7 @@ static hipError_t worklist_v(int variant, const void *jobs, const uint2 *items, 
         case 5: return worklist_t<TP, TF, TA, 5, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
         case 6: return worklist_t<TP, TF, TA, 6, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
         case 7: return worklist_t<TP, TF, TA, 7, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
+        case 9: return worklist_t<TP, TF, TA, 9, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
         default: return worklist_t<TP, TF, TA, 0, GEO>(jobs, items, nitems, counter, lds, block, groups, s);
     }
 }

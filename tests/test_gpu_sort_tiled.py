@@ -138,7 +138,7 @@ def _gpu_steps(spic, ctx, h, f, sps, qoms, nsteps, dtype=torch.float64, sort_eve
     return [spic.to_host(d) for d in dev], [m.cpu().numpy() for m in moms]
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_tiled_fp64_every_step_matches_oracle(spic, ctx, variant):
     """32x16x4 cells, 4 species, 10 steps, sorted every 4 steps; with and
     without home-cell register accumulation of the deposit."""
@@ -158,7 +158,7 @@ def test_tiled_fp64_every_step_matches_oracle(spic, ctx, variant):
     _gpu_steps(spic, ctx, h, f, sps, h.qoms, 10, check=check)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_tiled_fp32_one_step(spic, ctx, variant):
     ctx.set_option("tile_variant", variant)
     h = W.harris_32x16x4()
@@ -181,7 +181,8 @@ def test_tiled_fp32_one_step(spic, ctx, variant):
                                                ((4, 4, 2), 1, 5), ((3, 3, 3), 1, 5), ((4, 4, 4), 0, 6),
                                                ((2, 4, 8), 1, 6), ((3, 3, 3), 2, 6), ((4, 4, 4), 0, 7),
                                                ((2, 4, 8), 1, 7), ((4, 4, 4), 0, 8), ((2, 4, 8), 1, 8),
-                                               ((3, 3, 3), 2, 8)])
+                                               ((3, 3, 3), 2, 8), ((4, 4, 4), 0, 9), ((2, 4, 8), 1, 9),
+                                               ((3, 3, 3), 2, 9), ((4, 4, 2), 1, 9)])
 def test_tile_shapes_and_halo_overflow_match_oracle(spic, ctx, tile, halo, variant):
     """Fast particles leave small regions (halo 0) -> global fallbacks; tile
     shapes that do not divide the grid leave ragged edge tiles."""
@@ -201,7 +202,7 @@ def test_tile_shapes_and_halo_overflow_match_oracle(spic, ctx, tile, halo, varia
         P.assert_moments(ms[s], oms[s], P.MOM64)
 
 
-@pytest.mark.parametrize("variant", [0, 4, 5, 6, 8])
+@pytest.mark.parametrize("variant", [0, 4, 5, 6, 8, 9])
 @pytest.mark.parametrize("cells", [(5, 3, 2), (2, 2, 2), (9, 7, 5)])
 def test_tiny_and_odd_grids(spic, ctx, cells, variant):
     """Grids smaller than one LDS region: periodic images alias inside it."""
@@ -217,10 +218,10 @@ def test_tiny_and_odd_grids(spic, ctx, cells, variant):
         P.assert_moments(ms[s], oms[s], P.MOM64)
 
 
-@pytest.mark.parametrize("variant", [5, 6, 7, 8])
+@pytest.mark.parametrize("variant", [5, 6, 7, 8, 9])
 @pytest.mark.parametrize("L", [(1.0, 4.0, 2.0), (4.0, 1.0, 2.0), (4.0, 2.0, 1.0)])
 def test_lane_cell_variant_with_each_slow_axis(spic, ctx, L, variant):
-    """Variants 5 to 8 map lane l of a full 4x4x4 tile to local cell l,
+    """Variants 5 to 9 map lane l of a full 4x4x4 tile to local cell l,
     whose index depends on which axis is the slow one (the finest cells):
     x, y and z in turn, 3 steps with a sort every step and every 2 steps."""
     ctx.set_option("tile_variant", variant)
