@@ -400,7 +400,7 @@ def main():
                     help="autotune block size, variant, layout and cadence first (cached per workload class); "
                          "the default uses the library defaults, which are the measured best on MI355X")
     ap.add_argument("--no-tune", action="store_true", help="(default) use the library defaults")
-    ap.add_argument("--variant", type=int, default=-1, help="tiled kernel variant (-1: autotuned)")
+    ap.add_argument("--variant", type=int, default=-1, help="tiled kernel variant (-1: the library default for the precision)")
     ap.add_argument("--path", type=int, default=0)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
