@@ -185,6 +185,11 @@ int spic_version(void);
  *                  particles and 0 for FP64)
  *   sort_ordered   1 = a re-sort walks each tile of the current order in
  *                  order, so ranks inside a cell keep that order (0/1)
+ *   sort_rows      1 = full rows: a tile of n particles and C cells gets
+ *                  n / C rows of C slots, slot (r, c) holding rank r of cell
+ *                  c where that exists and the particles of higher ranks
+ *                  filling the rest; 0 = plain rank blocks (default 1 for
+ *                  tile variants 5-9, else 0)
  *   graph          batch engine: replay unchanged ticks as a hipGraph (0/1)
  *   batch_particles  batch engine: particles per streamed batch
  *   max_groups     batch engine: cap on workgroups of the persistent launch

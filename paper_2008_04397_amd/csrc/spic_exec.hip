@@ -37,12 +37,17 @@ std::string spic_ctx_s::layout_key(const spic_grid &g, const spic_species &s) co
 // cells, so no padding for bank spread either); the others rank-major.  The
 // two-phase variant deposits mostly from registers and takes the dense
 // layout (the smallest LDS footprint, more workgroups per CU).
+// Full rows pay off for the lane-cell variants (5-9: lane c keeps cell c's
+// moments); the LDS-atomic variants keep plain rank blocks, whose rows
+// never hold one cell twice.
 TileGeom spic_ctx_s::tile_geom(const spic_grid &g, int dtype) const {
-    const int var = (int)opt("tile_variant", -1);
+    int var = (int)opt("tile_variant", -1);
+    if (var < 0) var = auto_variant(dtype, SPIC_F64);
     const bool cm = var == 4;
     const int dflt = var == 6 ? 2 : (dtype == SPIC_F64 || cm) ? 0 : 1;
     return make_tile_geom(g, (int)opt("tile_x", 4), (int)opt("tile_y", 4), (int)opt("tile_z", 4),
-                          (int)opt("halo", 1), (int)opt("bank_align", dflt), cm);
+                          (int)opt("halo", 1), (int)opt("bank_align", dflt), cm,
+                          opt("sort_rows", var >= 5 ? 1 : 0) != 0);
 }
 
 

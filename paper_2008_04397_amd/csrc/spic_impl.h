@@ -90,8 +90,15 @@ struct TileGeom {
     // Order of a tile's particles after a sort: 0 rank-major (rank 0 of
     // every cell, then rank 1, ...: a wave's lanes in distinct cells), 1
     // cell-major (all particles of cell 0, then cell 1, ...: a wave's lanes
-    // mostly in one cell, for the segmented deposit).
-    int cellmajor, pad;
+    // mostly in one cell, for the segmented deposit).  rows (rank-major
+    // only): 1 = full rows -- a tile of n particles and C cells has
+    // R = n / C rows in which slot (r, c) holds rank r of cell c whenever
+    // cell c has more than r particles; the particles of ranks >= R fill the
+    // remaining slots of those rows, then a last partial row -- so lane c
+    // holds cell c for all but a few particles even when the cell counts
+    // differ; 0 = plain rank blocks (a rank's block holds only the cells
+    // that have that rank).
+    int cellmajor, rows;
 };
 
 // LDS bank spread of a region layout.  A wave deposits with one lane per
@@ -304,7 +311,7 @@ hipError_t launch_deposit_generic(const spic_grid &g, const SpeciesWork &w, cons
 
 // Sort (spic_sort.hip).
 TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo, int layout = 1,
-                        bool cellmajor = false);
+                        bool cellmajor = false, bool rows = true);
 size_t sort_scratch_bytes(int64_t n, int dtype, bool with_id, const TileGeom &tg);
 // prev: tile_off already holds the per-tile ranges of the particles'
 // current order (an earlier sort with the same tiles and n); the key pass

@@ -192,6 +192,8 @@ static const char *const kOptionNames[] = {
                     // 3 bank-balanced LDS deposit, 4 segmented wave pre-reduction (cell-major order)
     "fixed_geo",    // tiled kernel: 1 = compile-time region geometry for 4x4x4 tiles, halo 1
     "sort_ordered", // sort: 1 = ranks follow the previous order (a sorted species' tiles walked in order)
+    "sort_rows",    // sort: 1 = full rows (lane = cell for all but a few particles), 0 = plain rank blocks
+                    // (default: 1 for the lane-cell variants 5-9)
     "bank_align",   // tiled kernel LDS layout: 0 compact conflict-free, 1 + slow-axis stride keeps bank pairs,
                     // 2 dense (no padding)
     "graph",        // batch engine: 1 = replay unchanged ticks as a hipGraph
@@ -293,7 +295,8 @@ int spic_set_option(spic_ctx ctx, const char *key, int64_t value) {
                 return ctx->fail(SPIC_E_ARG, "tick_items must be in [0, 2^30]");
             if (!strcmp(key, "srpt_aging") && (value < 0 || value > ((int64_t)1 << 40)))
                 return ctx->fail(SPIC_E_ARG, "srpt_aging must be in [0, 2^40]");
-            if ((!strcmp(key, "fixed_geo") || !strcmp(key, "sort_ordered")) && (value < 0 || value > 1))
+            if ((!strcmp(key, "fixed_geo") || !strcmp(key, "sort_ordered") || !strcmp(key, "sort_rows")) &&
+                (value < 0 || value > 1))
                 return ctx->fail(SPIC_E_ARG, "%s must be 0 or 1", key);
             if (!strcmp(key, "bank_align") && (value < 0 || value > 2))
                 return ctx->fail(SPIC_E_ARG, "bank_align must be 0, 1 or 2");

@@ -289,6 +289,76 @@ k_sort_slots(int64_t n, const uint2 *__restrict__ keyrank, const uint32_t *__res
     }
 }
 
+// Full-row layout, per tile (one wave; lane = cell): R = n_t / C full rows;
+// cell c leaves h_c = max(0, R - n_c) holes in them and has
+// e_c = max(0, n_c - R) particles of rank >= R.  hx[key] = (exclusive
+// prefix of h, exclusive prefix of e) over the tile's cells, rh[t] = (R,
+// total holes).
+__global__ void __launch_bounds__(64)
+k_tile_rows(const uint32_t *__restrict__ offsets, TileGeom tg, uint2 *__restrict__ hx, uint2 *__restrict__ rh) {
+    const int t = blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint32_t C = (uint32_t)tg.cells, key0 = (uint32_t)t * C;
+    const uint32_t nt = offsets[key0 + C] - offsets[key0];
+    const uint32_t R = nt / C;
+    uint32_t h = 0, e = 0;
+    if ((uint32_t)lane < C) {
+        const uint32_t nc = offsets[key0 + lane + 1] - offsets[key0 + lane];
+        h = nc < R ? R - nc : 0u;
+        e = nc > R ? nc - R : 0u;
+    }
+    // inclusive wave scans
+    uint32_t H = h, E = e;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t hu = __shfl_up(H, d, 64), eu = __shfl_up(E, d, 64);
+        if (lane >= d) {
+            H += hu;
+            E += eu;
+        }
+    }
+    if ((uint32_t)lane < C) hx[key0 + lane] = make_uint2(H - h, E - e);
+    if (lane == 63) rh[t] = make_uint2(R, H);
+}
+
+// Full-row slot of every particle (see TileGeom::rows): rank r < R of cell c
+// at row r, column c; the j-th particle of rank >= R (cells in order) in the
+// j-th hole (columns in order, rows upward), past the holes in the last
+// partial row.
+__global__ void __launch_bounds__(256)
+k_sort_slots_rows(int64_t n, const uint2 *__restrict__ keyrank, const uint32_t *__restrict__ offsets,
+                  const uint2 *__restrict__ hx, const uint2 *__restrict__ rh, int cells,
+                  const uint32_t *__restrict__ own, uint32_t *__restrict__ srcidx) {
+    const uint32_t C = (uint32_t)cells;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const uint2 kr = keyrank[p];
+        const uint32_t t = kr.x / C, c = kr.x - t * C, key0 = t * C;
+        const uint32_t rank = (own && (kr.y & kImmigrant)) ? own[kr.x] + (kr.y & ~kImmigrant) : kr.y;
+        const uint32_t base = offsets[key0];
+        const uint2 RH = rh[t];
+        uint32_t d;
+        if (rank < RH.x) {
+            d = base + C * rank + c;
+        } else {
+            const uint32_t j = hx[kr.x].y + (rank - RH.x);
+            if (j < RH.y) {
+                // the column whose holes hold j: the last c2 with H(c2) <= j
+                uint32_t lo = 0, hi = C - 1;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi + 1) >> 1;
+                    if (hx[key0 + mid].x <= j) lo = mid;
+                    else hi = mid - 1;
+                }
+                const uint32_t n2 = offsets[key0 + lo + 1] - offsets[key0 + lo];
+                d = base + C * (n2 + (j - hx[key0 + lo].x)) + lo;
+            } else {
+                d = base + C * RH.x + (j - RH.y);
+            }
+        }
+        srcidx[d] = (uint32_t)p;
+    }
+}
+
 // Cell-major slot of every particle: all particles of a cell together, in
 // rank order.
 __global__ void __launch_bounds__(256)
@@ -418,7 +488,7 @@ __global__ void k_tile_offsets(const uint32_t *__restrict__ offsets, TileGeom tg
 
 // ------------------------------------------------------------------ host
 
-TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo, int layout, bool cellmajor) {
+TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo, int layout, bool cellmajor, bool rows) {
     TileGeom t;
     t.tx = tx; t.ty = ty; t.tz = tz;
     t.cells = tx * ty * tz;
@@ -445,7 +515,7 @@ TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo, in
     t.sz = lay.sz;
     t.rnp = lay.rnp;
     t.cellmajor = cellmajor ? 1 : 0;
-    t.pad = 0;
+    t.rows = (rows && !cellmajor) ? 1 : 0;
     return t;
 }
 
@@ -463,6 +533,8 @@ size_t sort_scratch_bytes(int64_t n, int dtype, bool with_id, const TileGeom &tg
     b += (size_t)(tg.ntiles + 1) * 4 * 2 + 512;   // maxc, tab_off
     b += ((size_t)n + tg.ntiles) * 16 + 256;      // rank tables (sum of max counts <= n)
     b += (size_t)((tg.ntiles + SCAN_CHUNK) / SCAN_CHUNK) * 4 + 256;  // partials of the tile scan
+    b += (size_t)nkeys * 8 + 256;                 // full rows: hole / excess prefixes per key
+    b += (size_t)(tg.ntiles + 1) * 8 + 256;       // full rows: rows and holes per tile
     b += 7 * ((size_t)n * sp + 256);       // particle copy
     if (with_id) b += (size_t)n * 8 + 256;
     return b;
@@ -492,6 +564,8 @@ static hipError_t sort_t(const spic_grid &g, const SpeciesWork &w, const TileGeo
     uint4 *tab = (uint4 *)carve(cur, ((size_t)n + tg.ntiles) * 16);
     const int tparts = (int)((tg.ntiles + SCAN_CHUNK) / SCAN_CHUNK);
     uint32_t *tpartial = (uint32_t *)carve(cur, (size_t)tparts * 4);
+    uint2 *hx = (uint2 *)carve(cur, (size_t)nkeys * 8);
+    uint2 *rh = (uint2 *)carve(cur, (size_t)(tg.ntiles + 1) * 8);
     PartPtrs<T> src, tmp;
     src.x = (T *)w.a[0]; src.y = (T *)w.a[1]; src.z = (T *)w.a[2];
     src.u = (T *)w.a[3]; src.v = (T *)w.a[4]; src.w = (T *)w.a[5]; src.q = (T *)w.a[6];
@@ -521,6 +595,10 @@ static hipError_t sort_t(const spic_grid &g, const SpeciesWork &w, const TileGeo
     if (tg.cellmajor) {
         hipLaunchKernelGGL(k_sort_slots_cm, dim3(gp > 0 ? gp : 1), dim3(256), 0, s, n, keyrank, offsets,
                            prev ? (const uint32_t *)own : nullptr, srcidx);
+    } else if (tg.rows) {
+        hipLaunchKernelGGL(k_tile_rows, dim3(tg.ntiles), dim3(64), 0, s, offsets, tg, hx, rh);
+        hipLaunchKernelGGL(k_sort_slots_rows, dim3(gp > 0 ? gp : 1), dim3(256), 0, s, n, keyrank, offsets, hx, rh,
+                           tg.cells, prev ? (const uint32_t *)own : nullptr, srcidx);
     } else {
         // rank tables: max count per tile, exclusive scan of the max counts, fill
         hipLaunchKernelGGL(k_tile_maxc, dim3(tg.ntiles), dim3(64), 0, s, offsets, tg, maxc);

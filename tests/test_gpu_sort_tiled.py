@@ -62,7 +62,43 @@ def _keys_np(g, st, tile):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sort_permutes_into_full_rows(spic, ctx, dtype):
+    """Full rows: a tile of n particles and C cells holds n // C full
+    rows in which slot (r, c) is a particle of cell c whenever cell c has
+    more than r particles (the others fill the remaining slots).  The
+    default for the lane-cell variants; set here for both precisions."""
+    ctx.set_option("sort_rows", 1)
+    h = W.harris_32x16x4()
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    g = h.grid
+    sps = [W.random_particles(g, 20011, 1.0, seed=5), W.make_species(h, W.SHEET_E)]
+    for sp in sps:
+        perm = np.random.default_rng(3).permutation(sp["x"].size)
+        sp = {k: v[perm] for k, v in sp.items()}
+        dev = spic.to_device(sp, tdt)
+        _say("case sort %s full rows, %d particles" % (dtype, sp["x"].size))
+        for rep in range(2):  # the second sort runs the ordered key pass and the tiled gather
+            spic.spic_sort(ctx, g, [dev])
+            torch.cuda.synchronize()
+            out = spic.to_host(dev)
+            a, b = P.by_id(out), P.by_id(spic.to_host(spic.to_device(sp, tdt)))
+            for k in a:
+                assert np.array_equal(a[k], b[k]), k
+            tile_id, local = _keys_np(g, out, (4, 4, 4))
+            assert np.all(np.diff(tile_id) >= 0), "tiles not contiguous"
+            for t in np.unique(tile_id)[:60]:
+                loc = local[tile_id == t]
+                counts = np.bincount(loc, minlength=64)
+                R = loc.size // 64
+                for r in range(R):
+                    row = loc[64 * r:64 * (r + 1)]
+                    home = counts > r
+                    assert np.array_equal(row[home], np.flatnonzero(home)), (t, r)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_sort_permutes_into_tile_rank_major_order(spic, ctx, dtype):
+    ctx.set_option("sort_rows", 0)
     h = W.harris_32x16x4()
     tdt = torch.float64 if dtype == "f64" else torch.float32
     sp = W.make_species(h, W.SHEET_E)
