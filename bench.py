@@ -157,8 +157,9 @@ def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: 
     n = h.n_total
     s_p = 4 if dtype_name == "f32" else 8
     per_launch_bytes = algorithmic_bytes(h.n_per_species, g.nodes, s_p, s_p)
-    # the dominant kernel's own launches: calls on steps without a sort launch
-    # only the moment zeroing (~6 us) and the fused kernel
+    # the fused pass's own launches: calls on steps without a sort launch only
+    # the moment zeroing (~6 us) and the fused kernel (or, split, the mover
+    # and deposit kernels)
     sort_step = np.array([sort_every > 0 and (warmup + k) % sort_every == 0 for k in range(steps)])
     fused_ms = launch_ms[~sort_step] if (~sort_step).any() else launch_ms
     avg_launch_s = float(fused_ms.mean()) / 1e3
@@ -180,7 +181,8 @@ def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: 
         "sort_ms_per_species": sort_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_fused_tiled (one launch per species)",
+                     "kernel": ("k_fused_tiled (mover) + k_deposit_tiled (lane-cell deposit), one pair per species"
+                                if launch.get("tile_variant") == 8 else "k_fused_tiled (one launch per species)"),
                      "bytes_per_launch": per_launch_bytes, "avg_launch_ms": avg_launch_s * 1e3,
                      "traffic_bytes_per_launch": traffic_bytes},
     }

@@ -170,12 +170,13 @@ int spic_version(void);
  *   grid_cap       cap on blocks of grid-stride kernels
  *   path           0 = tiled kernel for sorted species, 1 = unsorted path only
  *   tile_block     threads per block of the tiled kernel (64..512, x64; -1 =
- *                  by variant: 256 for variants 5 and 6, else 512)
+ *                  by variant: 256 for variants 5 to 9, else 512)
  *   tile_x/y/z     sort tile shape in cells (product <= 64)
  *   halo           cells of halo staged around a tile in LDS (0..8)
  *   lds_max        read only: LDS bytes a workgroup may use on the device
- *   tile_variant   tiled-kernel variant (0..6; see spic_tiled.hip; -1 = by
- *                  precision: 5 for FP32 particles with FP64 moments, else 0)
+ *   tile_variant   tiled-kernel variant (0..9; see spic_tiled.hip; -1 = by
+ *                  precision: 8 -- a mover launch, then a lane-cell deposit
+ *                  launch -- for FP32 particles with FP64 moments, else 0)
  *   fixed_geo      1 = kernels compiled for 4x4x4 tiles with halo 1 are used
  *                  when that tiling is in effect
  *   bank_align     1 = LDS region layout that keeps a particle's bank pair

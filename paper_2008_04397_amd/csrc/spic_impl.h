@@ -63,10 +63,11 @@ struct LaunchCfg {
 };
 
 // Tiled-kernel variant and workgroup size when the options leave them to
-// the library: FP32 particles with FP64 moments take the lane-cell register
-// deposit at 256 threads (measured fastest on the Harris boxes), every
-// other precision combination the LDS-atomic deposit at 512.
-inline int auto_variant(int dtype, int acc_dtype) { return (dtype == SPIC_F32 && acc_dtype == SPIC_F64) ? 5 : 0; }
+// the library: FP32 particles with FP64 moments take the split launch
+// (mover, then the lane-cell register deposit at 256 threads; measured
+// fastest on the Harris boxes), every other precision combination the
+// LDS-atomic deposit at 512.
+inline int auto_variant(int dtype, int acc_dtype) { return (dtype == SPIC_F32 && acc_dtype == SPIC_F64) ? 8 : 0; }
 inline int auto_tile_block(int variant) { return variant >= 5 ? 256 : 512; }
 inline LaunchCfg resolve_cfg(LaunchCfg c, int dtype, int acc_dtype) {
     if (c.variant < 0) c.variant = auto_variant(dtype, acc_dtype);

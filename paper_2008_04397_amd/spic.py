@@ -260,12 +260,13 @@ def spic_poll(ctx: Context, ticket: int) -> bool:
 def resolved_launch(ctx: Context, dtype: str, acc: str = "f64") -> Dict[str, int]:
     """The tiled-kernel launch settings the library uses for species of the
     given particle and moment precision ("f32"/"f64"): options left at -1
-    resolve as the library resolves them (variant 5 at 256 threads for FP32
-    particles with FP64 moments, otherwise variant 0 at 512; layout 1 for
-    FP32 particles, 0 for FP64, 2 for the two-phase variant)."""
+    resolve as the library resolves them (variant 8 -- mover, then the
+    lane-cell deposit at 256 threads -- for FP32 particles with FP64
+    moments, otherwise variant 0 at 512; layout 1 for FP32 particles, 0 for
+    FP64, 2 for the two-phase variant; full sort rows for variants 5-9)."""
     var = ctx.get_option("tile_variant")
     if var < 0:
-        var = 5 if (dtype == "f32" and acc == "f64") else 0
+        var = 8 if (dtype == "f32" and acc == "f64") else 0
     blk = ctx.get_option("tile_block")
     if blk < 0:
         blk = 256 if var >= 5 else 512
@@ -273,9 +274,10 @@ def resolved_launch(ctx: Context, dtype: str, acc: str = "f64") -> Dict[str, int
     if al < 0:
         al = 2 if var == 6 else (0 if (dtype == "f64" or var == 4) else 1)
     so = ctx.get_option("sort_ordered")
+    rows = ctx.get_option("sort_rows")
     halo = ctx.get_option("halo")
     return {"tile_variant": var, "tile_block": blk, "bank_align": al, "sort_ordered": 1 if so < 0 else so,
-            "halo": 1 if halo < 0 else halo}
+            "sort_rows": (1 if var >= 5 else 0) if rows < 0 else rows, "halo": 1 if halo < 0 else halo}
 
 
 # --------------------------------------------------------- tensor helpers
