@@ -177,8 +177,12 @@ int spic_version(void);
  *   tile_variant   tiled-kernel variant (0..9; see spic_tiled.hip; -1 = by
  *                  precision: 8 -- a mover launch, then a lane-cell deposit
  *                  launch -- for FP32 particles with FP64 moments, else 0)
- *   fixed_geo      1 = kernels compiled for 4x4x4 tiles with halo 1 are used
- *                  when that tiling is in effect
+ *   mover_halo     variant 8: cells of halo of the mover launch's field
+ *                  region (-1..8; -1 = the tile halo + 1; a region too large
+ *                  for the device's LDS falls back to the tile halo)
+ *   fixed_geo      1 = kernels compiled for 4x4x4 tiles with halo 1 (and
+ *                  the variant-8 mover's halo 2) are used when that tiling
+ *                  is in effect
  *   bank_align     1 = LDS region layout that keeps a particle's bank pair
  *                  when it drifts along the most-crossed axis (more LDS);
  *                  0 = the most compact conflict-free layout; 2 = dense,

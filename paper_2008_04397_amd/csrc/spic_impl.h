@@ -60,6 +60,8 @@ struct LaunchCfg {
     int tile_block = -1;    // tiled fused kernel (-1: by variant)
     int variant = -1;       // tiled kernel variant (see spic_tiled.hip; -1: by precision)
     int fixed_geo = 1;      // compile-time region geometry for the default tiling
+    int mover_halo = -1;    // split variant: halo of the mover's field region (-1: tile halo + 1)
+    size_t lds_max = 65536; // LDS bytes a workgroup may use on the device
 };
 
 // Tiled-kernel variant and workgroup size when the options leave them to
@@ -195,6 +197,9 @@ struct GeoFixed {
 using GeoDefault = GeoFixed<4, 4, 4, 1, 2, 0, 1>;
 // the same tiling with the dense layout
 using GeoDense = GeoFixed<4, 4, 4, 1, 2, 0, 1, 2>;
+// the mover launch of the split variant: two cells of halo (particles that
+// drifted since the last sort still gather from LDS)
+using GeoMover2 = GeoFixed<4, 4, 4, 2, 2, 0, 1>;
 
 // The tiled kernels address particle arrays with 32-bit byte offsets.
 inline bool tiled_fits(int64_t n, int dtype) {

@@ -201,6 +201,7 @@ static const char *const kOptionNames[] = {
     "max_groups",   // batch engine: cap on workgroups of the persistent launch (0 = occupancy)
     "tick_items",   // batch engine: (job, tile) items per tick, shortest runs first (0 = all runs)
     "srpt_aging",   // batch engine: credit, in M particle-steps per second waited, against starvation
+    "mover_halo",   // split tiled variant: halo of the mover's field region (-1: tile halo + 1)
 };
 
 int64_t spic_ctx_s::opt(const char *k, int64_t dflt) const {
@@ -215,6 +216,8 @@ LaunchCfg spic_ctx_s::launch_cfg() const {
     c.tile_block = (int)opt("tile_block", -1);
     c.variant = (int)opt("tile_variant", -1);
     c.fixed_geo = (int)opt("fixed_geo", 1);
+    c.mover_halo = (int)opt("mover_halo", -1);
+    c.lds_max = lds_max;
     return c;
 }
 
@@ -302,6 +305,8 @@ int spic_set_option(spic_ctx ctx, const char *key, int64_t value) {
                 return ctx->fail(SPIC_E_ARG, "bank_align must be 0, 1 or 2");
             if (!strcmp(key, "halo") && (value < 0 || value > 8))
                 return ctx->fail(SPIC_E_ARG, "halo must be in [0, 8]");
+            if (!strcmp(key, "mover_halo") && (value < -1 || value > 8))
+                return ctx->fail(SPIC_E_ARG, "mover_halo must be -1 or in [0, 8]");
             if (!strcmp(key, "lds_max")) return ctx->fail(SPIC_E_ARG, "lds_max is read only");
             ctx->options[key] = value;
             return SPIC_OK;

@@ -296,7 +296,9 @@ struct BalanceLds {
     int hole[64];   // lanes left empty, in lane order
 };
 
-template <typename TP, typename TA, class GEO>
+// TIGHT picks deposit_tight (corner loop rolled, few live registers) for the
+// deposit of the re-placed particles.
+template <typename TP, typename TA, class GEO, bool TIGHT = false>
 __device__ __forceinline__ void deposit_balanced(const GridT<TA> &ga, const TileGeom &tg, int ox, int oy, int oz,
                                                  TA *__restrict__ ml, TA *__restrict__ mom, int nn,
                                                  StagedParticle<TP> *__restrict__ stage, BalanceLds *__restrict__ bl,
@@ -331,8 +333,12 @@ __device__ __forceinline__ void deposit_balanced(const GridT<TA> &ga, const Tile
     wave_sync();
     if (!hole || h < __popcll(omask)) {
         const StagedParticle<TP> s = stage[lane];
-        deposit_one<TA, GEO>(ga, tg, ox, oy, oz, ml, mom, nn, (TA)s.x, (TA)s.y, (TA)s.z, (TA)s.q, (TA)s.u, (TA)s.v,
-                             (TA)s.w);
+        if constexpr (TIGHT)
+            deposit_tight<TA, GEO>(ga, tg, ox, oy, oz, ml, mom, nn, (TA)s.x, (TA)s.y, (TA)s.z, (TA)s.q, (TA)s.u,
+                                   (TA)s.v, (TA)s.w);
+        else
+            deposit_one<TA, GEO>(ga, tg, ox, oy, oz, ml, mom, nn, (TA)s.x, (TA)s.y, (TA)s.z, (TA)s.q, (TA)s.u,
+                                 (TA)s.v, (TA)s.w);
     }
     wave_sync();  // the stage is rewritten by the next call
 }
@@ -460,7 +466,9 @@ inline size_t stage_lds_bytes(int variant, int block, int dtype) {
     if (variant == 3) return (size_t)(block / 64) * (64 * rec + sizeof(BalanceLds));
     if (variant == 5 || variant == 7 || variant == 9)  // queue, reused as the balancing stage when flushed
         return (size_t)(block / 64) * (64 * rec + sizeof(BalanceLds));
-    if (variant == 6 || variant == 8) return (size_t)(block / 64) * 64 * 7 * (dtype == SPIC_F64 ? 8 : 4);
+    if (variant == 8)  // the deposit kernel: queue and balancing stage side by side
+        return (size_t)(block / 64) * (64 * 7 * (rec / 8) + 64 * rec + sizeof(BalanceLds));
+    if (variant == 6) return (size_t)(block / 64) * 64 * 7 * (dtype == SPIC_F64 ? 8 : 4);
     return 0;
 }
 
@@ -1216,7 +1224,7 @@ __device__ __forceinline__ void tile_body_pair(const TileJob<TP, TF, TA> &J, int
 
 // Deposit of a tile whose particles a mover-only launch has just moved
 // (variant 8, the second of its two kernels): the lane-cell register sums
-// and the compact queue of variant 5, with only the 80 sums and one
+// and the compact queue of variant 5 (deposited bank-balanced), with only the 80 sums and one
 // particle live; LDS holds the FP64 region moments (dense layout) and the
 // queues only (no fields), three workgroups of 256 per CU.
 template <typename TP, typename TF, typename TA, class GEO>
@@ -1236,7 +1244,15 @@ __device__ __forceinline__ void deposit_body(const TileJob<TP, TF, TA> &J, int t
     if (beg == end) return;
     const int RNP = tg.rnp;
     TA *ml = (TA *)smem;
-    TP *sq = (TP *)(smem + (((size_t)10 * RNP * sizeof(TA) + 15) & ~(size_t)15)) + (threadIdx.x >> 6) * (7 * 64);
+    // per-wave queue (7 arrays of 64: x y z u v w q) and, beside it, the
+    // balancing stage (so that the queue takes the overflow of a flush
+    // before the flush deposits)
+    unsigned char *mine = smem + (((size_t)10 * RNP * sizeof(TA) + 15) & ~(size_t)15) +
+                          (threadIdx.x >> 6) * (64 * 7 * sizeof(TP) + 64 * sizeof(StagedParticle<TP>) +
+                                                sizeof(BalanceLds));
+    TP *sq = (TP *)mine;
+    StagedParticle<TP> *lstage = (StagedParticle<TP> *)(mine + 64 * 7 * sizeof(TP));
+    BalanceLds *lbal = (BalanceLds *)(mine + 64 * 7 * sizeof(TP) + 64 * sizeof(StagedParticle<TP>));
     const int tzi = t % tg.ntz, tyi = (t / tg.ntz) % tg.nty, txi = t / (tg.ntz * tg.nty);
     int ox = (txi * tg.tx - tg.halo) % g.nx; ox += ox < 0 ? g.nx : 0;
     int oy = (tyi * tg.ty - tg.halo) % g.ny; oy += oy < 0 ? g.ny : 0;
@@ -1319,8 +1335,8 @@ __device__ __forceinline__ void deposit_body(const TileJob<TP, TF, TA> &J, int t
                 if (enq && pos >= 64)
 #pragma unroll
                     for (int a = 0; a < 7; ++a) sq[a * 64 + pos - 64] = rec[a];
-                deposit_tight<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, (TA)r[0], (TA)r[1], (TA)r[2], (TA)r[6],
-                                       (TA)r[3], (TA)r[4], (TA)r[5]);
+                deposit_balanced<TP, TA, GEO, true>(J.ga, tg, ox, oy, oz, ml, mom, nn, lstage, lbal, lane, true, r[0],
+                                                    r[1], r[2], r[3], r[4], r[5], r[6]);
                 sqn += cnt - 64;
             } else {
                 sqn += cnt;
@@ -1328,12 +1344,15 @@ __device__ __forceinline__ void deposit_body(const TileJob<TP, TF, TA> &J, int t
         }
     }
     wave_sync();
-    if (lane < sqn) {
-        TP r[7];
+    {
+        TP r[7] = {TP(0), TP(0), TP(0), TP(0), TP(0), TP(0), TP(0)};
+        if (lane < sqn)
 #pragma unroll
-        for (int a = 0; a < 7; ++a) r[a] = sq[a * 64 + lane];
-        deposit_tight<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, (TA)r[0], (TA)r[1], (TA)r[2], (TA)r[6], (TA)r[3],
-                               (TA)r[4], (TA)r[5]);
+            for (int a = 0; a < 7; ++a) r[a] = sq[a * 64 + lane];
+        wave_sync();
+        if (sqn > 0)
+            deposit_balanced<TP, TA, GEO, true>(J.ga, tg, ox, oy, oz, ml, mom, nn, lstage, lbal, lane, lane < sqn,
+                                                r[0], r[1], r[2], r[3], r[4], r[5], r[6]);
     }
     settle(sacc);
     if (lc >= 0) {
@@ -1449,11 +1468,38 @@ static void tiled_launch(const TileJob<TP, TF, TA> &job, int chunk, size_t lds, 
 template <typename TP, typename TF, typename TA, class GEO>
 static void split_launch(const TileJob<TP, TF, TA> &job, int chunk, const LaunchCfg &cfg, hipStream_t s) {
     const TileGeom &tg = job.tg;
-    const size_t fl = ((size_t)tg.rnp * sizeof(LdsFieldNode<TP>) + 15) & ~(size_t)15;
+    // the mover stages a wider field region than the deposit (fields are 6
+    // values a node against the deposit's 10 FP64 moments, and a particle
+    // that left the region gathers from global memory, three times)
     TileJob<TP, TF, TA> mv = job;
     mv.mom = nullptr;
-    allow_lds(k_fused_tiled<TP, TF, TA, 0, GEO>, fl);
-    hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, 0, GEO>), dim3(8 * chunk), dim3(512), fl, s, mv, chunk);
+    int mh = cfg.mover_halo >= 0 ? cfg.mover_halo : tg.halo + 1;
+    // the layout search is memoised per thread (one tiling per run, as a rule)
+    thread_local int key[5] = {-1, -1, -1, -1, -1};
+    thread_local RegionLayout ml{0, 0, 0, 0};
+    if (key[0] != tg.tx || key[1] != tg.ty || key[2] != tg.tz || key[3] != mh || key[4] != tg.slow * 9 + tg.mid * 3 + tg.fast) {
+        ml = region_layout(tg.tx, tg.ty, tg.tz, mh, tg.slow, tg.mid, tg.fast, 1);
+        key[0] = tg.tx; key[1] = tg.ty; key[2] = tg.tz; key[3] = mh; key[4] = tg.slow * 9 + tg.mid * 3 + tg.fast;
+    }
+    // a region that does not fit the device's LDS keeps the tile's halo
+    if ((size_t)ml.rnp * sizeof(LdsFieldNode<TP>) > cfg.lds_max) mh = tg.halo;
+    if (mh != tg.halo) {
+        mv.tg.halo = mh;
+        mv.tg.rx = tg.tx + 2 * mh + 1; mv.tg.ry = tg.ty + 2 * mh + 1; mv.tg.rz = tg.tz + 2 * mh + 1;
+        mv.tg.sx = ml.sx; mv.tg.sy = ml.sy; mv.tg.sz = ml.sz; mv.tg.rnp = ml.rnp;
+    }
+    const size_t fl = ((size_t)mv.tg.rnp * sizeof(LdsFieldNode<TP>) + 15) & ~(size_t)15;
+    if (mh == tg.halo) {
+        allow_lds(k_fused_tiled<TP, TF, TA, 0, GEO>, fl);
+        hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, 0, GEO>), dim3(8 * chunk), dim3(512), fl, s, mv, chunk);
+    } else if (cfg.fixed_geo && geo_is<GeoMover2>(mv.tg)) {
+        allow_lds(k_fused_tiled<TP, TF, TA, 0, GeoMover2>, fl);
+        hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, 0, GeoMover2>), dim3(8 * chunk), dim3(512), fl, s, mv, chunk);
+    } else {
+        allow_lds(k_fused_tiled<TP, TF, TA, 0, GeoRuntime>, fl);
+        hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, 0, GeoRuntime>), dim3(8 * chunk), dim3(512), fl, s, mv,
+                           chunk);
+    }
     if (!job.mom) return;
     // the deposit kernel's region uses the dense layout (smallest LDS: three
     // workgroups per CU)
@@ -1461,7 +1507,7 @@ static void split_launch(const TileJob<TP, TF, TA> &job, int chunk, const Launch
     const RegionLayout lay = region_layout(tg.tx, tg.ty, tg.tz, tg.halo, tg.slow, tg.mid, tg.fast, 2);
     dj.tg.sx = lay.sx; dj.tg.sy = lay.sy; dj.tg.sz = lay.sz; dj.tg.rnp = lay.rnp;
     const size_t dl = (((size_t)10 * lay.rnp * sizeof(TA) + 15) & ~(size_t)15) +
-                      (size_t)(cfg.tile_block / 64) * 64 * 7 * sizeof(TP);
+                      stage_lds_bytes(8, cfg.tile_block, sizeof(TP) == 8 ? SPIC_F64 : SPIC_F32);
     if (cfg.fixed_geo && geo_is<GeoDense>(dj.tg)) {
         allow_lds(k_deposit_tiled<TP, TF, TA, GeoDense>, dl);
         hipLaunchKernelGGL((k_deposit_tiled<TP, TF, TA, GeoDense>), dim3(8 * chunk), dim3(cfg.tile_block), dl, s, dj,

@@ -114,6 +114,11 @@ def test_options(hctx):
         hctx.set_option("block", 100)
     with pytest.raises(spic.SpicError):
         hctx.set_option("no_such_knob", 1)
+    hctx.set_option("mover_halo", 2)
+    assert hctx.get_option("mover_halo") == 2
+    for bad in (-2, 9):
+        with pytest.raises(spic.SpicError):
+            hctx.set_option("mover_halo", bad)
 
 
 def test_python_binding_refuses_to_run_without_the_library(monkeypatch, tmp_path):

@@ -238,6 +238,29 @@ def test_tile_shapes_and_halo_overflow_match_oracle(spic, ctx, tile, halo, varia
         P.assert_moments(ms[s], oms[s], P.MOM64)
 
 
+@pytest.mark.parametrize("tile,halo,mover_halo", [((4, 4, 4), 1, 0), ((4, 4, 4), 1, 1), ((4, 4, 4), 1, 2),
+                                                    ((4, 4, 4), 1, 3), ((4, 4, 4), 0, -1), ((2, 4, 8), 1, -1),
+                                                    ((3, 3, 3), 2, 4)])
+def test_split_variant_mover_halo(spic, ctx, tile, halo, mover_halo):
+    """The split variant's mover stages its own field region (by default one
+    cell of halo more than the deposit's); fast particles leave both."""
+    h = W.harris_32x16x4()
+    f = W.make_fields(h)
+    g = h.grid
+    sps = [W.random_particles(g, 20011, 2.0, seed=11), W.make_species(h, W.SHEET_E)]
+    qoms = [-64.0, -64.0]
+    ctx.set_option("tile_x", tile[0]); ctx.set_option("tile_y", tile[1]); ctx.set_option("tile_z", tile[2])
+    ctx.set_option("halo", halo)
+    ctx.set_option("mover_halo", mover_halo)
+    ctx.set_option("tile_variant", 8)
+    _say("case split mover halo: tiles %s halo %d mover_halo %d" % (tile, halo, mover_halo))
+    st, ms = _gpu_steps(spic, ctx, h, f, sps, qoms, 3, sort_every=2)
+    ora, oms = _oracle_steps(h, f, sps, qoms, 3)
+    for s in range(2):
+        P.assert_state(st[s], ora[s], g, P.POS64, P.VEL64)
+        P.assert_moments(ms[s], oms[s], P.MOM64)
+
+
 @pytest.mark.parametrize("variant", [0, 4, 5, 6, 8, 9])
 @pytest.mark.parametrize("cells", [(5, 3, 2), (2, 2, 2), (9, 7, 5)])
 def test_tiny_and_odd_grids(spic, ctx, cells, variant):
