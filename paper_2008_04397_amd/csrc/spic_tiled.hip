@@ -1222,6 +1222,13 @@ __device__ __forceinline__ void tile_body_pair(const TileJob<TP, TF, TA> &J, int
     }
 }
 
+// Particles in flight per thread of the deposit kernel (at least 2: a
+// slot is refilled after its particle is deposited), and its register
+// budget in waves per SIMD.
+constexpr int kDepositPrefetch = 2;
+constexpr int kDepositWaves = 3;
+static_assert(kDepositPrefetch >= 2, "the deposit loop refills a slot after depositing it");
+
 // Deposit of a tile whose particles a mover-only launch has just moved
 // (variant 8, the second of its two kernels): the lane-cell register sums
 // and the compact queue of variant 5 (deposited bank-balanced), with only the 80 sums and one
@@ -1271,23 +1278,18 @@ __device__ __forceinline__ void deposit_body(const TileJob<TP, TF, TA> &J, int t
     const uint32_t stride = blockDim.x;
     constexpr uint32_t ES = sizeof(TP);
     uint32_t ii = beg + threadIdx.x;
-    TP nrec[7] = {TP(0), TP(0), TP(0), TP(0), TP(0), TP(0), TP(0)};
-    if (ii < end) {
-        const uint32_t o = ii * ES;
-        nrec[0] = ld32(p.x, o); nrec[1] = ld32(p.y, o); nrec[2] = ld32(p.z, o);
-        nrec[3] = ld32(p.u, o); nrec[4] = ld32(p.v, o); nrec[5] = ld32(p.w, o); nrec[6] = ld32(p.q, o);
-    }
-    for (uint32_t i0 = beg + (threadIdx.x & ~63u); i0 < end; i0 += stride, ii += stride) {
-        const bool valid = ii < end;
-        TP rec[7];
-#pragma unroll
-        for (int a = 0; a < 7; ++a) rec[a] = nrec[a];
-        const uint32_t inext = ii + stride;
-        if (inext < end) {  // the next particle loads while this one deposits
-            const uint32_t o = inext * ES;
-            nrec[0] = ld32(p.x, o); nrec[1] = ld32(p.y, o); nrec[2] = ld32(p.z, o);
-            nrec[3] = ld32(p.u, o); nrec[4] = ld32(p.v, o); nrec[5] = ld32(p.w, o); nrec[6] = ld32(p.q, o);
-        }
+    // the next PF particles of this thread load while one deposits
+    constexpr int PF = kDepositPrefetch;
+    // unconditional loads (past the range: the tile's last particle, read
+    // and ignored), so a slot is refilled in place with no merge of old and
+    // new values that would make the compiler copy it and wait for it
+    auto load = [&](TP (&dst)[7], uint32_t i) __attribute__((always_inline)) {
+        const uint32_t o = min(i, end - 1) * ES;
+        dst[0] = ld32(p.x, o); dst[1] = ld32(p.y, o); dst[2] = ld32(p.z, o);
+        dst[3] = ld32(p.u, o); dst[4] = ld32(p.v, o); dst[5] = ld32(p.w, o); dst[6] = ld32(p.q, o);
+    };
+    // one particle: its lane-cell sums or the queue
+    auto process = [&](const TP (&rec)[7], bool valid) __attribute__((always_inline)) {
         bool enq = false;
         if (valid) {
             // the cell from the particle-precision position, the in-cell
@@ -1342,6 +1344,20 @@ __device__ __forceinline__ void deposit_body(const TileJob<TP, TF, TA> &J, int t
                 sqn += cnt;
             }
         }
+    };
+    // PF particles of this thread are in flight: the loop is unrolled by PF
+    // and each slot is deposited from and then refilled in place, so that
+    // no register copy of a slot whose load is in flight (which would wait
+    // for every load) is needed; a load has PF - 1 particles' time to land
+    TP ring[PF][7];
+#pragma unroll
+    for (int k = 0; k < PF; ++k) load(ring[k], ii + k * stride);
+    for (uint32_t i0 = beg + (threadIdx.x & ~63u); i0 < end; i0 += PF * stride, ii += PF * stride) {
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            process(ring[k], ii + k * stride < end);
+            load(ring[k], ii + (k + PF) * stride);
+        }
     }
     wave_sync();
     {
@@ -1375,7 +1391,7 @@ __device__ __forceinline__ void deposit_body(const TileJob<TP, TF, TA> &J, int t
 }
 
 template <typename TP, typename TF, typename TA, class GEO>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(kDepositWaves)))
 k_deposit_tiled(TileJob<TP, TF, TA> J, int chunk) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int b = blockIdx.x;
