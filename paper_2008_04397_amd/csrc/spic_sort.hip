@@ -444,6 +444,67 @@ __device__ __forceinline__ void gather_tile_array(const V *__restrict__ sa, V *_
     __syncthreads();
 }
 
+// Pipelined re-sort gather of one tile whose new and old ranges hold at
+// most kPipeU * blockDim slots: the source indices are loaded once; while
+// array a is scattered from the stage, array a + 1's old range is already
+// loading into registers; particles that came from another tile are moved
+// in one last pass over all seven arrays (their loads in flight together).
+constexpr int kPipeU = 20;
+
+template <typename T>
+__device__ __forceinline__ void gather_tile_piped(const T *const (&sa)[7], T *const (&da)[7], T *stage, uint32_t ob,
+                                                  uint32_t span, uint32_t nb, uint32_t ne, int64_t n,
+                                                  const uint32_t *__restrict__ srcidx) {
+    constexpr int U = kPipeU;
+    const uint32_t B = blockDim.x;
+    uint32_t p[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t d = nb + threadIdx.x + u * B;
+        p[u] = d < ne ? srcidx[d] : 0u;
+    }
+    T nv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t j = threadIdx.x + u * B;
+        if (j < span) nv[u] = sa[0][ob + j];
+    }
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t j = threadIdx.x + u * B;
+            if (j < span) stage[j] = nv[u];
+        }
+        __syncthreads();
+        if (a + 1 < 7)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t j = threadIdx.x + u * B;
+                if (j < span) nv[u] = sa[a + 1][ob + j];
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t d = nb + threadIdx.x + u * B;
+            const uint32_t r = p[u] - ob;  // wraps past span when p < ob
+            if (d < ne && r < span) da[a][d] = stage[r];
+        }
+        __syncthreads();  // the stage is rewritten by the next array
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t d = nb + threadIdx.x + u * B;
+        const uint32_t r = p[u] - ob;
+        if (d < ne && r >= span && p[u] < (uint64_t)n) {
+            T v[7];
+#pragma unroll
+            for (int a = 0; a < 7; ++a) v[a] = sa[a][p[u]];
+#pragma unroll
+            for (int a = 0; a < 7; ++a) da[a][d] = v[a];
+        }
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_sort_gather_tiled(PartPtrs<T> src, PartPtrs<T> dst, int64_t n, const uint32_t *__restrict__ srcidx,
@@ -460,10 +521,15 @@ k_sort_gather_tiled(PartPtrs<T> src, PartPtrs<T> dst, int64_t n, const uint32_t 
     const uint32_t capT = kGatherLdsBytes / sizeof(T), cap8 = kGatherLdsBytes / 8;
     const uint32_t oc = span < capT ? span : capT;
     T *st = (T *)lds;
-    const T *sa[7] = {src.x, src.y, src.z, src.u, src.v, src.w, src.q};
-    T *da[7] = {dst.x, dst.y, dst.z, dst.u, dst.v, dst.w, dst.q};
+    const T *const sa[7] = {src.x, src.y, src.z, src.u, src.v, src.w, src.q};
+    T *const da[7] = {dst.x, dst.y, dst.z, dst.u, dst.v, dst.w, dst.q};
+    const uint32_t piped = (uint32_t)kPipeU * blockDim.x;
+    if (ne - nb <= piped && span <= piped && span <= capT) {
+        gather_tile_piped<T>(sa, da, st, ob, span, nb, ne, n, srcidx);
+    } else {
 #pragma unroll
-    for (int a = 0; a < 7; ++a) gather_tile_array<T, T>(sa[a], da[a], st, ob, oc, nb, ne, n, srcidx);
+        for (int a = 0; a < 7; ++a) gather_tile_array<T, T>(sa[a], da[a], st, ob, oc, nb, ne, n, srcidx);
+    }
     if (src.id)
         gather_tile_array<T, int64_t>(src.id, dst.id, (int64_t *)lds, ob, span < cap8 ? span : cap8, nb, ne, n,
                                       srcidx);
