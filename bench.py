@@ -84,6 +84,18 @@ def algorithmic_bytes(n_particles: int, nodes: int, s_p: int, s_f: int) -> float
     return n_particles * 13 * s_p + 6 * nodes * s_f + 10 * nodes * 8
 
 
+# library options given on the command line (--option KEY=VALUE), applied to
+# every context the bench creates
+EXTRA_OPTS = {}
+
+
+def _new_ctx(spic, *a):
+    ctx = spic.Context(*a)
+    for k, v in EXTRA_OPTS.items():
+        ctx.set_option(k, v)
+    return ctx
+
+
 def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: int, tune: bool = True,
             variant: int = -1):
     import torch
@@ -91,7 +103,7 @@ def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: 
 
     dt = torch.float32 if dtype_name == "f32" else torch.float64
     g = h.grid
-    ctx = spic.Context(0)
+    ctx = _new_ctx(spic, 0)
     if path:
         ctx.set_option("path", path)
     log("[bench] generating %s inputs (%d particles)" % (dtype_name, h.n_total))
@@ -216,7 +228,7 @@ def cpu_baseline(h, target_s: float = 12.0):
 
 def _engine_ctx(budget=0, tuned_key=None, variant=-1):
     from paper_2008_04397_amd import autotune, spic
-    ctx = spic.Context(0, budget)
+    ctx = _new_ctx(spic, 0, budget)
     cfg = autotune.load(tuned_key) if tuned_key else None
     if cfg:
         autotune.apply(ctx, cfg)
@@ -274,7 +286,7 @@ def bench_streamed(args):
     # 16 GiB, or a quarter of the particle bytes when that is smaller, so the
     # run never fits and every step streams every batch over the link
     budget = min(16 * (1 << 30), n_all * 28 // 4)
-    ctx = spic.Context(0, budget)
+    ctx = _new_ctx(spic, 0, budget)
     ctx.set_option("batch_particles", 1 << 26)
     f = W.fields_tensors(h, dtype=torch.float32)
     species, total = [], 0
@@ -332,7 +344,7 @@ def bench_cadence(args):
     for cad in ("once", 1, 4, 10):
         species = [spic.to_device(W.make_species(h, s, dtype=np.float32, with_id=False), torch.float32)
                    for s in range(4)]
-        ctx = spic.Context(0)
+        ctx = _new_ctx(spic, 0)
         if cad == "once":
             spic.spic_sort(ctx, g, species, stream=stream)
         se = 0 if cad == "once" else cad
@@ -404,11 +416,16 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="(default) use the library defaults")
     ap.add_argument("--variant", type=int, default=-1, help="tiled kernel variant (-1: the library default for the precision)")
     ap.add_argument("--path", type=int, default=0)
+    ap.add_argument("--option", action="append", default=[], metavar="KEY=VALUE",
+                    help="set a library option on every context (repeatable), e.g. mover_cache=0")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a plain 1 GiB device-to-device copy (reference for HBM counters)")
     args = ap.parse_args()
+    for kv in args.option:
+        k, v = kv.split("=", 1)
+        EXTRA_OPTS[k] = int(v)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the particle decomposition across GPUs is described, not built).", file=sys.stderr)

@@ -177,6 +177,9 @@ int spic_version(void);
  *   tile_variant   tiled-kernel variant (0..9; see spic_tiled.hip; -1 = by
  *                  precision: 8 -- a mover launch, then a lane-cell deposit
  *                  launch -- for FP32 particles with FP64 moments, else 0)
+ *   mover_cache    variant 8: 1 = the mover launch keeps the 48 field
+ *                  values of a thread's last cell in registers (default), 0 =
+ *                  every gather reads LDS
  *   mover_halo     variant 8: cells of halo of the mover launch's field
  *                  region (-1..8; -1 = the tile halo + 1; a region too large
  *                  for the device's LDS falls back to the tile halo)

@@ -61,6 +61,7 @@ struct LaunchCfg {
     int variant = -1;       // tiled kernel variant (see spic_tiled.hip; -1: by precision)
     int fixed_geo = 1;      // compile-time region geometry for the default tiling
     int mover_halo = -1;    // split variant: halo of the mover's field region (-1: tile halo + 1)
+    int mover_cache = 1;    // split variant: the mover keeps the last cell's field corners in registers
     size_t lds_max = 65536; // LDS bytes a workgroup may use on the device
 };
 

@@ -202,6 +202,7 @@ static const char *const kOptionNames[] = {
     "tick_items",   // batch engine: (job, tile) items per tick, shortest runs first (0 = all runs)
     "srpt_aging",   // batch engine: credit, in M particle-steps per second waited, against starvation
     "mover_halo",   // split tiled variant: halo of the mover's field region (-1: tile halo + 1)
+    "mover_cache",  // split tiled variant: 1 = the mover keeps the last cell's field corners in registers
 };
 
 int64_t spic_ctx_s::opt(const char *k, int64_t dflt) const {
@@ -217,6 +218,7 @@ LaunchCfg spic_ctx_s::launch_cfg() const {
     c.variant = (int)opt("tile_variant", -1);
     c.fixed_geo = (int)opt("fixed_geo", 1);
     c.mover_halo = (int)opt("mover_halo", -1);
+    c.mover_cache = (int)opt("mover_cache", 1);
     c.lds_max = lds_max;
     return c;
 }
@@ -298,7 +300,8 @@ int spic_set_option(spic_ctx ctx, const char *key, int64_t value) {
                 return ctx->fail(SPIC_E_ARG, "tick_items must be in [0, 2^30]");
             if (!strcmp(key, "srpt_aging") && (value < 0 || value > ((int64_t)1 << 40)))
                 return ctx->fail(SPIC_E_ARG, "srpt_aging must be in [0, 2^40]");
-            if ((!strcmp(key, "fixed_geo") || !strcmp(key, "sort_ordered") || !strcmp(key, "sort_rows")) &&
+            if ((!strcmp(key, "fixed_geo") || !strcmp(key, "sort_ordered") || !strcmp(key, "sort_rows") ||
+                 !strcmp(key, "mover_cache")) &&
                 (value < 0 || value > 1))
                 return ctx->fail(SPIC_E_ARG, "%s must be 0 or 1", key);
             if (!strcmp(key, "bank_align") && (value < 0 || value > 2))

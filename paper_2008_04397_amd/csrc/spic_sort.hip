@@ -450,6 +450,9 @@ __device__ __forceinline__ void gather_tile_array(const V *__restrict__ sa, V *_
 // loading into registers; particles that came from another tile are moved
 // in one last pass over all seven arrays (their loads in flight together).
 constexpr int kPipeU = 20;
+// FP64 particles take the per-array form (the pipelined one needs 147
+// VGPRs for them: 3 waves per SIMD)
+constexpr bool kPipeFP64 = false;
 
 template <typename T>
 __device__ __forceinline__ void gather_tile_piped(const T *const (&sa)[7], T *const (&da)[7], T *stage, uint32_t ob,
@@ -524,7 +527,7 @@ k_sort_gather_tiled(PartPtrs<T> src, PartPtrs<T> dst, int64_t n, const uint32_t 
     const T *const sa[7] = {src.x, src.y, src.z, src.u, src.v, src.w, src.q};
     T *const da[7] = {dst.x, dst.y, dst.z, dst.u, dst.v, dst.w, dst.q};
     const uint32_t piped = (uint32_t)kPipeU * blockDim.x;
-    if (ne - nb <= piped && span <= piped && span <= capT) {
+    if ((kPipeFP64 || sizeof(T) == 4) && ne - nb <= piped && span <= piped && span <= capT) {
         gather_tile_piped<T>(sa, da, st, ob, span, nb, ne, n, srcidx);
     } else {
 #pragma unroll

@@ -1413,8 +1413,8 @@ k_deposit_tiled(TileJob<TP, TF, TA> J, int chunk) {
 //      keeps it at 2 waves/SIMD at 256 threads anyway)
 //   6  two-phase mover / deposit pass; <= 168 VGPRs (FP32), 3 waves/SIMD
 //   7  as 5 with a second register set for one drift cell; <= 256 VGPRs
-//   8  two launches: mover only (variant 0 without moments), then the
-//      lane-cell deposit kernel over the moved particles
+//   8  two launches: mover only (variant 1, or 0, without moments), then
+//      the lane-cell deposit kernel over the moved particles
 //   9  as 5 with two particles per thread in flight; <= 256 VGPRs
 template <int VAR, typename TP>
 struct VariantWaves {
@@ -1478,9 +1478,15 @@ static void tiled_launch(const TileJob<TP, TF, TA> &job, int chunk, size_t lds, 
     hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, VAR, GEO>), dim3(8 * chunk), dim3(block), lds, s, job, chunk);
 }
 
-// Variant 8: a mover-only launch (variant 0's tile body without moments,
-// LDS for the fields only) and then the deposit kernel over the moved
-// particles (LDS for the moments and queues only).
+template <int MV, typename TP, typename TF, typename TA, class G>
+static void mover_launch(const TileJob<TP, TF, TA> &mv, int chunk, size_t fl, hipStream_t s) {
+    allow_lds(k_fused_tiled<TP, TF, TA, MV, G>, fl);
+    hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, MV, G>), dim3(8 * chunk), dim3(512), fl, s, mv, chunk);
+}
+
+// Variant 8: a mover-only launch (variant 1's or 0's tile body without
+// moments, LDS for the fields only) and then the deposit kernel over the
+// moved particles (LDS for the moments and queues only).
 template <typename TP, typename TF, typename TA, class GEO>
 static void split_launch(const TileJob<TP, TF, TA> &job, int chunk, const LaunchCfg &cfg, hipStream_t s) {
     const TileGeom &tg = job.tg;
@@ -1505,16 +1511,17 @@ static void split_launch(const TileJob<TP, TF, TA> &job, int chunk, const Launch
         mv.tg.sx = ml.sx; mv.tg.sy = ml.sy; mv.tg.sz = ml.sz; mv.tg.rnp = ml.rnp;
     }
     const size_t fl = ((size_t)mv.tg.rnp * sizeof(LdsFieldNode<TP>) + 15) & ~(size_t)15;
-    if (mh == tg.halo) {
-        allow_lds(k_fused_tiled<TP, TF, TA, 0, GEO>, fl);
-        hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, 0, GEO>), dim3(8 * chunk), dim3(512), fl, s, mv, chunk);
-    } else if (cfg.fixed_geo && geo_is<GeoMover2>(mv.tg)) {
-        allow_lds(k_fused_tiled<TP, TF, TA, 0, GeoMover2>, fl);
-        hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, 0, GeoMover2>), dim3(8 * chunk), dim3(512), fl, s, mv, chunk);
+    // the mover body: variant 1's (the last cell's 48 field values in
+    // registers; in full rows a thread's particles share their sort cell, so
+    // most gathers skip LDS) or variant 0's
+    if (cfg.mover_cache) {
+        if (mh == tg.halo) mover_launch<1, TP, TF, TA, GEO>(mv, chunk, fl, s);
+        else if (cfg.fixed_geo && geo_is<GeoMover2>(mv.tg)) mover_launch<1, TP, TF, TA, GeoMover2>(mv, chunk, fl, s);
+        else mover_launch<1, TP, TF, TA, GeoRuntime>(mv, chunk, fl, s);
     } else {
-        allow_lds(k_fused_tiled<TP, TF, TA, 0, GeoRuntime>, fl);
-        hipLaunchKernelGGL((k_fused_tiled<TP, TF, TA, 0, GeoRuntime>), dim3(8 * chunk), dim3(512), fl, s, mv,
-                           chunk);
+        if (mh == tg.halo) mover_launch<0, TP, TF, TA, GEO>(mv, chunk, fl, s);
+        else if (cfg.fixed_geo && geo_is<GeoMover2>(mv.tg)) mover_launch<0, TP, TF, TA, GeoMover2>(mv, chunk, fl, s);
+        else mover_launch<0, TP, TF, TA, GeoRuntime>(mv, chunk, fl, s);
     }
     if (!job.mom) return;
     // the deposit kernel's region uses the dense layout (smallest LDS: three

@@ -119,6 +119,9 @@ def test_options(hctx):
     for bad in (-2, 9):
         with pytest.raises(spic.SpicError):
             hctx.set_option("mover_halo", bad)
+    hctx.set_option("mover_cache", 0)
+    with pytest.raises(spic.SpicError):
+        hctx.set_option("mover_cache", 2)
 
 
 def test_python_binding_refuses_to_run_without_the_library(monkeypatch, tmp_path):

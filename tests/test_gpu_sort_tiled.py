@@ -238,12 +238,15 @@ def test_tile_shapes_and_halo_overflow_match_oracle(spic, ctx, tile, halo, varia
         P.assert_moments(ms[s], oms[s], P.MOM64)
 
 
+@pytest.mark.parametrize("cache", [1, 0])
 @pytest.mark.parametrize("tile,halo,mover_halo", [((4, 4, 4), 1, 0), ((4, 4, 4), 1, 1), ((4, 4, 4), 1, 2),
                                                     ((4, 4, 4), 1, 3), ((4, 4, 4), 0, -1), ((2, 4, 8), 1, -1),
                                                     ((3, 3, 3), 2, 4)])
-def test_split_variant_mover_halo(spic, ctx, tile, halo, mover_halo):
+def test_split_variant_mover_halo(spic, ctx, tile, halo, mover_halo, cache):
     """The split variant's mover stages its own field region (by default one
-    cell of halo more than the deposit's); fast particles leave both."""
+    cell of halo more than the deposit's), with or without the last cell's
+    field corners in registers; fast particles leave both regions."""
+    ctx.set_option("mover_cache", cache)
     h = W.harris_32x16x4()
     f = W.make_fields(h)
     g = h.grid
@@ -253,7 +256,7 @@ def test_split_variant_mover_halo(spic, ctx, tile, halo, mover_halo):
     ctx.set_option("halo", halo)
     ctx.set_option("mover_halo", mover_halo)
     ctx.set_option("tile_variant", 8)
-    _say("case split mover halo: tiles %s halo %d mover_halo %d" % (tile, halo, mover_halo))
+    _say("case split mover halo: tiles %s halo %d mover_halo %d cache %d" % (tile, halo, mover_halo, cache))
     st, ms = _gpu_steps(spic, ctx, h, f, sps, qoms, 3, sort_every=2)
     ora, oms = _oracle_steps(h, f, sps, qoms, 3)
     for s in range(2):
