@@ -1499,9 +1499,10 @@ static void split_launch(const TileJob<TP, TF, TA> &job, int chunk, const Launch
     // the layout search is memoised per thread (one tiling per run, as a rule)
     thread_local int key[5] = {-1, -1, -1, -1, -1};
     thread_local RegionLayout ml{0, 0, 0, 0};
-    if (key[0] != tg.tx || key[1] != tg.ty || key[2] != tg.tz || key[3] != mh || key[4] != tg.slow * 9 + tg.mid * 3 + tg.fast) {
+    const int axes = tg.slow * 9 + tg.mid * 3 + tg.fast;
+    if (key[0] != tg.tx || key[1] != tg.ty || key[2] != tg.tz || key[3] != mh || key[4] != axes) {
         ml = region_layout(tg.tx, tg.ty, tg.tz, mh, tg.slow, tg.mid, tg.fast, 1);
-        key[0] = tg.tx; key[1] = tg.ty; key[2] = tg.tz; key[3] = mh; key[4] = tg.slow * 9 + tg.mid * 3 + tg.fast;
+        key[0] = tg.tx; key[1] = tg.ty; key[2] = tg.tz; key[3] = mh; key[4] = axes;
     }
     // a region that does not fit the device's LDS keeps the tile's halo
     if ((size_t)ml.rnp * sizeof(LdsFieldNode<TP>) > cfg.lds_max) mh = tg.halo;
