@@ -38,10 +38,8 @@ def lib():
         L.oracle_gather.argtypes = [gp] + [dp] * 6 + [dp] * 3 + [C.c_int64, dp]
         L.oracle_mover.argtypes = [gp, C.c_double, C.c_double, C.c_int, C.c_double] + [dp] * 6 + [dp] * 6 + [C.c_int64]
         L.oracle_deposit.argtypes = [gp] + [dp] * 7 + [C.c_int64, dp, C.c_int]
-        L.oracle_step.argtypes = ([gp, C.c_double, C.c_double, C.c_int, C.c_double] + [dp] * 6 + [dp] * 6
-                                  + [dp, C.c_int64, dp, C.c_int])
         L.oracle_max_threads.argtypes = []
-        for f in ("oracle_weights", "oracle_gather", "oracle_mover", "oracle_deposit", "oracle_step",
+        for f in ("oracle_weights", "oracle_gather", "oracle_mover", "oracle_deposit",
                   "oracle_max_threads"):
             getattr(L, f).restype = C.c_int
         _lib = L

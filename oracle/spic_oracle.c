@@ -245,19 +245,6 @@ int oracle_deposit(const og_grid *g, const double *x, const double *y, const dou
     return 0;
 }
 
-/* One fused step of one species: move every particle, then deposit the
- * new state (mom may be NULL for a mover-only step). */
-int oracle_step(const og_grid *g, double dt, double c, int niter, double qom,
-                const double *ex, const double *ey, const double *ez,
-                const double *bx, const double *by, const double *bz,
-                double *x, double *y, double *z, double *u, double *v, double *w,
-                const double *q, int64_t n, double *mom, int accumulate)
-{
-    int rc = oracle_mover(g, dt, c, niter, qom, ex, ey, ez, bx, by, bz, x, y, z, u, v, w, n);
-    if (rc || !mom) return rc;
-    return oracle_deposit(g, x, y, z, u, v, w, q, n, mom, accumulate);
-}
-
 int oracle_max_threads(void)
 {
 #ifdef _OPENMP

@@ -334,3 +334,69 @@ def test_paper_workload_particle_count():
     assert abs(h.n_total - gold["particles_approx"]) / gold["particles_approx"] < 0.01
     assert abs(h.qom_e / h.qom_i) == gold["charge_to_mass_ratio"]
     assert h.niter == gold["mover_iterations"]
+
+
+# --------------------------------------------------------------------- P16
+
+def _gyrating(g):
+    """One particle per species-like case in uniform B along z, placed a
+    fifth of a cell below a node plane along x and moving towards it fast
+    enough to cross it within one step: its deposit before and after the
+    move land on different nodes."""
+    dx = g.d[0]
+    f = W.uniform_fields(g, E=(0.0, 0.0, 0.0), B=(0.0, 0.0, 0.02))
+    x0 = 3 * dx - 0.2 * dx
+    sp = _one(x0, 0.55 * g.Ly, 0.4 * g.Lz, 0.9 * dx / 0.25, 0.3, -0.2, q=0.7)
+    return f, sp
+
+
+def test_p16_step_deposits_the_moved_state():
+    """The fused step (Sec. II moment sum; Sec. III-B: mover and gathering in
+    one pass, with the new position used for the gathering) deposits
+    x^{n+1}, v^{n+1}: its moments equal the brute-force deposit of the
+    brute-force move, and differ from the deposit of the state before the
+    move, and from deposits that mix the old and new position or velocity."""
+    g = W.Grid(8, 6, 5)
+    f, sp = _gyrating(g)
+    new, mom = O.step(g, 0.25, 1.0, 3, -2.0, f, sp)
+    ref = brute.mover(g, 0.25, 1.0, 3, -2.0, f, sp)
+    for k in ("x", "y", "z", "u", "v", "w"):
+        np.testing.assert_allclose(new[k], ref[k], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(mom, brute.deposit(g, ref), rtol=1e-12, atol=1e-14)
+    scale = np.abs(mom).max()
+    old_x_new_v = dict(ref)
+    old_x_new_v.update({k: sp[k] for k in ("x", "y", "z")})
+    new_x_old_v = dict(ref)
+    new_x_old_v.update({k: sp[k] for k in ("u", "v", "w")})
+    for wrong in (sp, old_x_new_v, new_x_old_v):
+        assert np.abs(brute.deposit(g, wrong) - mom).max() > 1e-3 * scale
+    # the particle did cross the node plane: the node it left behind gets
+    # no charge after the move
+    node0 = ((2 * g.ny + int(0.55 * g.ny)) * g.nz) + int(0.4 * g.nz)
+    assert brute.deposit(g, sp)[0][node0] > 0
+    assert mom[0][node0] == 0.0
+
+
+def test_p16_run_composes_steps_and_returns_the_last_moments():
+    """nsteps fused steps of several species: each species is stepped on its
+    own moved state, and the moments returned are those of the last step."""
+    g = W.Grid(6, 5, 4, 3.0, 2.0, 1.5)
+    f = _rand_fields(g, 161, 0.3)
+    parts = [W.random_particles(g, 6, 0.2, seed=162 + s) for s in range(2)]
+    qoms = [-3.0, 1.0]
+
+    class H:
+        grid, dt, c, niter = g, 0.25, 1.0, 3
+
+    states, moms = O.run(H, f, parts, 3, qoms)
+    for s in range(2):
+        ref = parts[s]
+        for _ in range(3):
+            ref = brute.mover(g, 0.25, 1.0, 3, qoms[s], f, ref)
+        for k in ("x", "y", "z", "u", "v", "w"):
+            np.testing.assert_allclose(states[s][k], ref[k], rtol=1e-11, atol=1e-13)
+        np.testing.assert_allclose(moms[s], brute.deposit(g, ref), rtol=1e-11, atol=1e-13)
+        two = parts[s]
+        for _ in range(2):
+            two = brute.mover(g, 0.25, 1.0, 3, qoms[s], f, two)
+        assert np.abs(brute.deposit(g, two) - moms[s]).max() > 1e-6 * np.abs(moms[s]).max()
