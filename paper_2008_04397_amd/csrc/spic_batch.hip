@@ -101,7 +101,9 @@ struct RunState {
     std::vector<spic_moment_array> mom;
     int nsteps = 0, done_steps = 0;
     bool host = false, streamed = false;
-    size_t footprint = 0;
+    size_t footprint = 0;  // engine-owned bytes while admitted (see RunPlan)
+    size_t sort_need = 0;  // shared sort scratch it needs
+    int64_t batch = 0;     // streamed: particles per batch
     TileGeom tg{};
     hipEvent_t ev_start = nullptr, ev_done = nullptr;
     enum Phase { QUEUED, ACTIVE, RETIRING, DONE } phase = QUEUED;
@@ -199,55 +201,27 @@ struct BatchEngine {
         std::vector<std::shared_ptr<RunState>> made;
         for (int r = 0; r < nruns; ++r) {
             const spic_run &R = runs[r];
+            RunPlan plan;
+            int rc = ctx->plan_run(R, r, plan);
+            if (rc) return rc;
             auto st = std::make_shared<RunState>();
             st->grid = R.grid;
             st->params = R.params;
             st->fields = R.fields;
             st->nsteps = R.nsteps;
-            // one tiling per run, for the dtype of its first species
-            st->tg = ctx->tile_geom(R.grid, R.nspecies > 0 ? R.species[0].dtype : SPIC_F32);
-            if (st->tg.cells < 1 || st->tg.cells > 64)
-                return ctx->fail(SPIC_E_ARG, "run %d: tile shape must hold 1..64 cells", r);
-            size_t fp = 0;
+            st->tg = plan.tg;
+            st->host = plan.host;
+            st->streamed = plan.streamed;
+            st->footprint = plan.footprint;
+            st->sort_need = plan.sort_need;
+            st->batch = plan.batch;
             for (int s = 0; s < R.nspecies; ++s) {
                 SpeciesSlot sl;
                 sl.user = R.species[s];
-                const int acc = R.moments ? R.moments[s].acc_dtype : SPIC_F64;
-                sl.combo = job_combo(sl.user.dtype, R.fields.dtype, acc);
-                if (sl.combo < 0) return ctx->fail(SPIC_E_UNSUPPORTED, "run %d species %d: dtype combination", r, s);
-                if (tiled_lds_bytes(st->tg, sl.user.dtype, acc, 0, 64) > ctx->lds_max)
-                    return ctx->fail(SPIC_E_UNSUPPORTED,
-                                     "run %d species %d: the tile region (tile_x/y/z, halo) does not fit in LDS", r, s);
-                const bool big = !tiled_fits(sl.user.n, sl.user.dtype);
-                if (big && !sl.user.host_resident)
-                    return ctx->fail(SPIC_E_UNSUPPORTED,
-                                     "run %d species %d: device-resident species need n * element size < 4 GiB", r, s);
-                if (sl.user.host_resident) {
-                    st->host = true;
-                    st->streamed = st->streamed || big;  // streamed in batches that fit
-                    fp += species_bytes(sl.user.n, sl.user.dtype, sl.user.id != nullptr);
-                }
-                fp += (size_t)(st->tg.ntiles + 1) * 4 + 256;
+                sl.combo = job_combo(sl.user.dtype, R.fields.dtype, R.moments ? R.moments[s].acc_dtype : SPIC_F64);
                 st->sp.push_back(sl);
             }
             if (R.moments) st->mom.assign(R.moments, R.moments + R.nspecies);
-            st->footprint = fp;
-            if ((ctx->budget && st->host && fp > ctx->budget) || st->streamed) {
-                st->streamed = true;
-                // a streamed run needs two batch slots, the batch sort scratch and its tile ranges
-                int64_t nb = batch_particles;
-                int dt = SPIC_F32;
-                bool id = false;
-                for (auto &sl : st->sp) {
-                    if (sl.user.dtype == SPIC_F64) dt = SPIC_F64;
-                    id = id || sl.user.id;
-                }
-                while (nb > 1024 && 2 * species_bytes(nb, dt, id) + sort_scratch_bytes(nb, dt, id, st->tg) +
-                                            (size_t)64 * (st->tg.ntiles + 1) * 4 > ctx->budget)
-                    nb /= 2;
-                if (2 * species_bytes(nb, dt, id) + sort_scratch_bytes(nb, dt, id, st->tg) > ctx->budget)
-                    return ctx->fail(SPIC_E_BUDGET, "run %d cannot fit the HBM budget even streamed", r);
-            }
             made.push_back(st);
         }
         {
@@ -307,9 +281,12 @@ struct BatchEngine {
         r.ev_start = r.ev_done = nullptr;
     }
 
+    // Engine-owned bytes (admitted runs and the shared sort scratch) plus
+    // the ctx's own scratch stay within the ctx's budget.
     bool fits(const RunState &r) const {
         if (!ctx->budget) return true;
-        return used + r.footprint <= ctx->budget;
+        const uint64_t sort_after = std::max<uint64_t>(sort_bytes, r.sort_need);
+        return used + r.footprint + sort_after + ctx->used.load() <= ctx->budget;
     }
 
     // Allocate and upload a resident run (scheduler thread, engine lock held).
@@ -388,13 +365,22 @@ struct BatchEngine {
         r.phase = RunState::RETIRING;
     }
 
-    void ensure_sort_scratch(size_t need) {
-        if (need <= sort_bytes) return;
+    // Grow the shared sort scratch to `need` bytes.  On failure no scratch
+    // is held (sort_scr == nullptr) and the error is returned: the caller
+    // fails the run before launching anything on it.
+    hipError_t ensure_sort_scratch(size_t need) {
+        if (need <= sort_bytes && sort_scr) return hipSuccess;
         (void)hipStreamSynchronize(cs);
         if (sort_scr) (void)hipFree(sort_scr);
         sort_scr = nullptr;
         sort_bytes = 0;
-        if (hipMalloc(&sort_scr, need) == hipSuccess) sort_bytes = need;
+        const hipError_t e = hipMalloc(&sort_scr, need ? need : 256);
+        if (e != hipSuccess) {
+            sort_scr = nullptr;
+            return e;
+        }
+        sort_bytes = need;
+        return hipSuccess;
     }
 
     void ensure_tables(size_t need) {
@@ -428,12 +414,30 @@ struct BatchEngine {
                     (void)launch_zero32(sl.tile_off, r.tg.ntiles + 1, cs);
                     continue;
                 }
-                ensure_sort_scratch(sort_scratch_bytes(sl.dev.n, sl.dev.dtype, sl.dev.id != nullptr, r.tg));
-                hipError_t e = launch_sort(r.grid, work_of(sl.dev, nullptr), r.tg, sort_scr, sl.tile_off,
-                                           sort_ordered && r.done_steps > 0, cs);
-                if (e != hipSuccess) fail_run(r, e, "sort");
+                hipError_t e = ensure_sort_scratch(sort_scratch_bytes(sl.dev.n, sl.dev.dtype, sl.dev.id != nullptr, r.tg));
+                if (e != hipSuccess) {
+                    fail_run(r, e, "sort scratch");
+                    break;
+                }
+                e = launch_sort(r.grid, work_of(sl.dev, nullptr), r.tg, sort_scr, sl.tile_off,
+                                sort_ordered && r.done_steps > 0, cs);
+                if (e != hipSuccess) {
+                    fail_run(r, e, "sort");
+                    break;
+                }
             }
             sorted_now = true;
+        }
+        // a run whose sort could not run is retired without a kernel touching
+        // its (possibly never written) tile ranges
+        {
+            std::vector<std::shared_ptr<RunState>> ok, bad;
+            for (auto &rp : act) (rp->status == SPIC_OK ? ok : bad).push_back(rp);
+            if (!bad.empty()) {
+                advance(bad);
+                act.swap(ok);
+                if (act.empty()) return;
+            }
         }
         // 2. tables: moment arrays to zero, jobs and items per combo
         std::vector<uint64_t> key;
@@ -737,19 +741,9 @@ void BatchEngine::stream_run(RunState &r) {
         if (sl.user.dtype == SPIC_F64) dt = SPIC_F64;
         with_id = with_id || sl.user.id;
     }
-    const size_t budget = ctx->budget;
-    int64_t nb = batch_particles;
-    auto need = [&](int64_t b, int64_t nbatches) {
-        return 2 * species_bytes(b, dt, with_id) + sort_scratch_bytes(b, dt, with_id, r.tg) +
-               (size_t)nbatches * (r.tg.ntiles + 1) * 4;
-    };
+    const int64_t nb = r.batch;
     int64_t total_batches = 0;
-    for (;;) {
-        total_batches = 0;
-        for (auto &sl : r.sp) total_batches += (sl.user.n + nb - 1) / nb;
-        if (need(nb, total_batches) <= budget || nb <= 1024) break;
-        nb /= 2;
-    }
+    for (auto &sl : r.sp) total_batches += (sl.user.n + nb - 1) / nb;
     void *slot[2] = {nullptr, nullptr};
     void *tiles = nullptr;
     hipEvent_t loaded[2], computed[2], freed[2], t0, t1;
@@ -764,8 +758,9 @@ void BatchEngine::stream_run(RunState &r) {
     if ((e = hipMalloc(&slot[0], sb)) != hipSuccess || (e = hipMalloc(&slot[1], sb)) != hipSuccess ||
         (e = hipMalloc(&tiles, (size_t)std::max<int64_t>(total_batches, 1) * (r.tg.ntiles + 1) * 4)) != hipSuccess) {
         fail_run(r, e, "streaming slots");
+    } else if ((e = ensure_sort_scratch(sort_scratch_bytes(nb, dt, with_id, r.tg))) != hipSuccess) {
+        fail_run(r, e, "sort scratch");
     } else {
-        ensure_sort_scratch(sort_scratch_bytes(nb, dt, with_id, r.tg));
         (void)hipEventRecord(t0, cs);
         int use = 0;  // which slot the next batch goes to
         for (int step = 0; step < r.nsteps && r.status == SPIC_OK; ++step) {
@@ -846,6 +841,72 @@ void BatchEngine::stream_run(RunState &r) {
 }
 
 }  // namespace spic
+
+// ------------------------------------------------------------ planning
+
+namespace spic {
+
+int64_t stream_batch_size(uint64_t budget, int64_t max_batch, int dtype, bool with_id, const TileGeom &tg,
+                          const int64_t *n, int nsp) {
+    auto need = [&](int64_t b) {
+        int64_t nbatches = 0;
+        for (int s = 0; s < nsp; ++s) nbatches += (n[s] + b - 1) / b;
+        return 2 * species_bytes(b, dtype, with_id) + sort_scratch_bytes(b, dtype, with_id, tg) +
+               (size_t)nbatches * (tg.ntiles + 1) * 4;
+    };
+    int64_t nb = max_batch;
+    if (budget == 0) return nb;
+    while (nb > 1024 && need(nb) > budget) nb /= 2;
+    return need(nb) <= budget ? nb : 0;
+}
+
+}  // namespace spic
+
+int spic_ctx_s::plan_run(const spic_run &R, int r, spic::RunPlan &p) {
+    using namespace spic;
+    p = RunPlan{};
+    // one tiling per run, for the dtype of its first species
+    p.tg = tile_geom(R.grid, R.nspecies > 0 ? R.species[0].dtype : SPIC_F32);
+    if (p.tg.cells < 1 || p.tg.cells > 64) return fail(SPIC_E_ARG, "run %d: tile shape must hold 1..64 cells", r);
+    std::vector<int64_t> ns;
+    for (int s = 0; s < R.nspecies; ++s) {
+        const spic_species &sp = R.species[s];
+        const int acc = R.moments ? R.moments[s].acc_dtype : SPIC_F64;
+        if (job_combo(sp.dtype, R.fields.dtype, acc) < 0)
+            return fail(SPIC_E_UNSUPPORTED, "run %d species %d: dtype combination", r, s);
+        if (tiled_lds_bytes(p.tg, sp.dtype, acc, 0, 64) > lds_max)
+            return fail(SPIC_E_UNSUPPORTED, "run %d species %d: the tile region (tile_x/y/z, halo) does not fit in LDS",
+                        r, s);
+        const bool big = !tiled_fits(sp.n, sp.dtype);
+        if (big && !sp.host_resident)
+            return fail(SPIC_E_UNSUPPORTED,
+                        "run %d species %d: device-resident species need n * element size < 4 GiB", r, s);
+        if (sp.dtype == SPIC_F64) p.dtype = SPIC_F64;
+        p.with_id = p.with_id || sp.id;
+        if (sp.host_resident) {
+            p.host = true;
+            p.streamed = p.streamed || big;  // streamed in batches that fit
+            p.footprint += species_bytes(sp.n, sp.dtype, sp.id != nullptr);
+        }
+        // tile ranges, and the species' share of the tick tables (one job, one item per tile)
+        p.footprint += (size_t)(p.tg.ntiles + 1) * 4 + 256 + (size_t)p.tg.ntiles * 8 + 512;
+        if (!big) p.sort_need = std::max(p.sort_need, sort_scratch_bytes(sp.n, sp.dtype, sp.id != nullptr, p.tg));
+        ns.push_back(sp.n);
+    }
+    if (budget && p.host && p.footprint + p.sort_need > budget) p.streamed = true;
+    if (p.streamed) {
+        p.batch = stream_batch_size(budget, opt("batch_particles", (int64_t)1 << 26), p.dtype, p.with_id, p.tg,
+                                    ns.data(), (int)ns.size());
+        if (p.batch <= 0) return fail(SPIC_E_BUDGET, "run %d cannot fit the HBM budget even streamed", r);
+        p.footprint = 0;  // a streamed run runs alone and owns its slots for its duration
+        p.sort_need = 0;
+        return SPIC_OK;
+    }
+    if (budget && p.footprint + p.sort_need > budget)
+        return fail(SPIC_E_BUDGET, "run %d needs %zu bytes of engine memory and %zu of sort scratch; the budget is %llu",
+                    r, p.footprint, p.sort_need, (unsigned long long)budget);
+    return SPIC_OK;
+}
 
 // ------------------------------------------------------------ ctx hooks
 

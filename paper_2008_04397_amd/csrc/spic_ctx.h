@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -12,6 +13,27 @@
 
 namespace spic {
 struct BatchEngine;  // spic_batch.hip
+
+// Host-side plan of one spic_batch_submit run (spic_batch.hip): its tiling,
+// the engine-owned bytes it holds while admitted, the sort scratch its
+// resident species need, and whether (and in batches of how many
+// particles) it is streamed from host memory.
+struct RunPlan {
+    TileGeom tg{};
+    size_t footprint = 0;  // particle slots (host-resident runs) + tile ranges + tick tables
+    size_t sort_need = 0;  // shared sort scratch for its largest resident species
+    bool host = false, streamed = false;
+    int dtype = SPIC_F32;  // widest particle dtype of its species
+    bool with_id = false;
+    int64_t batch = 0;     // streamed: particles per batch
+};
+
+// Particles per streamed batch: the largest power-of-two fraction of
+// max_batch whose two device slots, batch sort scratch and per-batch tile
+// ranges fit `budget` (0 = no limit: max_batch itself); 0 when even 1024
+// particles do not fit.
+int64_t stream_batch_size(uint64_t budget, int64_t max_batch, int dtype, bool with_id, const TileGeom &tg,
+                          const int64_t *n, int nsp);
 }
 
 struct spic_ctx_s {
@@ -21,9 +43,9 @@ struct spic_ctx_s {
     };
 
     int device = 0;        // -1: host-only context (validation only)
-    size_t lds_max = 64 * 1024;  // LDS bytes one workgroup may use on the device
+    size_t lds_max = 160 * 1024;  // LDS bytes one workgroup may use (gfx950: 160 KiB; queried on a device)
     uint64_t budget = 0;   // 0 = unlimited
-    uint64_t used = 0;     // bytes of library scratch currently allocated
+    std::atomic<uint64_t> used{0};  // bytes of library scratch currently allocated (read by the engine)
     std::string err;
     std::mutex mu;         // serialises the ABI calls on one ctx
     std::map<std::string, int64_t> options;
@@ -73,6 +95,9 @@ struct spic_ctx_s {
     int sort_prepare(const spic_grid &g, const spic_species *sp, int32_t nsp, size_t &need);
     int sort_one(const spic_grid &g, const spic_species &sp, const spic::TileGeom &tg, size_t need, hipStream_t s,
                  uint32_t **toff_out, spic::SpeciesWork *sorted_out);
+    // the plan of run r (validated), or an error (SPIC_E_BUDGET when it
+    // cannot fit the budget even streamed); makes no HIP call
+    int plan_run(const spic_run &R, int r, spic::RunPlan &p);
     int batch_submit(const spic_run *runs, int32_t nruns, uint64_t *tickets);
     int wait(uint64_t ticket, double *secs);
     int poll(uint64_t ticket, int32_t *done);

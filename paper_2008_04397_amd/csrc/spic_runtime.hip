@@ -382,6 +382,10 @@ int spic_batch_submit(spic_ctx ctx, const spic_run *runs, int32_t nruns, uint64_
             (rc = ctx->check_combo(&R.fields, R.species, R.nspecies)))
             return ctx->fail(rc, "run %d: %s", r, std::string(ctx->err).c_str());
         if (R.nsteps < 0) return ctx->fail(SPIC_E_ARG, "run %d: nsteps < 0", r);
+        // admission plan (host only): a run that cannot fit the budget even
+        // streamed is refused here, also on a host-only context
+        spic::RunPlan plan;
+        if ((rc = ctx->plan_run(R, r, plan))) return rc;
     }
     if (ctx->device < 0) return ctx->host_only();
     DeviceGuard dg(ctx->device);

@@ -706,6 +706,7 @@ hipError_t launch_sort(const spic_grid &g, const SpeciesWork &w, const TileGeom 
         if (sorted_out) *sorted_out = w;
         return launch_zero32(tile_off, tg.ntiles + 1, s);
     }
+    if (!scratch || !tile_off) return hipErrorInvalidValue;  // nothing is launched without scratch
     return w.dtype == SPIC_F64 ? sort_t<double>(g, w, tg, scratch, tile_off, prev, s, sorted_out)
                                : sort_t<float>(g, w, tg, scratch, tile_off, prev, s, sorted_out);
 }

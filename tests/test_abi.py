@@ -181,3 +181,52 @@ def test_serving_summary_statistics():
     s = serving.summarize(done)
     assert abs(s["p50_s"] - 5.05) < 0.06 and abs(s["p99_s"] - 9.9) < 0.02
     assert s["particle_steps"] == 100 * 1000 * 10
+
+
+def _planned_submit(budget, n, host_resident=True, dtype=np.float32):
+    """spic_batch_submit of one run with one species of n particles on a
+    host-only context with the given HBM budget (the arrays stand in for
+    memory that is never touched: only the admission plan runs)."""
+    a = _HostArrays(dtype=dtype)
+    ctx = spic.Context(-1, budget)
+    try:
+        r = spic.spic_run()
+        r.grid = spic.make_grid(W.Grid(8, 8, 8))
+        r.params = spic.make_params(0.25, 1.0, 3, 4, 0)
+        r.fields = spic.make_fields(a.f)
+        s = spic.make_species(a.sp, -64.0, host_resident=host_resident)
+        s.n = int(n)
+        sp = spic._arr(spic.spic_species, [s])
+        mom = spic._arr(spic.spic_moment_array, [spic.make_moments(a.m)])
+        r.species = C.cast(sp, C.POINTER(spic.spic_species))
+        r.moments = C.cast(mom, C.POINTER(spic.spic_moment_array))
+        r.nspecies = 1
+        r.nsteps = 2
+        t = (C.c_uint64 * 1)()
+        st = spic.lib().spic_batch_submit(ctx.handle, spic._arr(spic.spic_run, [r]), 1, t)
+        return st, spic.lib().spic_last_error(ctx.handle).decode()
+    finally:
+        ctx.close()
+
+
+def test_batch_admission_plan_budget_zero_is_unlimited():
+    """A host-resident species of 2^31 FP32 particles (8 GiB per array, so it
+    must be streamed) with no budget (0 = no limit) is accepted, streamed in
+    batches of the configured size; it is not refused as over budget."""
+    st, msg = _planned_submit(0, 1 << 31)
+    assert st == spic.SPIC_E_STATE, msg
+
+
+def test_batch_admission_plan_small_budgets():
+    # 64 MiB: the same run streams in smaller batches
+    st, msg = _planned_submit(64 << 20, 1 << 31)
+    assert st == spic.SPIC_E_STATE, msg
+    # 1 MiB: not even batches of 1024 particles with their sort scratch fit
+    st, msg = _planned_submit(1 << 20, 1 << 31)
+    assert st == spic.SPIC_E_BUDGET and "even streamed" in msg, msg
+    # device-resident particles whose sort scratch alone exceeds the budget
+    st, msg = _planned_submit(1 << 20, 1 << 20, host_resident=False)
+    assert st == spic.SPIC_E_BUDGET and "sort scratch" in msg, msg
+    # the same run with room for its sort scratch is accepted
+    st, msg = _planned_submit(1 << 30, 1 << 20, host_resident=False)
+    assert st == spic.SPIC_E_STATE, msg
