@@ -45,16 +45,17 @@ class Done:
         return self.complete - self.arrival
 
 
-def make_request_run(req: W.Request, dtype=None, sort_every: int = 4, device="cuda"):
+def make_request_run(req: W.Request, dtype=None, sort_every: int = 4, device="cuda", with_id: bool = False):
     """Inputs of one request: fields on the device, 4 species in pinned host
-    memory, FP64 moment outputs on the device."""
+    memory (with int64 particle ids when with_id), FP64 moment outputs on the
+    device."""
     import torch
     dtype = dtype or torch.float32
     h = req.box
     f = W.fields_tensors(h, device=device, dtype=dtype)
     species = []
     for s in range(4):
-        t = W.species_tensors(h, s, device=device, dtype=dtype, seed_offset=req.rid)
+        t = W.species_tensors(h, s, device=device, dtype=dtype, seed_offset=req.rid, with_id=with_id)
         species.append({k: torch.empty(v.shape, dtype=v.dtype, pin_memory=True).copy_(v) for k, v in t.items()})
     moms = spic.moment_buffers(h.grid, 4, torch.float64, device)
     prm = spic.make_params(h.dt, h.c, h.niter, sort_every, 0)
@@ -70,7 +71,7 @@ def pinned_bytes(req: W.Request, dtype=None) -> int:
 
 def serve(ctx: "spic.Context", requests: Sequence[W.Request], mode: str = "continuous",
           dtype=None, sort_every: int = 4, time_scale: float = 1.0, log=None, keep=None,
-          max_pinned_bytes: int = 16 << 30) -> List[Done]:
+          max_pinned_bytes: int = 16 << 30, with_id: bool = False) -> List[Done]:
     """Replay the arrival trace (arrival times multiplied by time_scale).
     When `keep` is a dict, keep[rid] receives each request's finished run
     (its species and moments hold the results)."""
@@ -96,7 +97,7 @@ def serve(ctx: "spic.Context", requests: Sequence[W.Request], mode: str = "conti
         while inflight and sum(v[3] for v in inflight.values()) + need > max_pinned_bytes:
             poll_all()
             time.sleep(0.0005)
-        run = make_request_run(req, dtype, sort_every)
+        run = make_request_run(req, dtype, sort_every, with_id=with_id)
         torch.cuda.current_stream().synchronize()
         arrival = req.arrival * time_scale
         while now() < arrival:

@@ -353,7 +353,7 @@ def serving_stream(n_req: int = 1000, rate: float = 20.0, seed: int = 5,
 # ---------------------------------------------------------------------------
 
 def species_tensors(h: Harris, s: int, i0: int = 0, i1: Optional[int] = None, device="cuda", dtype=None,
-                    seed_offset: int = 0):
+                    seed_offset: int = 0, with_id: bool = False):
     import torch
     dtype = dtype or torch.float32
     g = h.grid
@@ -395,6 +395,8 @@ def species_tensors(h: Harris, s: int, i0: int = 0, i1: Optional[int] = None, de
     q = math.copysign(1.0, h.qoms[s]) * dens * (dx * dy * dz / ppc)
     out = {"x": x.to(dtype), "y": y.to(dtype), "z": z.to(dtype), "u": u.to(dtype), "v": v.to(dtype),
            "w": w.to(dtype), "q": q.to(dtype)}
+    if with_id:  # the particle's index in the whole box (cell-major, then lattice site)
+        out["id"] = (i0 * g.ny * g.nz) * ppc + torch.arange(n, device=device, dtype=torch.int64)
     return out
 
 

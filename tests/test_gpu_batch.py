@@ -259,3 +259,67 @@ def test_aging_credit_bounds_how_long_a_run_waits(spic, aging):
             P.assert_state(got[s], st[s], h.grid, P.POS64, P.VEL64)
             P.assert_moments(run.moments[s].cpu().numpy(), ms[s], P.MOM64)
     ctx.close()
+
+def _fp32_one_step_check(h, run, sps):
+    """One FP32 step from the FP32-rounded input against the oracle's step
+    of the same state (upcast): positions <= 1e-5 L_d, velocities <= 1e-5
+    max(|v|, vth); moments against the oracle's FP64 deposit of the GPU's
+    own final FP32 state, rel-L2 <= 1e-6 (Sec. II moment sum of the state
+    the mover produced)."""
+    f = W.make_fields(h)
+    f32 = {k: v.astype(np.float32).astype(np.float64) for k, v in f.items()}
+    got = _host(run)
+    worst = [0.0, 0.0, 0.0]
+    for s in range(4):
+        ora = O.mover(h.grid, h.dt, h.c, h.niter, h.qoms[s], f32, W.upcast(sps[s]))
+        pe, ve = P.assert_state(got[s], ora, h.grid, P.POS32, P.VEL32, vscale=max(P.vmax(ora), h.vths[s]))
+        ref = O.deposit(h.grid, W.upcast(got[s]))
+        me = P.assert_moments(run.moments[s].cpu().numpy(), ref, P.MOM32)
+        worst = [max(worst[0], pe), max(worst[1], ve), max(worst[2], me)]
+    return worst
+
+
+def test_fp32_work_list_run_matches_oracle(spic):
+    """The batch engine's FP32-particle path (work-list launches, FP64
+    moments) on three boxes of different shape: one step each against the
+    oracle."""
+    ctx = spic.Context(0)
+    boxes = _boxes()
+    made = [_run_of(spic, h, 1, dtype=torch.float32) for h in boxes]
+    _say("case batch fp32 work list: 3 boxes x 1 step")
+    for t in spic.spic_batch_submit(ctx, [m[0] for m in made]):
+        spic.spic_wait(ctx, t)
+    for h, (run, sps) in zip(boxes, made):
+        _say("fp32 work list %s: pos/L %.2e vel %.2e mom %.2e" % ((h.grid,) + tuple(_fp32_one_step_check(h, run, sps))))
+    ctx.close()
+
+
+def test_streamed_fp64_run_matches_oracle(spic):
+    """Streamed through a 3 MiB budget in batches of 8192 particles (sorted
+    at step 0 and every 2 steps, per batch), FP64: 3 steps against the
+    oracle at the FP64 tolerances."""
+    h = W.harris_32x16x4()
+    ctx = spic.Context(0, hbm_budget_bytes=3 << 20)
+    ctx.set_option("batch_particles", 8192)
+    run, sps = _run_of(spic, h, 3, dtype=torch.float64, host=True, sort_every=2)
+    _say("case streamed fp64 vs oracle, budget 3 MiB, batches of 8192")
+    spic.spic_wait(ctx, spic.spic_batch_submit(ctx, [run])[0])
+    st, ms = _oracle(h, sps, 3)
+    got = _host(run)
+    for s in range(4):
+        P.assert_state(got[s], st[s], h.grid, P.POS64, P.VEL64)
+        P.assert_moments(run.moments[s].cpu().numpy(), ms[s], P.MOM64)
+    ctx.close()
+
+
+def test_streamed_fp32_step_matches_oracle(spic):
+    """The same box streamed with FP32 particles (FP64 moments): one step
+    against the oracle at the FP32 tolerances."""
+    h = W.harris_32x16x4()
+    ctx = spic.Context(0, hbm_budget_bytes=3 << 20)
+    ctx.set_option("batch_particles", 8192)
+    run, sps = _run_of(spic, h, 1, dtype=torch.float32, host=True)
+    _say("case streamed fp32 vs oracle, budget 3 MiB, batches of 8192")
+    spic.spic_wait(ctx, spic.spic_batch_submit(ctx, [run])[0])
+    _say("streamed fp32: pos/L %.2e vel %.2e mom %.2e" % tuple(_fp32_one_step_check(h, run, sps)))
+    ctx.close()

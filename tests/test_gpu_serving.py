@@ -1,19 +1,18 @@
 """Serving: a Poisson stream of small Harris-box runs through the batch
 engine with continuous batching; every request's result must equal the
-same request run alone (particles bitwise by position in the sorted order
-of ids is not available here -- the inputs carry no ids -- so particles are
-compared as sorted multisets per component).  Moments agree within 1e-12
-with the LDS-atomic deposit (variant 0: FP64 terms, only the order of FP64
-additions differs); with the default lane-cell deposit of FP32 particles
-(variant 5) the FP32 partial sums depend on which particles share a
-thread, and the order of particles inside a cell after a sort is not
-fixed, so they agree within the FP32 moment tolerance (rel 1e-6)."""
+same request run alone: particles bitwise, matched by particle id (the
+engine sorts them, so their order differs), and moments within 1e-12
+where every deposit term is FP64 (only the order of FP64 additions
+differs) or within the FP32 moment tolerance (rel 1e-6) where FP32
+partial sums over the particles one thread holds are formed (their
+grouping depends on the order inside a cell after a sort)."""
 import sys
 
 import numpy as np
 import pytest
 
 from paper_2008_04397_amd import workloads as W
+from tests import parity as P
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -35,19 +34,20 @@ def test_each_request_alone_equals_continuous_mix(variant, tol):
     ctx.set_option("tile_variant", variant)
     mixed = {}
     _say("case serving continuous 8 requests, tile_variant %d" % variant)
-    done = serving.serve(ctx, reqs, mode="continuous", keep=mixed)
+    done = serving.serve(ctx, reqs, mode="continuous", keep=mixed, with_id=True)
     assert len(done) == len(reqs)
     s = serving.summarize(done)
     assert s["p99_s"] >= s["p50_s"] > 0
     for req in reqs:
-        alone = serving.make_request_run(req)
+        alone = serving.make_request_run(req, with_id=True)
         spic.spic_wait(ctx, spic.spic_batch_submit(ctx, [alone])[0])
         mix = mixed[req.rid]
         for sa, sb in zip(alone.species, mix.species):
-            for k in ("x", "y", "z", "u", "v", "w"):
-                a = np.sort(sa[k].numpy())
-                b = np.sort(sb[k].numpy())
-                assert np.array_equal(a, b), (req.rid, k)
+            a = P.by_id({k: v.numpy() for k, v in sa.items()})
+            b = P.by_id({k: v.numpy() for k, v in sb.items()})
+            assert np.array_equal(a["id"], b["id"]) and np.array_equal(a["id"], np.arange(a["id"].size))
+            for k in ("x", "y", "z", "u", "v", "w", "q"):
+                assert np.array_equal(a[k], b[k]), (req.rid, k)
         for ma, mb in zip(alone.moments, mix.moments):
             a, b = ma.cpu().numpy(), mb.cpu().numpy()
             for c in range(10):
