@@ -37,10 +37,13 @@ def lib():
         L.oracle_weights.argtypes = [gp, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_int64), dp]
         L.oracle_gather.argtypes = [gp] + [dp] * 6 + [dp] * 3 + [C.c_int64, dp]
         L.oracle_mover.argtypes = [gp, C.c_double, C.c_double, C.c_int, C.c_double] + [dp] * 6 + [dp] * 6 + [C.c_int64]
+        L.oracle_mover_tol.argtypes = ([gp, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double] + [dp] * 6 +
+                                       [dp] * 6 + [C.c_int64, C.POINTER(C.c_int32)])
         L.oracle_deposit.argtypes = [gp] + [dp] * 7 + [C.c_int64, dp, C.c_int]
         L.oracle_max_threads.argtypes = []
-        for f in ("oracle_weights", "oracle_gather", "oracle_mover", "oracle_deposit",
-                  "oracle_max_threads"):
+        L.oracle_set_threads.argtypes = [C.c_int]
+        for f in ("oracle_weights", "oracle_gather", "oracle_mover", "oracle_mover_tol", "oracle_deposit",
+                  "oracle_max_threads", "oracle_set_threads"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -61,6 +64,11 @@ def _f64(a) -> np.ndarray:
 
 def max_threads() -> int:
     return int(lib().oracle_max_threads())
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's parallel loops from now on; returns the count in effect."""
+    return int(lib().oracle_set_threads(int(n)))
 
 
 def weights(g, x: float, y: float, z: float):
@@ -98,6 +106,26 @@ def mover(g, dt: float, c: float, niter: int, qom: float, fields: Dict[str, np.n
     return out
 
 
+def mover_tol(g, dt: float, c: float, niter: int, tol: float, qom: float, fields: Dict[str, np.ndarray],
+              sp: Dict[str, np.ndarray]):
+    """One implicit step with the tolerance-terminated iteration (Sec. II:
+    the count may be set by a prescribed error tolerance): each particle
+    stops after pass k >= 2 once max_d |vbar^k - vbar^(k-1)| < tol, at most
+    niter passes; tol = 0 is the fixed count.  Returns (new state, passes
+    per particle)."""
+    f = [_f64(fields[k]) for k in _F6]
+    st = {k: _f64(sp[k]) for k in ("x", "y", "z", "u", "v", "w")}
+    n = st["x"].size
+    it = np.zeros(n, dtype=np.int32)
+    rc = lib().oracle_mover_tol(C.byref(_grid(g)), float(dt), float(c), int(niter), float(tol), float(qom),
+                                *[_p(a) for a in f], *[_p(st[k]) for k in ("x", "y", "z", "u", "v", "w")], n,
+                                it.ctypes.data_as(C.POINTER(C.c_int32)))
+    assert rc == 0
+    out = dict(sp)
+    out.update(st)
+    return out, it
+
+
 def deposit(g, sp: Dict[str, np.ndarray], mom: Optional[np.ndarray] = None) -> np.ndarray:
     """The ten moments [10, nodes] of one species (accumulated into mom if given)."""
     a = {k: _f64(sp[k]) for k in ("x", "y", "z", "u", "v", "w", "q")}
@@ -114,9 +142,11 @@ def deposit(g, sp: Dict[str, np.ndarray], mom: Optional[np.ndarray] = None) -> n
     return mom
 
 
-def step(g, dt: float, c: float, niter: int, qom: float, fields, sp):
-    """Fused step of one species: (new state, moments of the new state)."""
-    new = mover(g, dt, c, niter, qom, fields, sp)
+def step(g, dt: float, c: float, niter: int, qom: float, fields, sp, tol: float = 0.0):
+    """Fused step of one species: (new state, moments of the new state);
+    tol > 0 takes the tolerance-terminated iteration with niter as the cap."""
+    new = mover(g, dt, c, niter, qom, fields, sp) if tol == 0.0 else mover_tol(g, dt, c, niter, tol, qom, fields,
+                                                                                  sp)[0]
     return new, deposit(g, new)
 
 

@@ -138,17 +138,27 @@ int oracle_gather(const og_grid *g, const double *ex, const double *ey, const do
  *     vbar   = (vt + vt x bv + (vt . bv) bv) / (1 + bv . bv)      (Eq. 2)
  *     xbar   = x^n + vbar dt / 2                 (half-step position estimate)
  *   v^{n+1} = 2 vbar - v^n, x^{n+1} = x^n + vbar dt, wrapped     (Eq. 5)
+ *
+ * Sec. II also allows the iteration count to be set by a prescribed error
+ * tolerance instead of being fixed.  With tol > 0, niter is the cap and the
+ * iteration stops after the k-th pass (k >= 2) once the change of the mean
+ * velocity over that pass, max_d |vbar^k_d - vbar^(k-1)_d|, is below tol
+ * (an absolute tolerance in velocity units; the paper gives no criterion,
+ * this is the reading used by the library too).  tol = 0 never stops early:
+ * the fixed count.  Returns the number of passes made.
  */
-static void og_move1(const og_grid *g, const double *const f[6], double dt, double c,
-                     int niter, double qom, double *px, double *py, double *pz,
-                     double *pu, double *pv, double *pw)
+static int og_move1(const og_grid *g, const double *const f[6], double dt, double c,
+                    int niter, double tol, double qom, double *px, double *py, double *pz,
+                    double *pu, double *pv, double *pw)
 {
     const double x0 = *px, y0 = *py, z0 = *pz;
     const double u0 = *pu, v0 = *pv, w0 = *pw;
     const double beta = qom * dt / 2.0;
     double xb = x0, yb = y0, zb = z0;
     double ub = u0, vb = v0, wb = w0;
-    for (int it = 0; it < niter; ++it) {
+    int it = 0;
+    while (it < niter) {
+        const double pu_ = ub, pv_ = vb, pw_ = wb;
         double F[6];
         og_gather6(g, f, xb, yb, zb, F);
         double ut = u0 + beta * F[0];
@@ -169,6 +179,13 @@ static void og_move1(const og_grid *g, const double *const f[6], double dt, doub
         xb = x0 + ub * dt / 2.0;
         yb = y0 + vb * dt / 2.0;
         zb = z0 + wb * dt / 2.0;
+        ++it;
+        if (it >= 2 && tol > 0.0) {
+            double d = fabs(ub - pu_);
+            if (fabs(vb - pv_) > d) d = fabs(vb - pv_);
+            if (fabs(wb - pw_) > d) d = fabs(wb - pw_);
+            if (d < tol) break;
+        }
     }
     *pu = 2.0 * ub - u0;
     *pv = 2.0 * vb - v0;
@@ -176,6 +193,7 @@ static void og_move1(const og_grid *g, const double *const f[6], double dt, doub
     *px = og_wrap(x0 + ub * dt, g->Lx);
     *py = og_wrap(y0 + vb * dt, g->Ly);
     *pz = og_wrap(z0 + wb * dt, g->Lz);
+    return it;
 }
 
 int oracle_mover(const og_grid *g, double dt, double c, int niter, double qom,
@@ -188,7 +206,25 @@ int oracle_mover(const og_grid *g, double dt, double c, int niter, double qom,
     const double *f[6] = {ex, ey, ez, bx, by, bz};
 #pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < n; ++p)
-        og_move1(g, f, dt, c, niter, qom, &x[p], &y[p], &z[p], &u[p], &v[p], &w[p]);
+        (void)og_move1(g, f, dt, c, niter, 0.0, qom, &x[p], &y[p], &z[p], &u[p], &v[p], &w[p]);
+    return 0;
+}
+
+/* The mover with the tolerance-terminated iteration (tol > 0: niter is the
+ * cap); iters[p] (may be NULL) receives the passes particle p made. */
+int oracle_mover_tol(const og_grid *g, double dt, double c, int niter, double tol, double qom,
+                     const double *ex, const double *ey, const double *ez,
+                     const double *bx, const double *by, const double *bz,
+                     double *x, double *y, double *z, double *u, double *v, double *w,
+                     int64_t n, int32_t *iters)
+{
+    if (!g || n < 0 || niter < 0 || !(tol >= 0.0) || g->nx < 1 || g->ny < 1 || g->nz < 1) return -1;
+    const double *f[6] = {ex, ey, ez, bx, by, bz};
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < n; ++p) {
+        int k = og_move1(g, f, dt, c, niter, tol, qom, &x[p], &y[p], &z[p], &u[p], &v[p], &w[p]);
+        if (iters) iters[p] = k;
+    }
     return 0;
 }
 
@@ -211,7 +247,8 @@ static void og_deposit1(const og_grid *g, int64_t nn, double *m, double x, doubl
 
 /* Moments of n particles into mom[10][nodes]; overwrite unless accumulate.
  * Each thread sums its static block of particles, in particle order, into a
- * private grid; the private grids are then added in thread order. */
+ * private grid; the private grids are then added in thread order, node by
+ * node. */
 int oracle_deposit(const og_grid *g, const double *x, const double *y, const double *z,
                    const double *u, const double *v, const double *w, const double *q,
                    int64_t n, double *mom, int accumulate)
@@ -237,9 +274,13 @@ int oracle_deposit(const og_grid *g, const double *x, const double *y, const dou
         for (int64_t p = lo; p < hi; ++p)
             og_deposit1(g, nn, m, x[p], y[p], z[p], u[p], v[p], w[p], q[p]);
     }
-    for (int t = 0; t < nt; ++t) {
-        const double *m = priv + (size_t)t * 10 * (size_t)nn;
-        for (int64_t i = 0; i < 10 * nn; ++i) mom[i] += m[i];
+    /* node by node, the threads' grids in thread order (the same additions,
+     * in the same order, as adding whole grids one after the other) */
+#pragma omp parallel for schedule(static) num_threads(nt)
+    for (int64_t i = 0; i < 10 * nn; ++i) {
+        double acc = mom[i];
+        for (int t = 0; t < nt; ++t) acc += priv[(size_t)t * 10 * (size_t)nn + (size_t)i];
+        mom[i] = acc;
     }
     free(priv);
     return 0;
@@ -250,6 +291,19 @@ int oracle_max_threads(void)
 #ifdef _OPENMP
     return omp_get_max_threads();
 #else
+    return 1;
+#endif
+}
+
+/* Threads the oracle's parallel loops use from now on (>= 1); returns the
+ * count in effect.  Lets the CPU timing run on one core and on all. */
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
     return 1;
 #endif
 }

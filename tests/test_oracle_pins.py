@@ -400,3 +400,84 @@ def test_p16_run_composes_steps_and_returns_the_last_moments():
         for _ in range(2):
             two = brute.mover(g, 0.25, 1.0, 3, qoms[s], f, two)
         assert np.abs(brute.deposit(g, two) - moms[s]).max() > 1e-6 * np.abs(moms[s]).max()
+
+
+# --------------------------------------------------------------------- P17
+# The tolerance-terminated predictor-corrector (Sec. II: the iteration count
+# may be set by a prescribed error tolerance instead of being fixed).  Each
+# particle stops after pass k >= 2 once max_d |vbar^k - vbar^(k-1)| < tol,
+# with niter as the cap; tol = 0 is the fixed count.
+
+def test_p17_zero_tolerance_is_the_fixed_count():
+    f = _rand_fields(G, 17, 0.05)
+    sp = W.random_particles(G, 300, 0.05, seed=17)
+    for niter in (1, 2, 3, 5):
+        ref = O.mover(G, 0.25, 1.0, niter, -64.0, f, sp)
+        out, it = O.mover_tol(G, 0.25, 1.0, niter, 0.0, -64.0, f, sp)
+        assert np.all(it == niter)
+        for k in ("x", "y", "z", "u", "v", "w"):
+            assert np.array_equal(out[k], ref[k]), (niter, k)
+
+
+def test_p17_uniform_fields_stop_after_the_second_pass():
+    """In uniform fields the second pass gathers the same fields (to a few
+    ulp, P2), so its mean velocity repeats the first's and every particle
+    stops there, with the two-pass fixed-count result."""
+    f = W.uniform_fields(G, E=(0.01, -0.02, 0.005), B=(0.3, 0.1, -0.2))
+    sp = W.random_particles(G, 200, 0.05, seed=18)
+    ref = O.mover(G, 0.25, 1.0, 2, -64.0, f, sp)
+    out, it = O.mover_tol(G, 0.25, 1.0, 8, 1e-12, -64.0, f, sp)
+    assert np.all(it == 2)
+    for k in ("x", "y", "z", "u", "v", "w"):
+        assert np.array_equal(out[k], ref[k]), k
+    # no field: the first pass already returns v^n, and the change is first
+    # measured over the second pass (pass 1 has no predecessor)
+    z = W.uniform_fields(G, E=(0.0, 0.0, 0.0), B=(0.0, 0.0, 0.0))
+    out, it = O.mover_tol(G, 0.25, 1.0, 8, 1e-12, -64.0, z, sp)
+    assert np.all(it == 2)
+    for k in ("u", "v", "w"):
+        assert np.array_equal(out[k], sp[k]), k
+
+
+def test_p17_each_particle_stops_at_its_first_small_change():
+    """Against fixed-count runs: a particle that made k passes has the k-pass
+    fixed-count state, the change of the mean velocity over pass k is below
+    tol and (below the cap) no earlier pass's change was; the mean velocity
+    of a j-pass run is (v^{n+1} + v^n) / 2 of that run."""
+    f = _rand_fields(G, 19, 0.05)
+    sp = W.random_particles(G, 400, 0.05, seed=19)
+    cap, tol, qom, dt = 8, 1e-6, -64.0, 0.25
+    out, it = O.mover_tol(G, dt, 1.0, cap, tol, qom, f, sp)
+    assert it.min() >= 2 and it.max() <= cap and len(np.unique(it)) >= 3, np.bincount(it)
+    runs = {j: O.mover(G, dt, 1.0, j, qom, f, sp) for j in range(1, cap + 1)}
+    vbar = {j: np.stack([(runs[j][k] + sp[k]) / 2 for k in ("u", "v", "w")]) for j in runs}
+    dv = {j: np.abs(vbar[j] - vbar[j - 1]).max(axis=0) for j in range(2, cap + 1)}
+    for p in range(sp["x"].size):
+        k = int(it[p])
+        for a in ("x", "y", "z", "u", "v", "w"):
+            assert out[a][p] == runs[k][a][p], (p, k, a)
+        margin = 1e-9 * tol + 1e-15
+        if k < cap:
+            assert dv[k][p] < tol + margin, (p, k, dv[k][p])
+        for j in range(2, k):
+            assert dv[j][p] >= tol - margin, (p, j, k, dv[j][p])
+
+
+def test_p17_converged_mean_velocity_solves_the_implicit_equation():
+    """With a tight tolerance the iteration reaches its fixed point: vbar
+    solves Eq. 2's implicit equation vbar = v^n + beta E + (beta/c) vbar x B
+    with E, B gathered (brute force, all nodes) at its own half-step
+    position x^n + vbar dt/2."""
+    f = _rand_fields(G, 20, 0.05)
+    sp = W.random_particles(G, 40, 0.05, seed=20)
+    dt, c, qom = 0.25, 1.0, -64.0
+    out, it = O.mover_tol(G, dt, c, 200, 1e-15, qom, f, sp)
+    assert it.max() < 200
+    beta = qom * dt / 2
+    for p in range(sp["x"].size):
+        v0 = np.array([sp["u"][p], sp["v"][p], sp["w"][p]])
+        vb = (np.array([out["u"][p], out["v"][p], out["w"][p]]) + v0) / 2
+        xh = np.array([sp["x"][p], sp["y"][p], sp["z"][p]]) + vb * dt / 2
+        F = brute.gather(G, f, *xh)
+        res = vb - (v0 + beta * F[:3] + (beta / c) * np.cross(vb, F[3:]))
+        assert np.abs(res).max() <= 1e-13, (p, res)
