@@ -46,6 +46,12 @@ sys.path.insert(0, HERE)
 from paper_2008_04397_amd import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# what each path computes in which precision (the default launch)
+PRECISION = {
+    "f32": "f32 particles and mover; deposit weights in f64, the ten terms in f32 and summed in f32 over the "
+           "particles one lane holds in one cell (~16 at 64 per cell), every further sum in f64",
+    "f64": "f64 particles, mover and moment accumulation",
+}
 METRIC = "particle-steps/s (mover+moments) FP32 vs FP64; % HBM peak; p99 latency"
 
 
@@ -97,7 +103,7 @@ def _new_ctx(spic, *a):
 
 
 def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: int, tune: bool = True,
-            variant: int = -1):
+            variant: int = -1, tol: float = 0.0, niter: int = 3):
     import torch
     from paper_2008_04397_amd import autotune, spic
 
@@ -132,11 +138,11 @@ def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: 
         sort_every = 4
     if variant >= 0:
         ctx.set_option("tile_variant", variant)
-    launch = spic.resolved_launch(ctx, "f32" if dtype_name == "f32" else "f64", "f64")
+    launch = spic.resolved_launch(ctx, "f32" if dtype_name == "f32" else "f64")
     launch["sort_every"] = sort_every
 
     def step(k, ev=None):
-        prm = spic.make_params(h.dt, h.c, h.niter, sort_every, k)
+        prm = spic.make_params(h.dt, h.c, niter, sort_every, k, tol=tol)
         if ev is None:
             spic.spic_mover(ctx, g, prm, f, species, h.qoms, moms, stream=stream)
             return
@@ -193,37 +199,67 @@ def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: 
         "sort_ms_per_species": sort_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": ("k_fused_tiled (mover) + k_deposit_tiled (lane-cell deposit), one pair per species"
-                                if launch.get("tile_variant") == 8 else "k_fused_tiled (one launch per species)"),
+                     "kernel": ("k_fused_tiled (mover) + k_deposit_tiled (sorted register deposit), one pair per "
+                                "species" if launch.get("tile_variant") == 2 else "k_fused_tiled (one launch per species)"),
                      "bytes_per_launch": per_launch_bytes, "avg_launch_ms": avg_launch_s * 1e3,
                      "traffic_bytes_per_launch": traffic_bytes},
     }
 
 
-def cpu_baseline(h, target_s: float = 12.0):
-    """The FP64 oracle on a bounded sample: a seeded 1/64 subsample of every
-    species of the same workload (full grid), stepped until ~target_s."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(h, reps: int = 5):
+    """The FP64 oracle (C, OpenMP; never tuned for this) timed on this host:
+    the 32x16x4 box in full (4 species x 27 ppc, 10 fused steps) and a
+    seeded 1/64 subsample (by particle-id hash) of every species of the
+    128x64x32 box on its full grid (one fused step), each on all host cores
+    and on one core, the median of `reps` runs.  `value` is the subsample on
+    all cores, in particle-steps/s (a fused step: mover + FP64 deposit)."""
     from oracle import oracle as O
-    f = W.make_fields(h)
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+
+    def timed(hh, f, species, nsteps, threads):
+        used = O.set_threads(threads)
+        n = sum(sp["x"].size for sp in species)
+        ts = []
+        for _ in range(reps):
+            states = species
+            t0 = time.perf_counter()
+            for _ in range(nsteps):
+                states = [O.step(hh.grid, hh.dt, hh.c, hh.niter, hh.qoms[s], f, states[s])[0]
+                          for s in range(len(states))]
+            ts.append(time.perf_counter() - t0)
+        med = float(np.median(ts))
+        return {"value": n * nsteps / med, "threads": used, "median_s": med, "particles": n, "steps": nsteps}
+
+    h1 = W.harris_32x16x4()
+    f1, sp1 = W.make_fields(h1), W.make_all_species(h1)
+    f2 = W.make_fields(h)
     subs = []
     for s in range(4):
         sp = W.make_species(h, s)
         m = W.subsample_mask(sp["id"], 64, seed=7)
         subs.append({k: v[m] for k, v in sp.items()})
         del sp
-    n = sum(s["x"].size for s in subs)
-    steps = 0
-    t0 = time.perf_counter()
-    states = subs
-    while True:
-        states = [O.step(h.grid, h.dt, h.c, h.niter, h.qoms[s], f, states[s])[0] for s in range(4)]
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= target_s or steps >= 40:
-            break
-    return {"value": n * steps / el, "unit": "particle-steps/s", "cores": O.max_threads(), "kind": "oracle",
-            "sample": "seeded 1/64 subsample by particle-id hash of all 4 species (%d particles) on the full "
-                      "128x64x32 grid, %d fused steps (mover + FP64 deposit), %.1f s" % (n, steps, el)}
+    runs = {}
+    for name, args in (("harris_32x16x4_full_10_steps", (h1, f1, sp1, 10)),
+                       ("harris_128x64x32_subsample_1_64_one_step", (h, f2, subs, 1))):
+        runs[name] = {"all_cores": timed(*args, nproc), "one_core": timed(*args, 1)}
+    O.set_threads(nproc)
+    head = runs["harris_128x64x32_subsample_1_64_one_step"]["all_cores"]
+    return {"value": head["value"], "unit": "particle-steps/s", "cores": head["threads"], "kind": "oracle",
+            "sample": "seeded 1/64 subsample by particle-id hash of all 4 species of the 128x64x32 box (%d "
+                      "particles) on its full grid, one fused step (mover + FP64 deposit), median of %d runs on "
+                      "all %d host cores" % (head["particles"], reps, head["threads"]),
+            "nproc": nproc, "cpu_model": _cpu_model(), "runs": runs}
 
 
 def _engine_ctx(budget=0, tuned_key=None, variant=-1):
@@ -419,6 +455,11 @@ def main():
     ap.add_argument("--option", action="append", default=[], metavar="KEY=VALUE",
                     help="set a library option on every context (repeatable), e.g. mover_cache=0")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-f32", action="store_true",
+                    help="time the FP64 path only (its line then carries the FP64 value and roofline)")
+    ap.add_argument("--mover-tol", type=float, default=0.0,
+                    help="tolerance-terminated mover iterations (niter_mover is then the cap)")
+    ap.add_argument("--niter", type=int, default=3, help="mover iterations (the cap with --mover-tol)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a plain 1 GiB device-to-device copy (reference for HBM counters)")
@@ -444,14 +485,15 @@ def main():
 
     h = W.harris_128x64x32()
     tune = args.tune and not args.no_tune
-    r32 = run_gpu(h, "f32", args.steps, args.warmup, args.sort_every, args.path, tune=tune,
-                  variant=args.variant)
-    log("[bench] f32: %.3e particle-steps/s, %.3f ms/step, %.1f%% HBM" %
-        (r32["value"], r32["ms_per_step"], 100 * r32["roofline"]["frac"]))
+    kw = dict(tune=tune, variant=args.variant, tol=args.mover_tol, niter=args.niter)
+    r32 = None
+    if not args.no_f32:
+        r32 = run_gpu(h, "f32", args.steps, args.warmup, args.sort_every, args.path, **kw)
+        log("[bench] f32: %.3e particle-steps/s, %.3f ms/step, %.1f%% HBM" %
+            (r32["value"], r32["ms_per_step"], 100 * r32["roofline"]["frac"]))
     r64 = None
     if not args.no_fp64:
-        r64 = run_gpu(h, "f64", args.steps, args.warmup, args.sort_every, args.path, tune=tune,
-                      variant=args.variant)
+        r64 = run_gpu(h, "f64", args.steps, args.warmup, args.sort_every, args.path, **kw)
         log("[bench] f64: %.3e particle-steps/s, %.3f ms/step, %.1f%% HBM" %
             (r64["value"], r64["ms_per_step"], 100 * r64["roofline"]["frac"]))
     cpu = None
@@ -459,34 +501,39 @@ def main():
         log("[bench] timing the CPU oracle on a bounded sample")
         cpu = cpu_baseline(h)
         log("[bench] cpu oracle: %.3e particle-steps/s on %d threads" % (cpu["value"], cpu["cores"]))
+    head = r32 if r32 is not None else r64
+    hname = "f32" if r32 is not None else "f64"
     out = {
         "metric": METRIC,
-        "value": r32["value"],
+        "value": head["value"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r32["ms_per_step"],
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": hname,
         "data": "synthetic",
         "config": {"workload": "harris_128x64x32_ppc64_4species", "cells": [128, 64, 32],
-                   "particles": h.n_total, "species": 4, "ppc": 64, "niter_mover": h.niter, "dt": h.dt,
-                   "precision": "f32 particles and mover, f64 moment accumulation",
-                   "sort_every": r32["sort_every"], "path": args.path or "auto", "launch": r32["launch"],
-                   "tuned": r32["tuned"]},
-        "roofline": r32["roofline"],
+                   "particles": h.n_total, "species": 4, "ppc": 64, "niter_mover": args.niter, "dt": h.dt,
+                   "mover_tol": args.mover_tol,
+                   "precision": PRECISION[hname],
+                   "sort_every": head["sort_every"], "path": args.path or "auto", "launch": head["launch"],
+                   "tuned": head["tuned"]},
+        "roofline": head["roofline"],
         "cpu_baseline": cpu,
-        "ms_per_step_stats": {k: r32[k] for k in ("ms_per_step_mean", "ms_per_step_std", "ms_per_step_median",
-                                                   "sort_ms_per_species")},
+        "ms_per_step_stats": {k: head[k] for k in ("ms_per_step_mean", "ms_per_step_std", "ms_per_step_median",
+                                                    "sort_ms_per_species")},
     }
-    if r64 is not None:
+    if r32 is not None and r64 is not None:
         out["fp64"] = {"value": r64["value"], "unit": "particle-steps/s", "dtype": "f64",
+                       "precision": PRECISION["f64"],
                        "ms_per_step": r64["ms_per_step"], "roofline": r64["roofline"], "launch": r64["launch"],
-                       "tuned": r64["tuned"],
-                       "sort_every": r64["sort_every"]}
+                       "tuned": r64["tuned"], "sort_every": r64["sort_every"],
+                       "ms_per_step_stats": {k: r64[k] for k in ("ms_per_step_mean", "ms_per_step_std",
+                                                                  "ms_per_step_median", "sort_ms_per_species")}}
     if args.copy_calibration:
         # 2^28 FP32 = 1 GiB read + 1 GiB written by one copy kernel
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")

@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define SPIC_ABI_VERSION 1
+#define SPIC_ABI_VERSION 2
 
 /* status codes */
 #define SPIC_OK             0
@@ -77,18 +77,27 @@ typedef struct {
 /* Time step and mover controls.
  *  dt           time step (Eq. 1, Eq. 2, Eq. 5)
  *  c            speed of light in the normalised units (Eq. 2); > 0
- *  niter_mover  predictor-corrector iterations (three in the paper); >= 1
+ *  niter_mover  predictor-corrector iterations (three in the paper); >= 1.
+ *               With mover_tol > 0 it is the cap on the iterations.
  *  sort_every   re-sort the particles by cell every sort_every steps
  *               (Sec. III-A, Sec. VI: sorting restores locality); 0 = never.
  *               Sorting permutes the particle arrays (and id, if given).
  *  step         the caller's step counter: a sort runs before the move when
- *               sort_every > 0 and step % sort_every == 0. */
+ *               sort_every > 0 and step % sort_every == 0.
+ *  mover_tol    0 (default): exactly niter_mover iterations.  > 0: the
+ *               iteration count is set by this error tolerance instead
+ *               (Sec. II, after Eq. 2): each particle stops after its k-th
+ *               iteration (k >= 2) once the change of its mean velocity over
+ *               that iteration, max over x, y, z of |vbar^k - vbar^(k-1)|,
+ *               is below mover_tol (velocity units), and after niter_mover
+ *               iterations at the latest.  Finite, >= 0. */
 typedef struct {
     double dt;
     double c;
     int32_t niter_mover;
     int32_t sort_every;
     int64_t step;
+    double mover_tol;
 } spic_params;
 
 /* Node-centred E and B (Sec. II, Eq. 4): six device arrays of `nodes`

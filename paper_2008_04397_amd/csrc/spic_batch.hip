@@ -452,8 +452,9 @@ struct BatchEngine {
         struct Combo {
             std::vector<unsigned char> jobs;
             std::vector<uint2> items;
-            size_t lds = 0, lds0 = 0;  // LDS with the configured variant, with variant 0
+            TileGeom tg{};             // the job tiling with the largest region
             int var = 0, var_cfg = -1, block = 512;
+            int dtype = SPIC_F32, acc = SPIC_F64;
         };
         std::map<int, Combo> combos;
         std::vector<void *> mptr[2];
@@ -478,8 +479,10 @@ struct BatchEngine {
                     rc.variant = variant;
                     rc.tile_block = tile_block;
                     rc = resolve_cfg(rc, sl.dev.dtype, acc);
-                    if (rc.variant == 8) rc.variant = 5;  // the split variant has no work-list form
                     c.var_cfg = rc.variant;
+                    c.dtype = sl.dev.dtype;
+                    c.acc = acc;
+                    c.tg = r.tg;
                     c.block = rc.tile_block;
                 }
                 const size_t jb = tile_job_bytes(sl.combo);
@@ -489,8 +492,7 @@ struct BatchEngine {
                 write_tile_job(sl.combo, c.jobs.data() + jidx * jb, r.grid, prm, r.fields, work_of(sl.dev, m), r.tg,
                                sl.tile_off);
                 for (int t = 0; t < r.tg.ntiles; ++t) c.items.push_back(make_uint2(jidx, (uint32_t)t));
-                c.lds = std::max(c.lds, tiled_lds_bytes(r.tg, sl.dev.dtype, acc, c.var_cfg, c.block));
-                c.lds0 = std::max(c.lds0, tiled_lds_bytes(r.tg, sl.dev.dtype, acc, 0, c.block));
+                if (r.tg.rnp > c.tg.rnp || r.tg.rx * r.tg.ry * r.tg.rz > c.tg.rx * c.tg.ry * c.tg.rz) c.tg = r.tg;
             }
         }
         // layout of the device table: [ptrs f64][cnt f64][ptrs f32][cnt f32][counters x16] then per launch key jobs, items
@@ -498,7 +500,7 @@ struct BatchEngine {
         auto reserve = [&](size_t b) { size_t o = off; off += (b + 255) & ~(size_t)255; return o; };
         const size_t o_p0 = reserve(mptr[0].size() * 8), o_c0 = reserve(mcnt[0].size() * 8);
         const size_t o_p1 = reserve(mptr[1].size() * 8), o_c1 = reserve(mcnt[1].size() * 8);
-        const size_t o_ctr = reserve(16 * 4);
+        const size_t o_ctr = reserve(32 * 4);  // two per launch key
         std::map<int, std::pair<size_t, size_t>> co;
         for (auto &kv : combos) {
             const size_t oj = reserve(kv.second.jobs.size());
@@ -522,7 +524,7 @@ struct BatchEngine {
         memcpy(h + o_c0, mcnt[0].data(), mcnt[0].size() * 8);
         memcpy(h + o_p1, mptr[1].data(), mptr[1].size() * 8);
         memcpy(h + o_c1, mcnt[1].data(), mcnt[1].size() * 8);
-        memset(h + o_ctr, 0, 32);
+        memset(h + o_ctr, 0, 32 * 4);
         for (auto &kv : combos) {
             memcpy(h + co[kv.first].first, kv.second.jobs.data(), kv.second.jobs.size());
             memcpy(h + co[kv.first].second, kv.second.items.data(), kv.second.items.size() * sizeof(uint2));
@@ -533,13 +535,12 @@ struct BatchEngine {
 
         // 3. the step itself (captured as a graph when enabled); launch sizes
         // are settled before the capture starts
-        std::map<int, int> groups;
+        std::map<int, WorklistGroups> groups;
         for (auto &kv : combos) {
-            // a variant whose extra LDS does not fit falls back to variant 0
+            // a variant whose LDS does not fit falls back to variant 0
             Combo &c = kv.second;
-            c.var = c.lds <= ctx->lds_max ? c.var_cfg : 0;
-            if (c.var != c.var_cfg) c.lds = c.lds0;
-            groups[kv.first] = worklist_groups(kv.first & 7, kv.first >= 8, c.var, c.lds, c.block,
+            c.var = tiled_lds_bytes(c.tg, c.dtype, c.acc, c.var_cfg, c.block) <= ctx->lds_max ? c.var_cfg : 0;
+            groups[kv.first] = worklist_groups(kv.first & 7, kv.first >= 8, c.var, c.tg, c.block,
                                                (int)c.items.size(), max_groups);
         }
         bool capturing = false;
@@ -549,13 +550,13 @@ struct BatchEngine {
             e = launch_fill_many((void *const *)(d + o_p0), (const int64_t *)(d + o_c0), (int)mptr[0].size(), 8, cs);
         if (e == hipSuccess && !mptr[1].empty())
             e = launch_fill_many((void *const *)(d + o_p1), (const int64_t *)(d + o_c1), (int)mptr[1].size(), 4, cs);
-        if (e == hipSuccess) e = launch_zero32(d + o_ctr, 16, cs);
+        if (e == hipSuccess) e = launch_zero32(d + o_ctr, 32, cs);
         int ci = 0;
         for (auto &kv : combos) {
             if (e != hipSuccess) break;
             e = launch_worklist(kv.first & 7, kv.first >= 8, kv.second.var, d + co[kv.first].first,
                                 (const uint2 *)(d + co[kv.first].second), (int)kv.second.items.size(),
-                                (unsigned *)(d + o_ctr) + ci++, kv.second.lds, kv.second.block, groups[kv.first], cs);
+                                (unsigned *)(d + o_ctr) + 2 * ci++, groups[kv.first], kv.second.block, cs);
         }
         if (capturing) {
             hipGraph_t g = nullptr;

@@ -115,7 +115,7 @@ __device__ __forceinline__ void gather_cell_global(const FieldPtrs<TF> &f, const
     for (int m = 0; m < 6; ++m) {
         T acc = T(0);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) acc += w[k] * (T)__ldg(f.f[m] + nd[k]);
+        for (int k = 0; k < 8; ++k) acc += w[k] * (T)f.f[m][nd[k]];
         out[m] = acc;
     }
 }
@@ -134,15 +134,21 @@ __device__ __forceinline__ void gather_global(const GridT<T> &g, const FieldPtrs
 //   vbar = (vt + vt x b + (vt . b) b) / (1 + b . b)       (Eq. 2)
 //   xbar = x^n + vbar dt/2
 // and finally v^{n+1} = 2 vbar - v^n, x^{n+1} = x^n + vbar dt (Eq. 5),
-// wrapped into the periodic box.  `gather(x, y, z, F)` evaluates Eq. 4 at a
-// point; the kernels differ only in where it reads the node fields.
+// wrapped into the periodic box.  With a tolerance (mv.tol > 0; the count
+// set by an error tolerance, Sec. II after Eq. 2) a particle stops after
+// iteration k >= 2 once max_d |vbar^k - vbar^(k-1)| < tol, at niter at the
+// latest (lanes leave the loop on their own).  `gather(x, y, z, F)`
+// evaluates Eq. 4 at a point; the kernels differ only in where it reads the
+// node fields.
 template <typename T, typename Gather>
 __device__ __forceinline__ void implicit_move(const GridT<T> &g, const MoveT<T> &mv, Gather &&gather, T &x, T &y,
                                               T &z, T &u, T &v, T &w) {
     const T x0 = x, y0 = y, z0 = z, u0 = u, v0 = v, w0 = w;
     T xb = x0, yb = y0, zb = z0;
     T ub = u0, vb = v0, wb = w0;
+    const bool use_tol = mv.tol > T(0);
     for (int it = 0; it < mv.niter; ++it) {
+        const T pu = ub, pv = vb, pw = wb;
         T F[6];
         gather(xb, yb, zb, F);
         const T ut = u0 + mv.beta * F[0];
@@ -157,6 +163,11 @@ __device__ __forceinline__ void implicit_move(const GridT<T> &g, const MoveT<T> 
         xb = x0 + ub * mv.hdt;
         yb = y0 + vb * mv.hdt;
         zb = z0 + wb * mv.hdt;
+        if (use_tol && it >= 1) {
+            const T d = __builtin_fmax(__builtin_fabs(ub - pu), __builtin_fmax(__builtin_fabs(vb - pv),
+                                                                               __builtin_fabs(wb - pw)));
+            if (d < mv.tol) break;
+        }
     }
     u = T(2) * ub - u0;
     v = T(2) * vb - v0;

@@ -32,22 +32,18 @@ std::string spic_ctx_s::layout_key(const spic_grid &g, const spic_species &s) co
 }
 
 // The bank-preserving layout pays off for FP32 particles; FP64 particles
-// keep the compact one (two workgroups per CU) unless bank_align is set.
-// The segmented-deposit variant wants cell-major order (its lanes share
-// cells, so no padding for bank spread either); the others rank-major.  The
-// two-phase variant deposits mostly from registers and takes the dense
-// layout (the smallest LDS footprint, more workgroups per CU).
-// Full rows pay off for the lane-cell variants (5-9: lane c keeps cell c's
-// moments); the LDS-atomic variants keep plain rank blocks, whose rows
-// never hold one cell twice.
+// keep the compact one (two workgroups per CU for the one-kernel variants)
+// unless bank_align is set.  Full rows for the split variant (the mover's
+// corner cache and the deposit's loads want lane c on cell c); the
+// LDS-atomic variants keep plain rank blocks, whose rows never hold one
+// cell twice.
 TileGeom spic_ctx_s::tile_geom(const spic_grid &g, int dtype) const {
     int var = (int)opt("tile_variant", -1);
     if (var < 0) var = auto_variant(dtype, SPIC_F64);
-    const bool cm = var == 4;
-    const int dflt = var == 6 ? 2 : (dtype == SPIC_F64 || cm) ? 0 : 1;
+    const int dflt = dtype == SPIC_F64 ? 0 : 1;
     return make_tile_geom(g, (int)opt("tile_x", 4), (int)opt("tile_y", 4), (int)opt("tile_z", 4),
-                          (int)opt("halo", 1), (int)opt("bank_align", dflt), cm,
-                          opt("sort_rows", var >= 5 ? 1 : 0) != 0);
+                          (int)opt("halo", 1), (int)opt("bank_align", dflt),
+                          opt("sort_rows", var == kVariantSplit ? 1 : 0) != 0);
 }
 
 

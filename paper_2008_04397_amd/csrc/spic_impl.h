@@ -20,10 +20,11 @@ struct GridT {
 };
 
 // Mover constants in T: beta = qom*dt/2 (Eq. 1), bc = beta/c (Eq. 2),
-// dt and dt/2 (Eq. 5 and the half-step position).
+// dt and dt/2 (Eq. 5 and the half-step position); niter iterations, or at
+// most niter with a tolerance tol > 0 on the change of the mean velocity.
 template <typename T>
 struct MoveT {
-    T beta, bc, dt, hdt;
+    T beta, bc, dt, hdt, tol;
     int niter, pad;
 };
 
@@ -58,20 +59,24 @@ struct LaunchCfg {
     int block = 256;        // generic kernels
     int grid_cap = 1 << 20;
     int tile_block = -1;    // tiled fused kernel (-1: by variant)
-    int variant = -1;       // tiled kernel variant (see spic_tiled.hip; -1: by precision)
+    int variant = -1;       // tiled kernel variant (0, 1, 2; see spic_tiled.hip; -1: 2)
     int fixed_geo = 1;      // compile-time region geometry for the default tiling
-    int mover_halo = -1;    // split variant: halo of the mover's field region (-1: tile halo + 1)
-    int mover_cache = 1;    // split variant: the mover keeps the last cell's field corners in registers
+    int mover_halo = -1;    // variant 2: halo of the mover's field region (-1: tile halo + 1)
+    int mover_cache = 1;    // variant 2: the mover keeps the last cell's field corners in registers
     size_t lds_max = 65536; // LDS bytes a workgroup may use on the device
 };
 
-// Tiled-kernel variant and workgroup size when the options leave them to
-// the library: FP32 particles with FP64 moments take the split launch
-// (mover, then the lane-cell register deposit at 256 threads; measured
-// fastest on the Harris boxes), every other precision combination the
-// LDS-atomic deposit at 512.
-inline int auto_variant(int dtype, int acc_dtype) { return (dtype == SPIC_F32 && acc_dtype == SPIC_F64) ? 8 : 0; }
-inline int auto_tile_block(int variant) { return variant >= 5 ? 256 : 512; }
+// Tiled-kernel variants (spic_tiled.hip): 0 one kernel with LDS-atomic
+// deposits, 1 the same with the field corners of a thread's last cell in
+// registers, 2 two launches -- the mover, then the sorted deposit into
+// per-lane register sums.  Defaults, measured fastest on the Harris boxes:
+// 2 for FP32 particles, 0 for FP64 (its 80 register sums take 160 VGPRs,
+// which leaves the deposit two waves per SIMD and spills).  Workgroup size
+// when the options leave it to the library: 256 for the sorted deposit,
+// 512 for the one-kernel forms.
+constexpr int kVariantSplit = 2;
+inline int auto_variant(int dtype, int) { return dtype == SPIC_F32 ? kVariantSplit : 0; }
+inline int auto_tile_block(int variant) { return variant == kVariantSplit ? 256 : 512; }
 inline LaunchCfg resolve_cfg(LaunchCfg c, int dtype, int acc_dtype) {
     if (c.variant < 0) c.variant = auto_variant(dtype, acc_dtype);
     if (c.tile_block < 0) c.tile_block = auto_tile_block(c.variant);
@@ -91,18 +96,15 @@ struct TileGeom {
     // region coordinates (a, b, c) is a*sx + b*sy + c*sz.
     int slow, mid, fast;
     int sx, sy, sz, rnp;  // slot strides and slots (padded for bank spread)
-    // Order of a tile's particles after a sort: 0 rank-major (rank 0 of
-    // every cell, then rank 1, ...: a wave's lanes in distinct cells), 1
-    // cell-major (all particles of cell 0, then cell 1, ...: a wave's lanes
-    // mostly in one cell, for the segmented deposit).  rows (rank-major
-    // only): 1 = full rows -- a tile of n particles and C cells has
-    // R = n / C rows in which slot (r, c) holds rank r of cell c whenever
-    // cell c has more than r particles; the particles of ranks >= R fill the
-    // remaining slots of those rows, then a last partial row -- so lane c
-    // holds cell c for all but a few particles even when the cell counts
-    // differ; 0 = plain rank blocks (a rank's block holds only the cells
-    // that have that rank).
-    int cellmajor, rows;
+    // Order of a tile's particles after a sort (rank-major): rows = 1, full
+    // rows -- a tile of n particles and C cells has R = n / C rows in which
+    // slot (r, c) holds rank r of cell c whenever cell c has more than r
+    // particles; the particles of ranks >= R fill the remaining slots of
+    // those rows, then a last partial row -- so lane c of a row holds cell c
+    // for all but a few particles even when the cell counts differ; rows =
+    // 0, plain rank blocks (a rank's block holds only the cells that have
+    // that rank, so a row never holds one cell twice).
+    int rows;
 };
 
 // LDS bank spread of a region layout.  A wave deposits with one lane per
@@ -238,6 +240,7 @@ inline MoveT<T> make_move(const spic_params &p, double qom) {
     m.bc = (T)(beta / p.c);
     m.dt = (T)p.dt;
     m.hdt = (T)(p.dt / 2.0);
+    m.tol = (T)p.mover_tol;
     m.niter = p.niter_mover;
     m.pad = 0;
     return m;
@@ -317,8 +320,7 @@ hipError_t launch_deposit_generic(const spic_grid &g, const SpeciesWork &w, cons
                                   hipStream_t s);
 
 // Sort (spic_sort.hip).
-TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo, int layout = 1,
-                        bool cellmajor = false, bool rows = true);
+TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo, int layout = 1, bool rows = true);
 size_t sort_scratch_bytes(int64_t n, int dtype, bool with_id, const TileGeom &tg);
 // prev: tile_off already holds the per-tile ranges of the particles'
 // current order (an earlier sort with the same tiles and n); the key pass
@@ -330,13 +332,13 @@ hipError_t launch_sort(const spic_grid &g, const SpeciesWork &w, const TileGeom 
                        uint32_t *tile_off, bool prev, hipStream_t s, SpeciesWork *sorted_out = nullptr);
 inline bool same_tiling(const TileGeom &a, const TileGeom &b) {
     return a.tx == b.tx && a.ty == b.ty && a.tz == b.tz && a.ntx == b.ntx && a.nty == b.nty && a.ntz == b.ntz &&
-           a.slow == b.slow && a.mid == b.mid && a.fast == b.fast && a.cellmajor == b.cellmajor;
+           a.slow == b.slow && a.mid == b.mid && a.fast == b.fast && a.rows == b.rows;
 }
 
-// Tiled fused path (spic_tiled.hip): one workgroup per tile of a sorted
-// species, fields and moments of the tile region staged in LDS.
-// LDS bytes of one workgroup of the tiled kernel (variant and block size
-// matter: variant 2 adds per-wave queues).
+// Tiled path (spic_tiled.hip): one workgroup per tile of a sorted species,
+// fields and moments of the tile region staged in LDS.  LDS bytes of one
+// workgroup (for variant 2 the larger of its two launches at the tile's
+// halo).
 size_t tiled_lds_bytes(const TileGeom &tg, int dtype, int acc_dtype, int variant, int block);
 hipError_t launch_fused_tiled(const spic_grid &g, const spic_params &prm, const spic_fields &f,
                               const SpeciesWork &w, const TileGeom &tg, const uint32_t *tile_off,
@@ -345,14 +347,25 @@ hipError_t launch_fused_tiled(const spic_grid &g, const spic_params &prm, const 
 // Work lists (spic_tiled.hip).  combo: 0 f64/f64/f64, 1 f32/f32/f64,
 // 2 f32/f32/f32, 3 f32/f64/f64, 4 f32/f64/f32 (particles/fields/moments);
 // -1 for an unsupported combination.  fixed: every job of the launch uses
-// the default tiling (GeoDefault) and the kernel compiled for it.
+// the default tiling (GeoDefault) and the kernels compiled for it.
 int job_combo(int dtype, int fdtype, int acc_dtype);
 size_t tile_job_bytes(int combo);
 void write_tile_job(int combo, void *dst, const spic_grid &g, const spic_params &prm, const spic_fields &f,
                     const SpeciesWork &w, const TileGeom &tg, const uint32_t *tile_off);
-int worklist_groups(int combo, bool fixed, int variant, size_t lds, int block, int nitems, int max_groups);
+// Launch sizes of one combination's persistent launches: variant 2 runs a
+// mover list (512 threads, fields) and then a deposit list (`block`
+// threads); variants 0 and 1 one list (`block` threads, `mover` fields).
+struct WorklistGroups {
+    int mover, deposit;
+    size_t lds_mover, lds_deposit;
+};
+// tg: the largest region of the launch's jobs.  Also allows the LDS sizes;
+// call before any stream capture.
+WorklistGroups worklist_groups(int combo, bool fixed, int variant, const TileGeom &tg, int block, int nitems,
+                               int max_groups);
+// counters: two zeroed counters (variant 2 uses both).
 hipError_t launch_worklist(int combo, bool fixed, int variant, const void *jobs, const uint2 *items, int nitems,
-                           unsigned *counter, size_t lds, int block, int groups, hipStream_t s);
+                           unsigned *counters, const WorklistGroups &gr, int block, hipStream_t s);
 hipError_t launch_fill_many(void *const *ptrs, const int64_t *counts, int narr, int elem_bytes, hipStream_t s);
 
 }  // namespace spic

@@ -76,6 +76,8 @@ int spic_ctx_s::check_params(const spic_params *p) {
     if (!std::isfinite(p->dt)) return fail(SPIC_E_ARG, "dt must be finite");
     if (!(p->c > 0) || !std::isfinite(p->c)) return fail(SPIC_E_ARG, "c must be finite and > 0");
     if (p->niter_mover < 1 || p->niter_mover > 1000) return fail(SPIC_E_ARG, "niter_mover must be in [1, 1000]");
+    if (!(p->mover_tol >= 0) || !std::isfinite(p->mover_tol))
+        return fail(SPIC_E_ARG, "mover_tol must be finite and >= 0");
     if (p->sort_every < 0) return fail(SPIC_E_ARG, "sort_every must be >= 0");
     if (p->step < 0) return fail(SPIC_E_ARG, "step must be >= 0");
     return SPIC_OK;
@@ -184,16 +186,16 @@ static const char *const kOptionNames[] = {
     "block",        // threads per block of the generic kernels
     "grid_cap",     // cap on blocks of the grid-stride kernels
     "path",         // 0 auto (tiled for sorted species), 1 generic only
-    "tile_block",   // threads per block of the tiled fused kernel
+    "tile_block",   // threads per block of the tiled kernel (variant 2: of the deposit launch)
     "tile_x", "tile_y", "tile_z",  // sort tile shape in cells (product <= 64)
     "halo",         // cells of halo staged around a tile
     "lds_max",      // read only: LDS bytes per workgroup on the device
-    "tile_variant", // tiled kernel: 0 LDS atomics, 1 + field corners in registers, 2 home-cell registers,
-                    // 3 bank-balanced LDS deposit, 4 segmented wave pre-reduction (cell-major order)
+    "tile_variant", // tiled kernel: 0 one kernel with LDS-atomic deposits, 1 + field corners in registers,
+                    // 2 mover launch then the sorted register deposit (default)
     "fixed_geo",    // tiled kernel: 1 = compile-time region geometry for 4x4x4 tiles, halo 1
     "sort_ordered", // sort: 1 = ranks follow the previous order (a sorted species' tiles walked in order)
     "sort_rows",    // sort: 1 = full rows (lane = cell for all but a few particles), 0 = plain rank blocks
-                    // (default: 1 for the lane-cell variants 5-9)
+                    // (default: 1 for variant 2)
     "bank_align",   // tiled kernel LDS layout: 0 compact conflict-free, 1 + slow-axis stride keeps bank pairs,
                     // 2 dense (no padding)
     "graph",        // batch engine: 1 = replay unchanged ticks as a hipGraph
@@ -201,8 +203,8 @@ static const char *const kOptionNames[] = {
     "max_groups",   // batch engine: cap on workgroups of the persistent launch (0 = occupancy)
     "tick_items",   // batch engine: (job, tile) items per tick, shortest runs first (0 = all runs)
     "srpt_aging",   // batch engine: credit, in M particle-steps per second waited, against starvation
-    "mover_halo",   // split tiled variant: halo of the mover's field region (-1: tile halo + 1)
-    "mover_cache",  // split tiled variant: 1 = the mover keeps the last cell's field corners in registers
+    "mover_halo",   // variant 2: halo of the mover's field region (-1: tile halo + 1)
+    "mover_cache",  // variant 2: 1 = the mover keeps the last cell's field corners in registers
 };
 
 int64_t spic_ctx_s::opt(const char *k, int64_t dflt) const {
@@ -292,8 +294,8 @@ int spic_set_option(spic_ctx ctx, const char *key, int64_t value) {
             if ((!strcmp(key, "tile_x") || !strcmp(key, "tile_y") || !strcmp(key, "tile_z")) &&
                 (value < 1 || value > 64))
                 return ctx->fail(SPIC_E_ARG, "tile sizes must be in [1, 64]");
-            if (!strcmp(key, "tile_variant") && (value < -1 || value > 9))
-                return ctx->fail(SPIC_E_ARG, "tile_variant must be -1 or in 0..9");
+            if (!strcmp(key, "tile_variant") && (value < -1 || value > 2))
+                return ctx->fail(SPIC_E_ARG, "tile_variant must be -1 or in 0..2");
             if (!strcmp(key, "batch_particles") && (value < 1024 || value > ((int64_t)1 << 29)))
                 return ctx->fail(SPIC_E_ARG, "batch_particles must be in [1024, 2^29]");
             if (!strcmp(key, "tick_items") && (value < 0 || value > ((int64_t)1 << 30)))
@@ -320,6 +322,24 @@ int spic_set_option(spic_ctx ctx, const char *key, int64_t value) {
 int spic_get_option(spic_ctx ctx, const char *key, int64_t *value) {
     if (!ctx || !key || !value) return SPIC_E_ARG;
     std::lock_guard<std::mutex> lk(ctx->mu);
+    // "f32:<name>" / "f64:<name>": the setting the library resolves for
+    // particles of that precision with FP64 moments
+    if ((!strncmp(key, "f32:", 4) || !strncmp(key, "f64:", 4)) && key[4]) {
+        const int dt = key[2] == '2' ? SPIC_F32 : SPIC_F64;
+        const char *k = key + 4;
+        const LaunchCfg c = resolve_cfg(ctx->launch_cfg(), dt, SPIC_F64);
+        const TileGeom tg = ctx->tile_geom(spic_grid{8, 8, 8, 0, 1.0, 1.0, 1.0}, dt);
+        if (!strcmp(k, "tile_variant")) *value = c.variant;
+        else if (!strcmp(k, "tile_block")) *value = c.tile_block;
+        else if (!strcmp(k, "sort_rows")) *value = tg.rows;
+        else if (!strcmp(k, "halo")) *value = tg.halo;
+        else if (!strcmp(k, "bank_align")) *value = ctx->opt("bank_align", dt == SPIC_F64 ? 0 : 1);
+        else if (!strcmp(k, "sort_ordered")) *value = ctx->opt("sort_ordered", 1);
+        else if (!strcmp(k, "mover_cache")) *value = c.mover_cache;
+        else if (!strcmp(k, "mover_halo")) *value = c.mover_halo >= 0 ? c.mover_halo : tg.halo + 1;
+        else return ctx->fail(SPIC_E_ARG, "unknown resolved setting '%s'", key);
+        return SPIC_OK;
+    }
     for (const char *k : kOptionNames)
         if (!strcmp(k, key)) {
             *value = !strcmp(key, "lds_max") ? (int64_t)ctx->lds_max : ctx->opt(key, -1);

@@ -359,18 +359,6 @@ k_sort_slots_rows(int64_t n, const uint2 *__restrict__ keyrank, const uint32_t *
     }
 }
 
-// Cell-major slot of every particle: all particles of a cell together, in
-// rank order.
-__global__ void __launch_bounds__(256)
-k_sort_slots_cm(int64_t n, const uint2 *__restrict__ keyrank, const uint32_t *__restrict__ offsets,
-                const uint32_t *__restrict__ own, uint32_t *__restrict__ srcidx) {
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
-        const uint2 kr = keyrank[p];
-        const uint32_t rank = (own && (kr.y & kImmigrant)) ? own[kr.x] + (kr.y & ~kImmigrant) : kr.y;
-        srcidx[offsets[kr.x] + rank] = (uint32_t)p;
-    }
-}
-
 // Gather the particles into slot order: writes are coalesced; the reads
 // are scattered over the tile's earlier range and its neighbours' (L2
 // resident) wherever particles changed cell since the last sort.
@@ -557,7 +545,7 @@ __global__ void k_tile_offsets(const uint32_t *__restrict__ offsets, TileGeom tg
 
 // ------------------------------------------------------------------ host
 
-TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo, int layout, bool cellmajor, bool rows) {
+TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo, int layout, bool rows) {
     TileGeom t;
     t.tx = tx; t.ty = ty; t.tz = tz;
     t.cells = tx * ty * tz;
@@ -583,8 +571,7 @@ TileGeom make_tile_geom(const spic_grid &g, int tx, int ty, int tz, int halo, in
     t.sy = lay.sy;
     t.sz = lay.sz;
     t.rnp = lay.rnp;
-    t.cellmajor = cellmajor ? 1 : 0;
-    t.rows = (rows && !cellmajor) ? 1 : 0;
+    t.rows = rows ? 1 : 0;
     return t;
 }
 
@@ -661,10 +648,7 @@ static hipError_t sort_t(const spic_grid &g, const SpeciesWork &w, const TileGeo
     hipLaunchKernelGGL(k_scan_partials, dim3(nparts), dim3(SCAN_BLOCK), 0, s, counts, nkeys, partial);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, partial, nparts);
     hipLaunchKernelGGL(k_scan_apply, dim3(nparts), dim3(SCAN_BLOCK), 0, s, counts, nkeys, partial, offsets);
-    if (tg.cellmajor) {
-        hipLaunchKernelGGL(k_sort_slots_cm, dim3(gp > 0 ? gp : 1), dim3(256), 0, s, n, keyrank, offsets,
-                           prev ? (const uint32_t *)own : nullptr, srcidx);
-    } else if (tg.rows) {
+    if (tg.rows) {
         hipLaunchKernelGGL(k_tile_rows, dim3(tg.ntiles), dim3(64), 0, s, offsets, tg, hx, rh);
         hipLaunchKernelGGL(k_sort_slots_rows, dim3(gp > 0 ? gp : 1), dim3(256), 0, s, n, keyrank, offsets, hx, rh,
                            tg.cells, prev ? (const uint32_t *)own : nullptr, srcidx);

@@ -39,7 +39,7 @@ class spic_grid(C.Structure):
 
 class spic_params(C.Structure):
     _fields_ = [("dt", C.c_double), ("c", C.c_double), ("niter_mover", C.c_int32), ("sort_every", C.c_int32),
-                ("step", C.c_int64)]
+                ("step", C.c_int64), ("mover_tol", C.c_double)]
 
 
 class spic_fields(C.Structure):
@@ -129,8 +129,10 @@ def make_grid(g) -> spic_grid:
     return spic_grid(int(g.nx), int(g.ny), int(g.nz), 0, float(g.Lx), float(g.Ly), float(g.Lz))
 
 
-def make_params(dt: float, c: float = 1.0, niter: int = 3, sort_every: int = 0, step: int = 0) -> spic_params:
-    return spic_params(float(dt), float(c), int(niter), int(sort_every), int(step))
+def make_params(dt: float, c: float = 1.0, niter: int = 3, sort_every: int = 0, step: int = 0,
+                tol: float = 0.0) -> spic_params:
+    """tol > 0: tolerance-terminated mover iterations, niter the cap."""
+    return spic_params(float(dt), float(c), int(niter), int(sort_every), int(step), float(tol))
 
 
 def make_fields(f: Dict[str, "object"]) -> spic_fields:
@@ -257,27 +259,13 @@ def spic_poll(ctx: Context, ticket: int) -> bool:
     return bool(done.value)
 
 
-def resolved_launch(ctx: Context, dtype: str, acc: str = "f64") -> Dict[str, int]:
-    """The tiled-kernel launch settings the library uses for species of the
-    given particle and moment precision ("f32"/"f64"): options left at -1
-    resolve as the library resolves them (variant 8 -- mover, then the
-    lane-cell deposit at 256 threads -- for FP32 particles with FP64
-    moments, otherwise variant 0 at 512; layout 1 for FP32 particles, 0 for
-    FP64, 2 for the two-phase variant; full sort rows for variants 5-9)."""
-    var = ctx.get_option("tile_variant")
-    if var < 0:
-        var = 8 if (dtype == "f32" and acc == "f64") else 0
-    blk = ctx.get_option("tile_block")
-    if blk < 0:
-        blk = 256 if var >= 5 else 512
-    al = ctx.get_option("bank_align")
-    if al < 0:
-        al = 2 if var == 6 else (0 if (dtype == "f64" or var == 4) else 1)
-    so = ctx.get_option("sort_ordered")
-    rows = ctx.get_option("sort_rows")
-    halo = ctx.get_option("halo")
-    return {"tile_variant": var, "tile_block": blk, "bank_align": al, "sort_ordered": 1 if so < 0 else so,
-            "sort_rows": (1 if var >= 5 else 0) if rows < 0 else rows, "halo": 1 if halo < 0 else halo}
+def resolved_launch(ctx: Context, dtype: str) -> Dict[str, int]:
+    """The tiled-kernel launch settings the library resolves for particles of
+    the given precision ("f32"/"f64") with FP64 moments (read-only option
+    keys "f32:<name>" / "f64:<name>"; no resolution logic here)."""
+    keys = ("tile_variant", "tile_block", "bank_align", "sort_ordered", "sort_rows", "halo", "mover_cache",
+            "mover_halo")
+    return {k: ctx.get_option("%s:%s" % (dtype, k)) for k in keys}
 
 
 # --------------------------------------------------------- tensor helpers

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_version_and_status_strings():
-    assert spic.spic_version() == 1
+    assert spic.spic_version() == 2
     assert spic.spic_status_str(0) == "SPIC_OK"
     assert spic.spic_status_str(-2) == "SPIC_E_BUDGET"
     assert spic.spic_status_str(-99) == "SPIC_E_UNKNOWN"
@@ -86,6 +86,9 @@ def test_valid_arguments_reach_the_host_only_stop(hctx):
     ("c<=0", lambda g, p, f, s, m: setattr(p, "c", 0.0), spic.SPIC_E_ARG),
     ("dt nan", lambda g, p, f, s, m: setattr(p, "dt", float("nan")), spic.SPIC_E_ARG),
     ("sort<0", lambda g, p, f, s, m: setattr(p, "sort_every", -1), spic.SPIC_E_ARG),
+    ("tol<0", lambda g, p, f, s, m: setattr(p, "mover_tol", -1e-6), spic.SPIC_E_ARG),
+    ("tol nan", lambda g, p, f, s, m: setattr(p, "mover_tol", float("nan")), spic.SPIC_E_ARG),
+    ("tol inf", lambda g, p, f, s, m: setattr(p, "mover_tol", float("inf")), spic.SPIC_E_ARG),
     ("n<0", lambda g, p, f, s, m: setattr(s, "n", -1), spic.SPIC_E_ARG),
     ("null x", lambda g, p, f, s, m: setattr(s, "x", None), spic.SPIC_E_ARG),
     ("misaligned", lambda g, p, f, s, m: setattr(s, "u", s.u + 4), spic.SPIC_E_ARG),
@@ -122,6 +125,29 @@ def test_options(hctx):
     hctx.set_option("mover_cache", 0)
     with pytest.raises(spic.SpicError):
         hctx.set_option("mover_cache", 2)
+    for bad in (-2, 3):
+        with pytest.raises(spic.SpicError):
+            hctx.set_option("tile_variant", bad)
+
+
+def test_resolved_launch_comes_from_the_library(hctx):
+    """Options left unset resolve inside the library (FP32 particles: the
+    split variant, full rows, 256 deposit threads, the bank-preserving
+    layout; FP64: the one-kernel LDS-atomic variant at 512 threads, plain
+    rank blocks, the compact layout); the binding only reads the resolved
+    values."""
+    f32, f64 = spic.resolved_launch(hctx, "f32"), spic.resolved_launch(hctx, "f64")
+    assert f32["tile_variant"] == 2 and f64["tile_variant"] == 0
+    assert f32["tile_block"] == 256 and f32["sort_rows"] == 1 and f32["halo"] == 1
+    assert f64["tile_block"] == 512 and f64["sort_rows"] == 0
+    assert f32["bank_align"] == 1 and f64["bank_align"] == 0 and f32["mover_halo"] == 2
+    hctx.set_option("tile_variant", 0)
+    r = spic.resolved_launch(hctx, "f32")
+    assert r["tile_variant"] == 0 and r["tile_block"] == 512 and r["sort_rows"] == 0
+    hctx.set_option("tile_block", 128)
+    assert spic.resolved_launch(hctx, "f64")["tile_block"] == 128
+    with pytest.raises(spic.SpicError):
+        hctx.get_option("f32:no_such_setting")
 
 
 def test_python_binding_refuses_to_run_without_the_library(monkeypatch, tmp_path):
@@ -172,7 +198,7 @@ def test_autotune_cache_roundtrip(tmp_path, monkeypatch):
     assert autotune.load(key) is None
     autotune.store(key, dict(autotune.DEFAULT))
     assert autotune.load(key) == autotune.DEFAULT
-    assert len(list(autotune.candidates(quick=True))) == 24
+    assert len(list(autotune.candidates(quick=True))) == 12
 
 
 def test_serving_summary_statistics():
