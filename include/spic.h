@@ -250,6 +250,36 @@ int spic_moments(spic_ctx ctx, const spic_grid *grid, const spic_species *sp, in
 int spic_sort(spic_ctx ctx, const spic_grid *grid, spic_species *sp, int32_t nsp,
               void *hip_stream);
 
+/* Bytes of device memory spic_mover_noalloc's fixed scratch holds on each
+ * GPU the library runs on (from the first context on that GPU until the
+ * process ends). */
+#define SPIC_NOALLOC_SCRATCH_BYTES (256u * 1024u * 1024u)
+
+/* For callers that cannot allocate device memory: code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  One
+ * fused step (spic_mover) with a sort of every species before its move:
+ * params->sort_every must be 1, and the particles end up permuted into
+ * sorted order (id with them, when given), as spic_mover leaves them with
+ * sort_every = 1.  All scratch -- sort keys, ranks and slot indices, the
+ * reordered copy of the particles, per-tile particle ranges -- lives in one
+ * fixed array of SPIC_NOALLOC_SCRATCH_BYTES per GPU instead of memory the
+ * library allocates; the call makes no hipMalloc, hipFree or other
+ * allocating call.  The caller passes and owns the particles, fields and
+ * moments as for spic_mover.
+ *  - A species whose sort needs more scratch than the array holds (about
+ *    4 million FP32 particles with ids) is refused with SPIC_E_BUDGET
+ *    before anything is enqueued.
+ *  - Every call on one GPU, from any context, shares that GPU's array and
+ *    finds the last call's contents in it (nothing is carried over; each
+ *    call clears what it uses).  Calls that overlap on one GPU (two
+ *    streams, threads or contexts) race on the array: serialise them.
+ *  - The sort layout an earlier spic_sort or spic_mover kept for a species
+ *    is dropped (its particles were reordered).
+ * Errors: as spic_mover, plus SPIC_E_ARG for sort_every != 1. */
+int spic_mover_noalloc(spic_ctx ctx, const spic_grid *grid, const spic_params *params,
+                       const spic_fields *fields, spic_species *sp, int32_t nsp,
+                       spic_moment_array *mom, void *hip_stream);
+
 /* ---------------------------------------------------------------- batches */
 
 /* Submit nruns independent multi-step runs (Sec. III-B, particle batching).

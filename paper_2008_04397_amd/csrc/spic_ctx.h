@@ -34,6 +34,11 @@ struct RunPlan {
 // particles do not fit.
 int64_t stream_batch_size(uint64_t budget, int64_t max_batch, int dtype, bool with_id, const TileGeom &tg,
                           const int64_t *n, int nsp);
+
+// Device address of spic_mover_noalloc's fixed scratch on `device` (which
+// must be current), looked up once per device (spic_noalloc.hip); NULL with
+// *err set when the lookup fails.
+void *noalloc_scratch(int device, hipError_t *err);
 }
 
 struct spic_ctx_s {
@@ -92,6 +97,10 @@ struct spic_ctx_s {
     int moments(const spic_grid &g, const spic_species *sp, int32_t nsp, spic_moment_array *mom, bool accumulate,
                 hipStream_t s);
     int sort(const spic_grid &g, spic_species *sp, int32_t nsp, hipStream_t s);
+    // spic_mover_noalloc (spic_noalloc.hip): the sizes (host only), then the step
+    int noalloc_check(const spic_grid &g, const spic_species *sp, int32_t nsp, const spic_moment_array *mom);
+    int mover_noalloc(const spic_grid &g, const spic_params &p, const spic_fields &f, spic_species *sp,
+                      int32_t nsp, spic_moment_array *mom, hipStream_t s);
     int sort_prepare(const spic_grid &g, const spic_species *sp, int32_t nsp, size_t &need);
     int sort_one(const spic_grid &g, const spic_species &sp, const spic::TileGeom &tg, size_t need, hipStream_t s,
                  uint32_t **toff_out, spic::SpeciesWork *sorted_out);

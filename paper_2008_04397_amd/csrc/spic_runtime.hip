@@ -259,6 +259,12 @@ int spic_ctx_create(int device, uint64_t hbm_budget_bytes, spic_ctx *out) {
         int v = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && v > 0)
             c->lds_max = (size_t)v;
+        // set-up of spic_mover_noalloc: the device address of its fixed
+        // scratch on this device, looked up once per device with it current
+        // (a failure surfaces at that entry point's call)
+        DeviceGuard dg(device);
+        hipError_t e;
+        (void)spic::noalloc_scratch(device, &e);
     }
     *out = c;
     return SPIC_OK;
@@ -361,6 +367,24 @@ int spic_mover(spic_ctx ctx, const spic_grid *grid, const spic_params *params, c
     if (ctx->device < 0) return ctx->host_only();
     DeviceGuard dg(ctx->device);
     return ctx->mover(*grid, *params, *fields, sp, nsp, mom, (hipStream_t)hip_stream);
+}
+
+int spic_mover_noalloc(spic_ctx ctx, const spic_grid *grid, const spic_params *params, const spic_fields *fields,
+                       spic_species *sp, int32_t nsp, spic_moment_array *mom, void *hip_stream) {
+    if (!ctx) return SPIC_E_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->err.clear();
+    int rc;
+    if ((rc = ctx->check_grid(grid)) || (rc = ctx->check_params(params)) || (rc = ctx->check_fields(fields)) ||
+        (rc = ctx->check_species(sp, nsp, false)) || (rc = ctx->check_moments(mom, sp, nsp)) ||
+        (rc = ctx->check_combo(fields, sp, nsp)))
+        return rc;
+    if (params->sort_every != 1)
+        return ctx->fail(SPIC_E_ARG, "spic_mover_noalloc sorts every species before its move: sort_every must be 1");
+    if ((rc = ctx->noalloc_check(*grid, sp, nsp, mom))) return rc;
+    if (ctx->device < 0) return ctx->host_only();
+    DeviceGuard dg(ctx->device);
+    return ctx->mover_noalloc(*grid, *params, *fields, sp, nsp, mom, (hipStream_t)hip_stream);
 }
 
 int spic_moments(spic_ctx ctx, const spic_grid *grid, const spic_species *sp, int32_t nsp, spic_moment_array *mom,

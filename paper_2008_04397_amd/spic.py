@@ -22,7 +22,7 @@ SPIC_F32, SPIC_F64 = 1, 2
 
 EXPORTED = ("spic_ctx_create", "spic_ctx_destroy", "spic_last_error", "spic_status_str", "spic_version",
             "spic_set_option", "spic_get_option", "spic_mover", "spic_moments", "spic_sort",
-            "spic_batch_submit", "spic_wait", "spic_poll")
+            "spic_batch_submit", "spic_wait", "spic_poll", "spic_mover_noalloc")
 
 
 class SpicError(RuntimeError):
@@ -85,6 +85,7 @@ def lib():
         L.spic_get_option.argtypes = [vp, C.c_char_p, C.POINTER(C.c_int64)]
         L.spic_mover.argtypes = [vp, C.POINTER(spic_grid), C.POINTER(spic_params), C.POINTER(spic_fields),
                                  C.POINTER(spic_species), C.c_int32, C.POINTER(spic_moment_array), vp]
+        L.spic_mover_noalloc.argtypes = L.spic_mover.argtypes
         L.spic_moments.argtypes = [vp, C.POINTER(spic_grid), C.POINTER(spic_species), C.c_int32,
                                    C.POINTER(spic_moment_array), C.c_int32, vp]
         L.spic_sort.argtypes = [vp, C.POINTER(spic_grid), C.POINTER(spic_species), C.c_int32, vp]
@@ -233,6 +234,20 @@ def spic_mover(ctx: Context, grid, params: spic_params, fields, species: Sequenc
     mom = _arr(spic_moment_array, [make_moments(m) for m in moments]) if moments is not None else None
     st = lib().spic_mover(ctx.handle, C.byref(g), C.byref(params), C.byref(f), sp, len(species), mom,
                           _stream(stream))
+    return st if raw else ctx.check(st)
+
+
+def spic_mover_noalloc(ctx: Context, grid, params: spic_params, fields, species: Sequence[dict],
+                       qoms: Sequence[float], moments: Optional[Sequence] = None, stream=None,
+                       raw: bool = False) -> int:
+    """spic_mover with a sort of every species before its move (sort_every
+    must be 1), all scratch in the library's fixed per-GPU array."""
+    g = make_grid(grid)
+    f = make_fields(fields)
+    sp = _arr(spic_species, [make_species(s, q) for s, q in zip(species, qoms)])
+    mom = _arr(spic_moment_array, [make_moments(m) for m in moments]) if moments is not None else None
+    st = lib().spic_mover_noalloc(ctx.handle, C.byref(g), C.byref(params), C.byref(f), sp, len(species), mom,
+                                  _stream(stream))
     return st if raw else ctx.check(st)
 
 

@@ -256,3 +256,29 @@ def test_batch_admission_plan_small_budgets():
     # the same run with room for its sort scratch is accepted
     st, msg = _planned_submit(1 << 30, 1 << 20, host_resident=False)
     assert st == spic.SPIC_E_STATE, msg
+
+
+def test_noalloc_step_validation_on_a_host_only_context(hctx):
+    """spic_mover_noalloc checks its arguments like spic_mover, requires a
+    sort every step, and refuses a species whose sort needs more than the
+    fixed scratch before anything is enqueued."""
+    a = _HostArrays()
+    g = spic.make_grid(W.Grid(8, 8, 8))
+    f = spic.make_fields(a.f)
+    sp = spic.make_species(a.sp, -64.0)
+    m = spic.make_moments(a.m)
+    L = spic.lib()
+
+    def call(params, species=sp):
+        return L.spic_mover_noalloc(hctx.handle, C.byref(g), C.byref(params), C.byref(f), C.byref(species), 1,
+                                    C.byref(m), None)
+
+    assert call(spic.make_params(0.25, 1.0, 3, 1, 0)) == spic.SPIC_E_STATE
+    assert call(spic.make_params(0.25, 1.0, 3, 0, 0)) == spic.SPIC_E_ARG
+    assert call(spic.make_params(0.25, 1.0, 3, 4, 0)) == spic.SPIC_E_ARG
+    assert "sort_every" in L.spic_last_error(hctx.handle).decode()
+    assert call(spic.make_params(0.25, 1.0, 0, 1, 0)) == spic.SPIC_E_ARG
+    big = spic.make_species(a.sp, -64.0)
+    big.n = 8_000_000  # FP64, about 90 bytes of sort scratch per particle
+    assert call(spic.make_params(0.25, 1.0, 3, 1, 0), big) == spic.SPIC_E_BUDGET
+    assert "SPIC_NOALLOC_SCRATCH_BYTES" in L.spic_last_error(hctx.handle).decode()
