@@ -64,6 +64,7 @@ extern "C" {
 /* element types */
 #define SPIC_F32 1
 #define SPIC_F64 2
+#define SPIC_F32C 3  /* moment accumulation only: compensated FP32 (see spic_moment_array) */
 
 typedef struct spic_ctx_s *spic_ctx;
 
@@ -129,8 +130,17 @@ typedef struct {
 } spic_species;
 
 /* Moment output of one species: a device array [10][nodes].
- *  acc_dtype  SPIC_F64 (default; accumulation in FP64) or SPIC_F32 (plain
- *             single precision accumulation, for precision studies). */
+ *  acc_dtype  SPIC_F64 (default; accumulation in FP64), SPIC_F32 (plain
+ *             single precision accumulation, for precision studies) or
+ *             SPIC_F32C (compensated FP32, FP32 particles only): m is then
+ *             [2][10][nodes] FP32, a high and a low plane whose sum is the
+ *             moment.  Every term is formed in FP32 (cell offsets from an
+ *             FMA with a two-float 1/dx, so a position's cell-relative
+ *             coordinate keeps its precision) and added to the high plane
+ *             with an atomic that returns the old value; the exact rounding
+ *             error of that addition (Knuth's two-sum, in FP32) is added to
+ *             the low plane.  No FP64 arithmetic; the species takes the
+ *             unsorted path (global atomics). */
 typedef struct {
     int32_t acc_dtype;
     int32_t reserved;   /* must be 0 */

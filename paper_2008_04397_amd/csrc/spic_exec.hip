@@ -68,7 +68,8 @@ int spic_ctx_s::mover(const spic_grid &g, const spic_params &p, const spic_field
         // a variant whose extra LDS does not fit falls back to variant 0
         LaunchCfg tcfg = resolve_cfg(cfg, w.dtype, w.mom ? w.acc_dtype : SPIC_F64);
         auto tiled_ok = [&](const TileGeom &tg) {
-            if (generic_only || !tiled_fits(w.n, w.dtype)) return false;
+            // compensated FP32 moments take the unsorted path (global atomics)
+            if (generic_only || !tiled_fits(w.n, w.dtype) || (w.mom && w.acc_dtype == SPIC_F32C)) return false;
             if (tiled_lds_bytes(tg, w.dtype, w.acc_dtype, tcfg.variant, tcfg.tile_block) > lds_max) tcfg.variant = 0;
             return tiled_lds_bytes(tg, w.dtype, w.acc_dtype, tcfg.variant, tcfg.tile_block) <= lds_max;
         };

@@ -73,6 +73,8 @@ int spic_ctx_s::noalloc_check(const spic_grid &g, const spic_species *sp, int32_
                         "(SPIC_NOALLOC_SCRATCH_BYTES)",
                         i, (long long)sp[i].n, need, (size_t)SPIC_NOALLOC_SCRATCH_BYTES);
         const int acc = mom ? mom[i].acc_dtype : SPIC_F64;
+        if (acc == SPIC_F32C)
+            return fail(SPIC_E_UNSUPPORTED, "species %d: compensated FP32 moments take the unsorted path", i);
         const LaunchCfg tcfg = resolve_cfg(cfg, sp[i].dtype, acc);
         if (tiled_lds_bytes(tg, sp[i].dtype, acc, tcfg.variant, tcfg.tile_block) > lds_max &&
             tiled_lds_bytes(tg, sp[i].dtype, acc, 0, 512) > lds_max)

@@ -125,7 +125,8 @@ int spic_ctx_s::check_moments(const spic_moment_array *m, const spic_species *sp
     if (!m) return SPIC_OK;
     for (int s = 0; s < nsp; ++s) {
         if (m[s].reserved != 0) return fail(SPIC_E_ARG, "moments %d: reserved must be 0", s);
-        if (!dtype_ok(m[s].acc_dtype)) return fail(SPIC_E_ARG, "moments %d: acc_dtype %d invalid", s, m[s].acc_dtype);
+        if (!dtype_ok(m[s].acc_dtype) && m[s].acc_dtype != SPIC_F32C)
+            return fail(SPIC_E_ARG, "moments %d: acc_dtype %d invalid", s, m[s].acc_dtype);
         if (!m[s].m) return fail(SPIC_E_ARG, "moments %d: array is NULL", s);
         if ((uintptr_t)m[s].m % (m[s].acc_dtype == SPIC_F64 ? 8 : 4))
             return fail(SPIC_E_ARG, "moments %d: array is misaligned", s);

@@ -960,6 +960,7 @@ hipError_t launch_fused_tiled(const spic_grid &g, const spic_params &prm, const 
 // deposit list over the same items.
 
 int job_combo(int dtype, int fdtype, int acc_dtype) {
+    if (acc_dtype == SPIC_F32C) return -1;  // compensated FP32: the unsorted spic_mover path only
     if (dtype == SPIC_F64) return (fdtype == SPIC_F64 && acc_dtype == SPIC_F64) ? 0 : -1;
     if (fdtype == SPIC_F32) return acc_dtype == SPIC_F64 ? 1 : 2;
     return acc_dtype == SPIC_F64 ? 3 : 4;

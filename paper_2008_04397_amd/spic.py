@@ -18,7 +18,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libspic.so")
 
 SPIC_OK, SPIC_E_ARG, SPIC_E_BUDGET, SPIC_E_HIP, SPIC_E_UNSUPPORTED, SPIC_E_STATE = 0, -1, -2, -3, -4, -5
-SPIC_F32, SPIC_F64 = 1, 2
+SPIC_F32, SPIC_F64, SPIC_F32C = 1, 2, 3
 
 EXPORTED = ("spic_ctx_create", "spic_ctx_destroy", "spic_last_error", "spic_status_str", "spic_version",
             "spic_set_option", "spic_get_option", "spic_mover", "spic_moments", "spic_sort",
@@ -148,6 +148,10 @@ def make_species(sp: Dict[str, "object"], qom: float, host_resident: bool = Fals
 
 
 def make_moments(m) -> spic_moment_array:
+    """A [10][nodes] tensor (FP64 or FP32 accumulation), or a float32
+    [2][10][nodes] tensor for compensated FP32 (high and low planes)."""
+    if getattr(m, "dim", lambda: 2)() == 3:
+        return spic_moment_array(SPIC_F32C, 0, _ptr(m))
     return spic_moment_array(_dtype_code(m), 0, _ptr(m))
 
 
@@ -301,10 +305,16 @@ def to_host(arrs: Dict[str, "object"]) -> Dict[str, np.ndarray]:
     return {k: v.detach().cpu().numpy() for k, v in arrs.items()}
 
 
-def moment_buffers(grid, nsp: int, dtype=None, device="cuda"):
+def moment_buffers(grid, nsp: int, dtype=None, device="cuda", compensated: bool = False):
+    """Moment outputs: [10][nodes] of dtype, or with compensated=True the
+    float32 [2][10][nodes] high and low planes of SPIC_F32C (moments =
+    high + low)."""
     import torch
+    nn = grid.nx * grid.ny * grid.nz
+    if compensated:
+        return [torch.zeros((2, 10, nn), dtype=torch.float32, device=device) for _ in range(nsp)]
     dtype = dtype or torch.float64
-    return [torch.zeros((10, grid.nx * grid.ny * grid.nz), dtype=dtype, device=device) for _ in range(nsp)]
+    return [torch.zeros((10, nn), dtype=dtype, device=device) for _ in range(nsp)]
 
 
 # ----------------------------------------------------------- batch engine

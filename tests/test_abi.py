@@ -97,6 +97,8 @@ def test_valid_arguments_reach_the_host_only_stop(hctx):
     ("host resident", lambda g, p, f, s, m: setattr(s, "host_resident", 1), spic.SPIC_E_ARG),
     ("f64 parts f32 fields", lambda g, p, f, s, m: setattr(f, "dtype", spic.SPIC_F32), spic.SPIC_E_UNSUPPORTED),
     ("f64 parts f32 acc", lambda g, p, f, s, m: setattr(m, "acc_dtype", spic.SPIC_F32), spic.SPIC_E_UNSUPPORTED),
+    ("f64 parts f32c acc", lambda g, p, f, s, m: setattr(m, "acc_dtype", spic.SPIC_F32C), spic.SPIC_E_UNSUPPORTED),
+    ("bad acc dtype", lambda g, p, f, s, m: setattr(m, "acc_dtype", 4), spic.SPIC_E_ARG),
     ("null moments", lambda g, p, f, s, m: setattr(m, "m", None), spic.SPIC_E_ARG),
 ])
 def test_invalid_arguments_are_rejected_before_any_work(hctx, what, mut, code):

@@ -219,3 +219,35 @@ def test_invalid_call_enqueues_nothing(spic, ctx):
     torch.cuda.synchronize()
     assert st == spic.SPIC_E_ARG
     assert torch.equal(before, sp["x"])
+
+
+def test_compensated_fp32_moments(spic, ctx):
+    """SPIC_F32C (compensated FP32: FP32 terms, high plane by atomics, the
+    exact rounding error of each addition in a low plane, no FP64) after one
+    fused step of the FP32 state, and from spic_moments: high + low against
+    the oracle's FP64 deposit of the same FP32 state within the FP32 moment
+    tolerance, and no worse than plain FP32 accumulation of the same terms."""
+    h = W.harris_32x16x4()
+    f32 = {k: v.astype(np.float32) for k, v in W.make_fields(h).items()}
+    sps = [W.round_state(s, np.float32) for s in W.make_all_species(h)]
+    dev_f = spic.to_device(f32, torch.float32)
+    dev = [spic.to_device(s, torch.float32) for s in sps]
+    mc = spic.moment_buffers(h.grid, 4, compensated=True)
+    _say("case compensated fp32 moments")
+    spic.spic_mover(ctx, h.grid, spic.make_params(h.dt, h.c, h.niter, 0, 0), dev_f, dev, h.qoms, mc)
+    torch.cuda.synchronize()
+    m32 = spic.moment_buffers(h.grid, 4, torch.float32)
+    spic.spic_moments(ctx, h.grid, dev, m32)
+    mc2 = spic.moment_buffers(h.grid, 4, compensated=True)
+    spic.spic_moments(ctx, h.grid, dev, mc2)
+    torch.cuda.synchronize()
+    worst = [0.0, 0.0]
+    for s in range(4):
+        ref = O.deposit(h.grid, W.upcast(spic.to_host(dev[s])))
+        for planes in (mc[s], mc2[s]):
+            hi_lo = planes.double().sum(dim=0).cpu().numpy()
+            ec = P.assert_moments(hi_lo, ref, P.MOM32)
+        e32 = float(P.rel_l2(m32[s].cpu().numpy(), ref).max())
+        worst = [max(worst[0], ec), max(worst[1], e32)]
+        assert ec <= e32, (s, ec, e32)
+    _say("compensated fp32 worst rel-L2 %.2e, plain fp32 %.2e" % tuple(worst))
