@@ -59,17 +59,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "fused_tiled_harris_128x64x32_f32_traffic.md")
+TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "traffic_harris_128x64x32_{}.md")
 KERNEL_SOURCES = ("paper_2008_04397_amd/csrc/spic_tiled.hip", "paper_2008_04397_amd/csrc/spic_device.h",
                   "paper_2008_04397_amd/csrc/spic_impl.h")
 
 
-def measured_traffic(launch) -> Optional[float]:
-    """HBM bytes per launch of the fused kernel from the committed rocprofv3
-    FETCH_SIZE/WRITE_SIZE summary, or None when the kernel sources changed
-    since the counters were taken or the launch configuration differs."""
+def measured_traffic(launch, dtype_name: str) -> Optional[float]:
+    """HBM bytes per species pass (the fused kernel, or the mover and
+    deposit kernels of the split variant) from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary of that particle dtype, or None when the
+    kernel sources changed since the counters were taken or the launch
+    configuration differs."""
     try:
-        txt = open(TRAFFIC_PROFILE).read()
+        txt = open(TRAFFIC_PROFILE.format(dtype_name)).read()
     except OSError:
         return None
     fields = dict(re.findall(r"^(\w+): (.*)$", txt, re.M))
@@ -183,7 +185,7 @@ def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: 
     avg_launch_s = float(fused_ms.mean()) / 1e3
     achieved = per_launch_bytes / avg_launch_s / 1e9
     # measured HBM bytes of the same launches (rocprofv3 counters, profiles/)
-    traffic_bytes = measured_traffic(launch) if dtype_name == "f32" and not path else None
+    traffic_bytes = measured_traffic(launch, dtype_name) if not path else None
     traffic = traffic_bytes / avg_launch_s / 1e9 if traffic_bytes else None
     step_ms = total_ms / steps
     per_step = launch_ms.sum(axis=1)
