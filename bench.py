@@ -130,7 +130,7 @@ def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: 
         key = autotune.workload_class(dtype_name, g, h.ppc)
         tuned = autotune.load(key)
         if tuned is None:
-            tuned = autotune.tune(h, f, species, h.qoms, moms, steps=16, log=log)
+            tuned = autotune.tune(h, f, species, h.qoms, moms, steps=16, log=log, dtype_name=dtype_name)
             autotune.store(key, tuned)
         autotune.apply(ctx, tuned)
         if sort_every < 0:
@@ -276,29 +276,48 @@ def _engine_ctx(budget=0, tuned_key=None, variant=-1):
 
 
 def bench_ensemble(args):
-    """64 independent boxes, one batch submission, 50 steps each."""
+    """64 independent boxes, one batch submission, 50 steps each.  With
+    --tune the engine's block size, the runs' sort cadence and the work-list
+    batch length are first tuned on the same boxes (8-step trials; cached
+    per workload)."""
     import torch
-    from paper_2008_04397_amd import spic
+    from paper_2008_04397_amd import autotune, spic
     boxes = W.ensemble_boxes(64)
     nsteps = 50
-    ctx = _engine_ctx(variant=args.variant)
-    runs, total, gbytes = [], 0, 0.0
     log("[bench] generating 64 boxes")
+    data, total, gbytes = [], 0, 0.0
     for b, h in enumerate(boxes):
         f = W.fields_tensors(h, dtype=torch.float32)
         sps = [W.species_tensors(h, s, dtype=torch.float32) for s in range(4)]
         moms = spic.moment_buffers(h.grid, 4, torch.float64)
-        runs.append(spic.Run(h.grid, spic.make_params(h.dt, h.c, h.niter, 4, 0), f, sps, h.qoms, moms, nsteps))
+        data.append((h, f, sps, moms))
         total += h.n_total
         gbytes += algorithmic_bytes(h.n_total, h.grid.nodes, 4, 4) + 3 * (6 * h.grid.nodes * 4 + 10 * h.grid.nodes * 8)
     torch.cuda.synchronize()
+
+    def make_runs(se, k):
+        return [spic.Run(h.grid, spic.make_params(h.dt, h.c, h.niter, se, 0), f, sps, h.qoms, moms, k)
+                for h, f, sps, moms in data]
+
+    key = "engine/f32/ensemble64"
+    tuned = autotune.load(key) if args.tune else None
+    if args.tune and tuned is None:
+        log("[bench] tuning the engine on the ensemble")
+        tuned = autotune.tune_runs(lambda: _engine_ctx(variant=args.variant), make_runs,
+                                   autotune.engine_candidates(quick=True), steps=8, log=log)
+        autotune.store(key, tuned)
+    ctx = _engine_ctx(variant=args.variant)
+    se = 4
+    if tuned:
+        autotune.apply(ctx, tuned)
+        se = tuned["sort_every"]
+        log("[bench] tuned %s: %s" % (key, tuned))
     log("[bench] %d particles in %d boxes; submitting" % (total, len(boxes)))
     # warm-up: one step of every box (not timed)
-    warm = [spic.Run(r.grid, r.params, r.fields, r.species, r.qoms, r.moments, 1) for r in runs]
-    for t in spic.spic_batch_submit(ctx, warm):
+    for t in spic.spic_batch_submit(ctx, make_runs(se, 1)):
         spic.spic_wait(ctx, t)
     t0 = time.perf_counter()
-    tickets = spic.spic_batch_submit(ctx, runs)
+    tickets = spic.spic_batch_submit(ctx, make_runs(se, nsteps))
     dev = [spic.spic_wait(ctx, t) for t in tickets]
     wall = time.perf_counter() - t0
     ctx.close()
@@ -307,25 +326,29 @@ def bench_ensemble(args):
     return {"metric": METRIC, "mode": "ensemble", "value": ps / wall, "unit": "particle-steps/s", "n_gpus": 1,
             "steps": nsteps, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "ensemble_64_harris_boxes", "boxes": len(boxes), "particles": total,
-                       "precision": "f32 particles, f64 moments", "sort_every": 4},
+                       "precision": PRECISION["f32"], "sort_every": se, "tuned": tuned,
+                       "tick_items": (tuned or {}).get("tick_items", 4096)},
             "wall_s": wall, "max_run_device_s": max(dev),
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": None}}
 
 
 def bench_streamed(args):
-    """The 2.1e9-particle box streamed through a 16 GB budget."""
+    """The 2.1e9-particle box streamed through a 16 GiB budget (with
+    --tune, the batch length and cadence are tuned first)."""
     import torch
-    from paper_2008_04397_amd import spic
+    from paper_2008_04397_amd import autotune, spic
     h = W.harris_512x256x32()
     g = h.grid
     nx_used = max(1, int(round(g.nx * args.fraction)))
     n_all = 4 * nx_used * g.ny * g.nz * h.ppc
-    # 16 GiB, or a quarter of the particle bytes when that is smaller, so the
-    # run never fits and every step streams every batch over the link
-    budget = min(16 * (1 << 30), n_all * 28 // 4)
-    ctx = _new_ctx(spic, 0, budget)
-    ctx.set_option("batch_particles", 1 << 26)
+    # 16 GiB; a reduced box (--fraction) whose particles would fit twice
+    # over gets a quarter of its particle bytes instead, so that every step
+    # still streams every batch over the link
+    budget = 16 * (1 << 30)
+    if n_all * 28 < 2 * budget:
+        budget = n_all * 28 // 4
+    tuned, batch, se = None, 1 << 26, 4
     f = W.fields_tensors(h, dtype=torch.float32)
     species, total = [], 0
     log("[bench] generating %d x-slabs of 512 into pinned host memory" % nx_used)
@@ -346,7 +369,22 @@ def bench_streamed(args):
         log("[bench] species %d ready (%.1f s)" % (s, time.time() - t0))
     moms = spic.moment_buffers(g, 4, torch.float64)
     nsteps = 5
-    run = spic.Run(g, spic.make_params(h.dt, h.c, h.niter, 4, 0), f, species, h.qoms, moms, nsteps)
+
+    def make_runs(se_, k):
+        return [spic.Run(g, spic.make_params(h.dt, h.c, h.niter, se_, 0), f, species, h.qoms, moms, k)]
+
+    if args.tune:
+        key = "stream/f32/%dx%dx%d/n%d/budget%d" % (nx_used, g.ny, g.nz, total, budget)
+        tuned = autotune.load(key)
+        if tuned is None:
+            log("[bench] tuning the streamed batch length")
+            tuned = autotune.tune_runs(lambda: _new_ctx(spic, 0, budget), make_runs,
+                                       autotune.stream_candidates(quick=True), steps=4, log=log)
+            autotune.store(key, tuned)
+        batch, se = tuned["batch_particles"], tuned["sort_every"]
+    ctx = _new_ctx(spic, 0, budget)
+    ctx.set_option("batch_particles", batch)
+    run = make_runs(se, nsteps)[0]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     dev = spic.spic_wait(ctx, spic.spic_batch_submit(ctx, [run])[0])
@@ -357,8 +395,8 @@ def bench_streamed(args):
     return {"metric": METRIC, "mode": "streamed", "value": total * nsteps / wall, "unit": "particle-steps/s",
             "n_gpus": 1, "steps": nsteps, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "harris_512x256x32_ppc125_4species_streamed", "particles": total,
-                       "fraction_of_x_slabs": nx_used / g.nx, "hbm_budget_bytes": budget, "batch": 1 << 26,
-                       "sort_every": 4},
+                       "fraction_of_x_slabs": nx_used / g.nx, "hbm_budget_bytes": budget, "batch": batch,
+                       "sort_every": se, "tuned": tuned},
             "wall_s": wall, "device_s": dev,
             "roofline": {"bound": "pcie", "achieved": link, "peak": 2 * 64.0, "unit": "GB/s",
                          "frac": link / 128.0, "traffic": None,
@@ -368,52 +406,102 @@ def bench_streamed(args):
 
 def bench_cadence(args):
     """Long-run sort-cadence study on the 128x64x32 box (FP32): throughput
-    per window of steps for a sort only at step 0 and for sorts every 1, 4
-    and 10 steps (Sec. VI: locality decays without re-sorting)."""
+    per window of steps for a sort only at step 0, for sorts every 1, 4 and
+    10 steps, for the autotuned cadence (tuned on a separate copy of the
+    initial state) and for an adaptive cadence that sorts once the time the
+    passes lost since the last sort (each step's time minus the first
+    step's after that sort) reaches the sort's own cost (Sec. VI: locality
+    decays without re-sorting).  For L2 counters per window, a tiny int32
+    fill kernel marks the start of every window and an int64 fill the start
+    of every arm, so counter rows can be split by dispatch order."""
     import torch
-    from paper_2008_04397_amd import spic
+    from paper_2008_04397_amd import autotune, spic
     h = W.harris_128x64x32()
     g = h.grid
     nsteps, window = args.steps, max(1, args.steps // 10)
     f = spic.to_device(W.make_fields(h), torch.float32)
     moms = spic.moment_buffers(g, 4, torch.float64)
     stream = torch.cuda.current_stream()
-    out = {}
-    for cad in ("once", 1, 4, 10):
-        species = [spic.to_device(W.make_species(h, s, dtype=np.float32, with_id=False), torch.float32)
-                   for s in range(4)]
+    mark_window = torch.zeros(1, dtype=torch.int32, device="cuda")
+    mark_arm = torch.zeros(1, dtype=torch.int64, device="cuda")
+
+    def fresh():
+        return [spic.to_device(W.make_species(h, s, dtype=np.float32, with_id=False), torch.float32)
+                for s in range(4)]
+
+    out, sorts, extra = {}, {}, {}
+    for cad in ("once", 1, 4, 10, "tuned", "adaptive"):
+        mark_arm.fill_(1)
         ctx = _new_ctx(spic, 0)
+        if cad == "tuned":
+            trial = fresh()
+            cfg = autotune.tune(h, f, trial, h.qoms, moms, steps=16, log=log, dtype_name="f32")
+            del trial
+            autotune.apply(ctx, cfg)
+            extra["tuned"] = cfg
+            log("[cadence tuned] %s" % cfg)
+        species = fresh()
+        torch.cuda.synchronize()
         if cad == "once":
             spic.spic_sort(ctx, g, species, stream=stream)
-        se = 0 if cad == "once" else cad
-        rates = []
+        fixed = {"once": 0, "tuned": extra.get("tuned", {}).get("sort_every", 4), "adaptive": None}.get(cad, cad)
+        rates, nsort = [], 0
+        # adaptive state: the sort's cost, the first pass time after it and
+        # the time lost since
+        sort_cost, t0, lost, want = 0.0, None, 0.0, True
         for w0 in range(0, nsteps, window):
+            mark_window.fill_(w0)
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(stream)
             for k in range(w0, min(nsteps, w0 + window)):
-                spic.spic_mover(ctx, g, spic.make_params(h.dt, h.c, h.niter, se, k), f, species, h.qoms, moms,
-                                stream=stream)
+                if fixed is not None:
+                    nsort += int(fixed > 0 and k % fixed == 0)
+                    spic.spic_mover(ctx, g, spic.make_params(h.dt, h.c, h.niter, fixed, k), f, species, h.qoms,
+                                    moms, stream=stream)
+                    continue
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                spic.spic_mover(ctx, g, spic.make_params(h.dt, h.c, h.niter, 1 if want else 0, k), f, species,
+                                h.qoms, moms, stream=stream)
+                e1.record(stream)
+                e1.synchronize()
+                ms = e0.elapsed_time(e1)
+                if want:
+                    sort_step_ms, want, t0, lost, nsort = ms, False, None, 0.0, nsort + 1
+                elif t0 is None:
+                    t0 = ms
+                    sort_cost = max(0.0, sort_step_ms - t0)
+                else:
+                    lost += ms - t0
+                    want = lost >= sort_cost
             b.record(stream)
             torch.cuda.synchronize()
             n = min(nsteps, w0 + window) - w0
             rates.append(h.n_total * n / (a.elapsed_time(b) / 1e3))
             log("[cadence %s] steps %d-%d: %.3e particle-steps/s" % (cad, w0, w0 + n - 1, rates[-1]))
         out[str(cad)] = rates
+        sorts[str(cad)] = nsort
         ctx.close()
         del species
         torch.cuda.empty_cache()
+    mark_arm.fill_(1)
+    torch.cuda.synchronize()
+    sustained = {k: float(np.mean(v[len(v) * 4 // 5:])) for k, v in out.items()}
     return {"metric": METRIC, "mode": "cadence", "value": float(np.mean(out["4"])), "unit": "particle-steps/s",
             "n_gpus": 1, "steps": nsteps, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "harris_128x64x32_ppc64_4species", "window_steps": window,
-                       "cadences": ["sort at step 0 only", 1, 4, 10]},
-            "rates_per_window": out}
+                       "cadences": ["sort at step 0 only", 1, 4, 10, "autotuned", "adaptive"],
+                       "tuned": extra.get("tuned")},
+            "rates_per_window": out, "sorts": sorts,
+            "mean_rate": {k: float(np.mean(v)) for k, v in out.items()},
+            "sustained_rate_last_fifth": sustained}
 
 
 def bench_serving(args):
     """Poisson request stream: continuous batching vs one at a time."""
     import torch
     from paper_2008_04397_amd import serving, spic
-    reqs = W.serving_stream(args.requests)
+    reqs = W.serving_stream(args.requests, rate=args.rate)
     res = {}
     for mode in ("continuous", "serial"):
         ctx = _engine_ctx(budget=64 * (1 << 30), variant=args.variant)
@@ -431,7 +519,7 @@ def bench_serving(args):
     c = res["continuous"]
     return {"metric": METRIC, "mode": "serving", "value": c["throughput"], "unit": "particle-steps/s", "n_gpus": 1,
             "higher_is_better": True, "dtype": "f32", "data": "synthetic",
-            "config": {"workload": "poisson_20_per_s_harris_runs", "requests": len(reqs),
+            "config": {"workload": "poisson_%g_per_s_harris_runs" % args.rate, "requests": len(reqs),
                        "precision": "f32 particles, f64 moments", "hbm_budget_bytes": 64 * (1 << 30),
                        "srpt_aging_M_per_s": args.srpt_aging if args.srpt_aging >= 0 else 10000},
             "p50_s": c["p50_s"], "p99_s": c["p99_s"], "continuous": c, "serial": res["serial"]}
@@ -446,6 +534,7 @@ def main():
     ap.add_argument("--mode", default="main", choices=("main", "ensemble", "streamed", "serving", "cadence"))
     ap.add_argument("--fraction", type=float, default=1.0)
     ap.add_argument("--requests", type=int, default=120)
+    ap.add_argument("--rate", type=float, default=20.0, help="serving: mean request arrivals per second")
     ap.add_argument("--srpt-aging", type=int, default=-1,
                     help="serving: engine aging credit in M particle-steps/s (-1: library default)")
     ap.add_argument("--tune", action="store_true",

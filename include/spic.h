@@ -189,34 +189,42 @@ int spic_version(void);
  *   grid_cap       cap on blocks of grid-stride kernels
  *   path           0 = tiled kernel for sorted species, 1 = unsorted path only
  *   tile_block     threads per block of the tiled kernel (64..512, x64; -1 =
- *                  by variant: 256 for variants 5 to 9, else 512)
+ *                  by variant: 256 for variant 2's deposit launch, else 512)
  *   tile_x/y/z     sort tile shape in cells (product <= 64)
  *   halo           cells of halo staged around a tile in LDS (0..8)
  *   lds_max        read only: LDS bytes a workgroup may use on the device
- *   tile_variant   tiled-kernel variant (0..9; see spic_tiled.hip; -1 = by
- *                  precision: 8 -- a mover launch, then a lane-cell deposit
- *                  launch -- for FP32 particles with FP64 moments, else 0)
- *   mover_cache    variant 8: 1 = the mover launch keeps the 48 field
+ *   tile_variant   tiled-kernel variant (0..2; -1 = by precision): 0 one
+ *                  kernel, every deposit an FP64 LDS atomic (default for
+ *                  FP64 particles); 1 as 0 with the 48 field values of a
+ *                  thread's last cell in registers; 2 a mover launch, then
+ *                  a deposit launch into per-lane register sums of sorted
+ *                  cells (default for FP32 particles)
+ *   mover_cache    variant 2: 1 = the mover launch keeps the 48 field
  *                  values of a thread's last cell in registers (default), 0 =
  *                  every gather reads LDS
- *   mover_halo     variant 8: cells of halo of the mover launch's field
+ *   mover_halo     variant 2: cells of halo of the mover launch's field
  *                  region (-1..8; -1 = the tile halo + 1; a region too large
  *                  for the device's LDS falls back to the tile halo)
+ *   tile_group     mapping of tiles to workgroups of a tiled launch: groups
+ *                  of 2^value consecutive tiles dealt to the 8 XCDs in turn
+ *                  (0..10, default 4); -1 = XCD slabs, each XCD taking a
+ *                  contiguous eighth of the tiles (a launch whose particles
+ *                  occupy a contiguous fraction of the tiles, as a streamed
+ *                  batch does, then runs on few XCDs)
  *   fixed_geo      1 = kernels compiled for 4x4x4 tiles with halo 1 (and
- *                  the variant-8 mover's halo 2) are used when that tiling
+ *                  the variant-2 mover's halo 2) are used when that tiling
  *                  is in effect
  *   bank_align     1 = LDS region layout that keeps a particle's bank pair
  *                  when it drifts along the most-crossed axis (more LDS);
  *                  0 = the most compact conflict-free layout; 2 = dense,
- *                  no padding (default: 2 for variant 6, else 1 for FP32
- *                  particles and 0 for FP64)
+ *                  no padding (default: 1 for FP32 particles, 0 for FP64)
  *   sort_ordered   1 = a re-sort walks each tile of the current order in
  *                  order, so ranks inside a cell keep that order (0/1)
  *   sort_rows      1 = full rows: a tile of n particles and C cells gets
  *                  n / C rows of C slots, slot (r, c) holding rank r of cell
  *                  c where that exists and the particles of higher ranks
  *                  filling the rest; 0 = plain rank blocks (default 1 for
- *                  tile variants 5-9, else 0)
+ *                  tile variant 2, else 0)
  *   graph          batch engine: replay unchanged ticks as a hipGraph (0/1)
  *   batch_particles  batch engine: particles per streamed batch
  *   max_groups     batch engine: cap on workgroups of the persistent launch
@@ -228,6 +236,12 @@ int spic_version(void);
  *                  long runs are not starved by a stream of short ones
  *                  (default 10000; 0 = pure least-remaining-work) */
 int spic_set_option(spic_ctx ctx, const char *key, int64_t value);
+/* The value of an option: the value set, or -1 when unset (the library then
+ * decides; tile_group reads 4, its default, and lds_max the device's limit).
+ * "f32:<key>" / "f64:<key>" read the launch setting the library resolves for
+ * FP32 / FP64 particles with FP64 moments (keys tile_variant, tile_block,
+ * sort_rows, halo, bank_align, sort_ordered, mover_cache, mover_halo,
+ * tile_group).  Unknown keys return SPIC_E_ARG. */
 int spic_get_option(spic_ctx ctx, const char *key, int64_t *value);
 
 /* ------------------------------------------------------------- hot path */

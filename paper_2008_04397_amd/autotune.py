@@ -1,14 +1,24 @@
-"""Autotuner for the fused tiled path: picks the threads per workgroup, the
-kernel variant (LDS atomics; + field corners in registers; home-cell
-register accumulation with a queue of drifted particles; bank-balanced
-LDS deposit), the halo and the sort
-cadence by timing short runs of the actual workload, and caches the choice
-per (dtype, workload class) in a JSON file next to this module.
+"""Autotuner: picks launch settings and the sort cadence by timing short
+runs of the actual workload, and caches the choice per workload class in a
+JSON file next to this module.
 
-Sorting costs a pass over the particles but keeps the tiles compact; the
-best cadence depends on how fast particles cross cells (Sec. VI: sorting
-every few cycles keeps the rate high over long runs), so it is measured, not
-assumed.
+Three spaces, one per way the library runs a workload:
+
+* one resident box (spic_mover): threads per workgroup, the tiled kernel
+  variant (the dtype's candidates), the bank-preserving layout and the sort
+  cadence;
+* many boxes in one engine submission (spic_batch_submit, an ensemble):
+  threads per workgroup, the sort cadence of the runs and the work-list
+  batch length (tick_items: (run, tile) items stepped per tick);
+* a streamed box (larger than its HBM budget): the batch length
+  (batch_particles per streamed batch) and the sort cadence.
+
+The sort costs a pass over the particles but keeps the tiles compact; how
+often it pays depends on how fast particles cross cells (Sec. VI: sorting
+every few cycles keeps the rate up over long runs), so it is measured, not
+assumed.  Batch length trades launch count against the work one tick holds
+(Sec. III-B: particles are processed in batches; Sec. V-C sweeps the batch
+count per species and the threads per block).
 """
 from __future__ import annotations
 
@@ -17,12 +27,16 @@ import json
 import math
 import os
 import time
-from typing import Dict, Iterable, Optional, Sequence
+from typing import Callable, Dict, Iterable, List, Optional, Sequence
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 
 DEFAULT = {"tile_block": 256, "tile_variant": 2, "halo": 1, "tile_x": 4, "tile_y": 4, "tile_z": 4,
            "bank_align": 1, "sort_ordered": 1, "sort_every": 4}
+
+# keys that are not library options: the cadence goes into each step's
+# spic_params.sort_every
+RUN_KEYS = ("sort_every",)
 
 
 def workload_class(dtype_name: str, grid, ppc: int) -> str:
@@ -53,39 +67,51 @@ def store(key: str, cfg: Dict[str, int]):
 
 
 def apply(ctx, cfg: Dict[str, int]):
+    """Set every library option of `cfg` on `ctx` (the cadence is not one)."""
     for k, v in cfg.items():
-        if k != "sort_every":
+        if k not in RUN_KEYS:
             ctx.set_option(k, v)
 
 
-def candidates(quick: bool = True) -> Iterable[Dict[str, int]]:
-    """quick: the variants that have won on MI355X (plain LDS atomics and the
-    lane-cell register deposit, in one launch and split); otherwise every
-    variant, cadence and halo."""
+def _lcm(values: Iterable[int]) -> int:
+    out = 1
+    for v in values:
+        out = out * v // math.gcd(out, v)
+    return out
+
+
+# ---------------------------------------------------------------- one box
+
+def candidates(quick: bool = True, dtype_name: str = "f32") -> Iterable[Dict[str, int]]:
+    """One resident box.  FP32 particles: the split variant (2) and, unless
+    quick, the one-kernel variants 0 and 1; FP64 particles: the one-kernel
+    variants (their LDS-atomic deposit is exact in FP64).  Blocks and
+    cadences as listed; the bank-preserving layout on and off."""
     blocks = (256, 512)
-    variants = (2,) if quick else (0, 1, 2)
+    if dtype_name == "f64":
+        variants = (0,) if quick else (0, 1)
+    else:
+        variants = (2,) if quick else (0, 1, 2)
     cadences = (2, 4, 8) if quick else (1, 2, 4, 8, 16)
-    halos = (1,) if quick else (1, 2)
     aligns = (1, 0)
-    for blk, var, se, halo, al in itertools.product(blocks, variants, cadences, halos, aligns):
+    for blk, var, se, al in itertools.product(blocks, variants, cadences, aligns):
         c = dict(DEFAULT)
-        c.update(tile_block=blk, tile_variant=var, sort_every=se, halo=halo, bank_align=al)
+        c.update(tile_block=blk, tile_variant=var, sort_every=se, bank_align=al)
         yield c
 
 
-def tune(h, fields, species, qoms, moments, steps: int = 16, quick: bool = True, log=None) -> Dict[str, int]:
-    """Time `steps` fused steps (after the first sort) for every candidate on
-    the given device-resident inputs; returns the fastest configuration.  The
-    inputs are advanced in time by the trials (a real run's state).  `steps`
-    is rounded up to a multiple of every candidate cadence, so each trial
-    pays its own sorts in full."""
+def tune(h, fields, species, qoms, moments, steps: int = 16, quick: bool = True, log=None,
+         dtype_name: str = "f32") -> Dict[str, int]:
+    """Time `steps` fused steps (after a first sort) for every candidate on
+    the given device-resident inputs; returns the fastest configuration.
+    The inputs are advanced in time by the trials (a real run's state).
+    `steps` is rounded up to a multiple of every candidate cadence, so each
+    trial pays its own sorts in full."""
     import torch
     from . import spic
     best, best_ms = None, float("inf")
-    cands = list(candidates(quick))
-    period = 1
-    for c in cands:
-        period = period * c["sort_every"] // math.gcd(period, c["sort_every"])
+    cands = list(candidates(quick, dtype_name))
+    period = _lcm(c["sort_every"] for c in cands)
     steps = -(-steps // period) * period
     for cfg in cands:
         ctx = spic.Context(0)
@@ -103,4 +129,55 @@ def tune(h, fields, species, qoms, moments, steps: int = 16, quick: bool = True,
             log("[tune] %s -> %.3f ms/step" % (cfg, ms))
         if ms < best_ms:
             best, best_ms = cfg, ms
+    return best
+
+
+# ------------------------------------------------ engine runs (ensemble, streamed)
+
+def engine_candidates(quick: bool = True) -> List[Dict[str, int]]:
+    """Many boxes per submission: threads per workgroup x sort cadence x
+    (run, tile) items per tick (0: every run steps at every tick)."""
+    blocks = (256, 512)
+    cadences = (2, 4, 8) if quick else (1, 2, 4, 8)
+    ticks = (2048, 8192, 0) if quick else (1024, 2048, 4096, 8192, 32768, 0)
+    return [{"tile_block": b, "sort_every": se, "tick_items": t} for b, se, t in itertools.product(blocks, cadences,
+                                                                                                   ticks)]
+
+
+def stream_candidates(quick: bool = True) -> List[Dict[str, int]]:
+    """A streamed box: particles per streamed batch x sort cadence."""
+    batches = (1 << 25, 1 << 26) if quick else (1 << 24, 1 << 25, 1 << 26, 1 << 27)
+    cadences = (4,) if quick else (2, 4, 8)
+    return [{"batch_particles": b, "sort_every": se} for b, se in itertools.product(batches, cadences)]
+
+
+def tune_runs(make_ctx: Callable[[], object], make_runs: Callable[[int, int], Sequence], cands: Sequence[Dict],
+              steps: int = 8, log=None) -> Dict[str, int]:
+    """Engine tuner.  For every candidate: a fresh context from make_ctx()
+    with the candidate's options, one untimed submission of 1 step (kernel
+    and engine warm-up), then `steps` steps of make_runs(sort_every, steps)
+    submitted together, timed from submission to the last spic_wait.
+    `steps` is rounded up to a multiple of every candidate cadence.  Returns
+    the fastest candidate."""
+    from . import spic
+    period = _lcm(c.get("sort_every", 1) for c in cands)
+    steps = -(-steps // period) * period
+    best, best_s = None, float("inf")
+    for cfg in cands:
+        ctx = make_ctx()
+        try:
+            apply(ctx, cfg)
+            se = cfg.get("sort_every", 4)
+            for t in spic.spic_batch_submit(ctx, make_runs(se, 1)):
+                spic.spic_wait(ctx, t)
+            t0 = time.perf_counter()
+            for t in spic.spic_batch_submit(ctx, make_runs(se, steps)):
+                spic.spic_wait(ctx, t)
+            secs = time.perf_counter() - t0
+        finally:
+            ctx.close()
+        if log:
+            log("[tune] %s -> %.3f s for %d steps" % (cfg, secs, steps))
+        if secs < best_s:
+            best, best_s = dict(cfg), secs
     return best

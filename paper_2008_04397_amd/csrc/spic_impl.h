@@ -63,6 +63,7 @@ struct LaunchCfg {
     int fixed_geo = 1;      // compile-time region geometry for the default tiling
     int mover_halo = -1;    // variant 2: halo of the mover's field region (-1: tile halo + 1)
     int mover_cache = 1;    // variant 2: the mover keeps the last cell's field corners in registers
+    int tile_group = 4;     // tiles to workgroups: g >= 0 groups of 2^g tiles dealt to the XCDs, -1 XCD slabs
     size_t lds_max = 65536; // LDS bytes a workgroup may use on the device
 };
 
@@ -74,6 +75,21 @@ struct LaunchCfg {
 // which leaves the deposit two waves per SIMD and spills).  Workgroup size
 // when the options leave it to the library: 256 for the sorted deposit,
 // 512 for the one-kernel forms.
+// Default mapping of tiles to workgroups: groups of 16 consecutive tiles
+// dealt to the XCDs in turn.  Measured as fast as XCD slabs on resident
+// boxes, and it keeps a streamed batch (a contiguous eighth of the tiles)
+// on all 8 XCDs where slabs would give it to one.
+constexpr int kTileGroup = 4;
+
+// Workgroups per XCD of a tiled launch over `ntiles` tiles (the grid is 8
+// times this): ceil(ntiles / 8) for the XCD-slab mapping (glog < 0); whole
+// groups of 2^glog tiles per XCD for the group mapping.
+inline int tile_chunk(int ntiles, int glog) {
+    if (glog < 0) return (ntiles + 7) / 8;
+    const int g = 1 << glog;
+    return ((ntiles + g - 1) / g + 7) / 8 * g;
+}
+
 constexpr int kVariantSplit = 2;
 inline int auto_variant(int dtype, int) { return dtype == SPIC_F32 ? kVariantSplit : 0; }
 inline int auto_tile_block(int variant) { return variant == kVariantSplit ? 256 : 512; }

@@ -206,6 +206,7 @@ static const char *const kOptionNames[] = {
     "srpt_aging",   // batch engine: credit, in M particle-steps per second waited, against starvation
     "mover_halo",   // variant 2: halo of the mover's field region (-1: tile halo + 1)
     "mover_cache",  // variant 2: 1 = the mover keeps the last cell's field corners in registers
+    "tile_group",   // tiles to workgroups: groups of 2^v tiles dealt to the XCDs (default 4); -1 XCD slabs
 };
 
 int64_t spic_ctx_s::opt(const char *k, int64_t dflt) const {
@@ -222,6 +223,7 @@ LaunchCfg spic_ctx_s::launch_cfg() const {
     c.fixed_geo = (int)opt("fixed_geo", 1);
     c.mover_halo = (int)opt("mover_halo", -1);
     c.mover_cache = (int)opt("mover_cache", 1);
+    c.tile_group = (int)opt("tile_group", kTileGroup);
     c.lds_max = lds_max;
     return c;
 }
@@ -317,6 +319,8 @@ int spic_set_option(spic_ctx ctx, const char *key, int64_t value) {
                 return ctx->fail(SPIC_E_ARG, "bank_align must be 0, 1 or 2");
             if (!strcmp(key, "halo") && (value < 0 || value > 8))
                 return ctx->fail(SPIC_E_ARG, "halo must be in [0, 8]");
+            if (!strcmp(key, "tile_group") && (value < -1 || value > 10))
+                return ctx->fail(SPIC_E_ARG, "tile_group must be -1 or in 0..10");
             if (!strcmp(key, "mover_halo") && (value < -1 || value > 8))
                 return ctx->fail(SPIC_E_ARG, "mover_halo must be -1 or in [0, 8]");
             if (!strcmp(key, "lds_max")) return ctx->fail(SPIC_E_ARG, "lds_max is read only");
@@ -344,12 +348,15 @@ int spic_get_option(spic_ctx ctx, const char *key, int64_t *value) {
         else if (!strcmp(k, "sort_ordered")) *value = ctx->opt("sort_ordered", 1);
         else if (!strcmp(k, "mover_cache")) *value = c.mover_cache;
         else if (!strcmp(k, "mover_halo")) *value = c.mover_halo >= 0 ? c.mover_halo : tg.halo + 1;
+        else if (!strcmp(k, "tile_group")) *value = c.tile_group;
         else return ctx->fail(SPIC_E_ARG, "unknown resolved setting '%s'", key);
         return SPIC_OK;
     }
     for (const char *k : kOptionNames)
         if (!strcmp(k, key)) {
-            *value = !strcmp(key, "lds_max") ? (int64_t)ctx->lds_max : ctx->opt(key, -1);
+            if (!strcmp(key, "lds_max")) *value = (int64_t)ctx->lds_max;
+            else if (!strcmp(key, "tile_group")) *value = ctx->opt(key, kTileGroup);  // -1 is a value here
+            else *value = ctx->opt(key, -1);
             return SPIC_OK;
         }
     return ctx->fail(SPIC_E_ARG, "unknown option '%s'", key);

@@ -38,10 +38,10 @@
 // deposit, so the result does not depend on the particle order; the order
 // only decides how much work stays in LDS and registers.
 //
-// Tiles are mapped to workgroups so that the 8 XCDs each take a contiguous
-// slab of tiles: workgroup b runs on XCD b % 8, and gets tile
-// (b % 8) * chunk + b / 8, keeping a slab's fields and moments in that XCD's
-// L2.
+// Tiles are mapped to workgroups with the 8 XCDs in mind (workgroup b runs
+// on XCD b % 8): by default groups of 16 consecutive tiles are dealt to the
+// XCDs in turn; the alternative gives each XCD a contiguous slab of tiles
+// (tile_of_block).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -744,6 +744,19 @@ __device__ __forceinline__ void deposit_body(const TileJob<TP, TF, TA> &J, int t
 
 // ---------------------------------------------------------------- kernels
 
+// Tile of workgroup b (workgroup b runs on XCD b % 8).  Slab mapping (glog
+// < 0): XCD x takes the contiguous tiles [x * chunk, (x + 1) * chunk), so
+// a slab's fields and moments stay in that XCD's L2.  Group mapping (glog
+// >= 0): groups of 2^glog consecutive tiles are dealt to the XCDs in turn,
+// for launches whose particles occupy a contiguous fraction of the tiles
+// (a streamed batch), which slabs would give to one XCD.  `chunk` is the
+// number of workgroups per XCD (tile_chunk).
+__host__ __device__ __forceinline__ int tile_of_block(int b, int chunk, int glog) {
+    if (glog < 0) return (b & 7) * chunk + (b >> 3);
+    const int r = b >> 3;
+    return ((((r >> glog) << 3) + (b & 7)) << glog) | (r & ((1 << glog) - 1));
+}
+
 // Register budget of the mover-carrying kernels in waves per SIMD: the
 // field-corner cache holds 48 values (96 VGPRs in FP64).
 template <bool CACHE, typename TP>
@@ -758,20 +771,20 @@ struct DepositWaves {
 
 template <typename TP, typename TF, typename TA, bool CACHE, bool MOVE_ONLY, class GEO>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MoverWaves<CACHE, TP>::value)))
-k_fused_tiled(TileJob<TP, TF, TA> J, int chunk) {
+k_fused_tiled(TileJob<TP, TF, TA> J, int chunk, int glog) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int b = blockIdx.x;
-    const int t = (b & 7) * chunk + (b >> 3);
+    const int t = tile_of_block(b, chunk, glog);
     if (t >= J.tg.ntiles) return;
     tile_body<TP, TF, TA, CACHE, MOVE_ONLY, GEO>(J, t, smem);
 }
 
 template <typename TP, typename TF, typename TA, class GEO>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(DepositWaves<TP>::value)))
-k_deposit_tiled(TileJob<TP, TF, TA> J, int chunk) {
+k_deposit_tiled(TileJob<TP, TF, TA> J, int chunk, int glog) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int b = blockIdx.x;
-    const int t = (b & 7) * chunk + (b >> 3);
+    const int t = tile_of_block(b, chunk, glog);
     if (t >= J.tg.ntiles) return;
     deposit_body<TP, TF, TA, GEO>(J, t, smem);
 }
@@ -846,10 +859,11 @@ static void allow_lds(K kernel, size_t bytes) {
 }
 
 template <typename TP, typename TF, typename TA, bool CACHE, bool MOVE_ONLY, class GEO>
-static void fused_launch(const TileJob<TP, TF, TA> &job, int chunk, size_t lds, int block, hipStream_t s) {
+static void fused_launch(const TileJob<TP, TF, TA> &job, int chunk, int glog, size_t lds, int block,
+                         hipStream_t s) {
     auto k = k_fused_tiled<TP, TF, TA, CACHE, MOVE_ONLY, GEO>;
     allow_lds(k, lds);
-    hipLaunchKernelGGL(k, dim3(8 * chunk), dim3(block), lds, s, job, chunk);
+    hipLaunchKernelGGL(k, dim3(8 * chunk), dim3(block), lds, s, job, chunk, glog);
 }
 
 // The mover launch of variant 2 stages its own field region, by default
@@ -889,13 +903,13 @@ static void split_launch(const TileJob<TP, TF, TA> &job, int chunk, const Launch
     const bool same = mv.tg.halo == tg.halo;
     const bool m2 = cfg.fixed_geo && geo_is<GeoMover2>(mv.tg);
     if (cfg.mover_cache) {
-        if (same) fused_launch<TP, TF, TA, true, true, GEO>(mv, chunk, fl, 512, s);
-        else if (m2) fused_launch<TP, TF, TA, true, true, GeoMover2>(mv, chunk, fl, 512, s);
-        else fused_launch<TP, TF, TA, true, true, GeoRuntime>(mv, chunk, fl, 512, s);
+        if (same) fused_launch<TP, TF, TA, true, true, GEO>(mv, chunk, cfg.tile_group, fl, 512, s);
+        else if (m2) fused_launch<TP, TF, TA, true, true, GeoMover2>(mv, chunk, cfg.tile_group, fl, 512, s);
+        else fused_launch<TP, TF, TA, true, true, GeoRuntime>(mv, chunk, cfg.tile_group, fl, 512, s);
     } else {
-        if (same) fused_launch<TP, TF, TA, false, true, GEO>(mv, chunk, fl, 512, s);
-        else if (m2) fused_launch<TP, TF, TA, false, true, GeoMover2>(mv, chunk, fl, 512, s);
-        else fused_launch<TP, TF, TA, false, true, GeoRuntime>(mv, chunk, fl, 512, s);
+        if (same) fused_launch<TP, TF, TA, false, true, GEO>(mv, chunk, cfg.tile_group, fl, 512, s);
+        else if (m2) fused_launch<TP, TF, TA, false, true, GeoMover2>(mv, chunk, cfg.tile_group, fl, 512, s);
+        else fused_launch<TP, TF, TA, false, true, GeoRuntime>(mv, chunk, cfg.tile_group, fl, 512, s);
     }
     if (!job.mom) return;
     TileJob<TP, TF, TA> dj = job;
@@ -905,11 +919,11 @@ static void split_launch(const TileJob<TP, TF, TA> &job, int chunk, const Launch
     if (cfg.fixed_geo && geo_is<GeoDense>(dj.tg)) {
         auto k = k_deposit_tiled<TP, TF, TA, GeoDense>;
         allow_lds(k, dl);
-        hipLaunchKernelGGL(k, dim3(8 * chunk), dim3(cfg.tile_block), dl, s, dj, chunk);
+        hipLaunchKernelGGL(k, dim3(8 * chunk), dim3(cfg.tile_block), dl, s, dj, chunk, cfg.tile_group);
     } else {
         auto k = k_deposit_tiled<TP, TF, TA, GeoRuntime>;
         allow_lds(k, dl);
-        hipLaunchKernelGGL(k, dim3(8 * chunk), dim3(cfg.tile_block), dl, s, dj, chunk);
+        hipLaunchKernelGGL(k, dim3(8 * chunk), dim3(cfg.tile_block), dl, s, dj, chunk, cfg.tile_group);
     }
 }
 
@@ -918,15 +932,18 @@ static void tiled_variant(const TileJob<TP, TF, TA> &job, int chunk, size_t lds,
                           hipStream_t s) {
     switch (cfg.variant) {
         case 2: split_launch<TP, TF, TA, GEO>(job, chunk, cfg, s); break;
-        case 1: fused_launch<TP, TF, TA, true, false, GEO>(job, chunk, lds, cfg.tile_block, s); break;
-        default: fused_launch<TP, TF, TA, false, false, GEO>(job, chunk, lds, cfg.tile_block, s);
+        case 1:
+            fused_launch<TP, TF, TA, true, false, GEO>(job, chunk, cfg.tile_group, lds, cfg.tile_block, s);
+            break;
+        default:
+            fused_launch<TP, TF, TA, false, false, GEO>(job, chunk, cfg.tile_group, lds, cfg.tile_block, s);
     }
 }
 
 template <typename TP, typename TF, typename TA>
 static void tiled_t(const spic_grid &g, const spic_params &prm, const spic_fields &f, const SpeciesWork &w,
                     const TileGeom &tg, const uint32_t *tile_off, const LaunchCfg &cfg, hipStream_t s) {
-    const int chunk = (tg.ntiles + 7) / 8;
+    const int chunk = tile_chunk(tg.ntiles, cfg.tile_group);
     const size_t lds = tiled_lds_bytes(tg, sizeof(TP) == 8 ? SPIC_F64 : SPIC_F32,
                                        sizeof(TA) == 8 ? SPIC_F64 : SPIC_F32, cfg.variant, cfg.tile_block);
     const auto job = make_tile_job<TP, TF, TA>(g, prm, f, w, tg, tile_off);

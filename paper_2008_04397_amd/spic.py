@@ -283,7 +283,7 @@ def resolved_launch(ctx: Context, dtype: str) -> Dict[str, int]:
     the given precision ("f32"/"f64") with FP64 moments (read-only option
     keys "f32:<name>" / "f64:<name>"; no resolution logic here)."""
     keys = ("tile_variant", "tile_block", "bank_align", "sort_ordered", "sort_rows", "halo", "mover_cache",
-            "mover_halo")
+            "mover_halo", "tile_group")
     return {k: ctx.get_option("%s:%s" % (dtype, k)) for k in keys}
 
 

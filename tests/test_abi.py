@@ -130,6 +130,14 @@ def test_options(hctx):
     for bad in (-2, 3):
         with pytest.raises(spic.SpicError):
             hctx.set_option("tile_variant", bad)
+    assert hctx.get_option("tile_group") == 4  # unset: the library default (groups of 16)
+    hctx.set_option("tile_group", -1)
+    assert hctx.get_option("tile_group") == -1
+    hctx.set_option("tile_group", 4)
+    assert hctx.get_option("tile_group") == 4
+    for bad in (-2, 11):
+        with pytest.raises(spic.SpicError):
+            hctx.set_option("tile_group", bad)
 
 
 def test_resolved_launch_comes_from_the_library(hctx):
@@ -143,6 +151,7 @@ def test_resolved_launch_comes_from_the_library(hctx):
     assert f32["tile_block"] == 256 and f32["sort_rows"] == 1 and f32["halo"] == 1
     assert f64["tile_block"] == 512 and f64["sort_rows"] == 0
     assert f32["bank_align"] == 1 and f64["bank_align"] == 0 and f32["mover_halo"] == 2
+    assert f32["tile_group"] == 4 and f64["tile_group"] == 4
     hctx.set_option("tile_variant", 0)
     r = spic.resolved_launch(hctx, "f32")
     assert r["tile_variant"] == 0 and r["tile_block"] == 512 and r["sort_rows"] == 0
@@ -201,6 +210,59 @@ def test_autotune_cache_roundtrip(tmp_path, monkeypatch):
     autotune.store(key, dict(autotune.DEFAULT))
     assert autotune.load(key) == autotune.DEFAULT
     assert len(list(autotune.candidates(quick=True))) == 12
+    # FP64 particles: only the one-kernel variants are candidates
+    assert {c["tile_variant"] for c in autotune.candidates(False, "f64")} == {0, 1}
+    assert {c["tile_variant"] for c in autotune.candidates(False, "f32")} == {0, 1, 2}
+    # the engine spaces: block x cadence x batch length, all distinct
+    for cands, keys in ((autotune.engine_candidates(True), ("tile_block", "sort_every", "tick_items")),
+                        (autotune.engine_candidates(False), ("tile_block", "sort_every", "tick_items")),
+                        (autotune.stream_candidates(False), ("batch_particles", "sort_every"))):
+        assert len({tuple(c[k] for k in keys) for c in cands}) == len(cands)
+    assert len(autotune.engine_candidates(True)) == 18
+    assert {c["tick_items"] for c in autotune.engine_candidates(False)} >= {0, 4096}
+
+
+class _FakeCtx:
+    """Records the options a tuner sets (no library behind it)."""
+
+    def __init__(self):
+        self.opts, self.closed = {}, False
+
+    def set_option(self, k, v):
+        self.opts[k] = v
+
+    def close(self):
+        self.closed = True
+
+
+def test_tune_runs_picks_the_fastest_and_rounds_steps(monkeypatch):
+    """tune_runs with a stand-in engine whose wait time depends on the
+    candidate: the fastest wins; every trial gets a fresh context with its
+    options; steps round up to a multiple of every cadence."""
+    from paper_2008_04397_amd import autotune, spic
+    clock = [0.0]
+    ctxs, steps_seen = [], []
+    monkeypatch.setattr(autotune.time, "perf_counter", lambda: clock[0])
+
+    def submit(ctx, runs):
+        steps_seen.append(runs[0])
+        cost = {256: 1.0, 512: 2.0}[ctx.opts["tile_block"]] * (1.0 + abs(ctx.opts["tick_items"] - 2048) / 1e4)
+        clock[0] += cost * runs[0]
+        return [1]
+
+    monkeypatch.setattr(spic, "spic_batch_submit", submit)
+    monkeypatch.setattr(spic, "spic_wait", lambda ctx, t: 0.0)
+
+    def make_ctx():
+        ctxs.append(_FakeCtx())
+        return ctxs[-1]
+
+    cands = autotune.engine_candidates(quick=True)
+    best = autotune.tune_runs(make_ctx, lambda se, k: [k], cands, steps=3)
+    assert best["tile_block"] == 256 and best["tick_items"] == 2048
+    assert len(ctxs) == len(cands) and all(c.closed for c in ctxs)
+    assert all("sort_every" not in c.opts for c in ctxs)
+    assert set(steps_seen) == {1, 8}  # warm-up step, then 3 rounded up to lcm(2, 4, 8)
 
 
 def test_serving_summary_statistics():

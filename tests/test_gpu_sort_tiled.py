@@ -334,3 +334,32 @@ def test_run_to_run_repeatability(spic, ctx):
         for k in ("x", "y", "z", "u", "v", "w"):
             assert np.array_equal(a[k], b[k])
         P.assert_moments(r1[1][s], r2[1][s], 1e-15)
+
+
+@pytest.mark.parametrize("variant", [0, 2])
+@pytest.mark.parametrize("group", [0, 4, 10])
+def test_tile_group_mapping_matches_slabs(spic, ctx, group, variant):
+    """Tiles dealt to the XCDs in groups of 2^group (4 is the default; 2^10
+    exceeds the 128 tiles here, so most workgroups find no tile) run the
+    same tile bodies as the XCD slabs: particles bitwise equal by id,
+    moments equal to rounding, and both match the oracle."""
+    h = W.harris_32x16x4()
+    f = W.make_fields(h)
+    sps = W.make_all_species(h)
+    ctx.set_option("tile_variant", variant)
+    ctx.set_option("tile_group", -1)
+    a_st, a_m = _gpu_steps(spic, ctx, h, f, sps, h.qoms, 3, sort_every=2)
+    ctx2 = spic.Context(0)
+    ctx2.set_option("tile_variant", variant)
+    ctx2.set_option("tile_group", group)
+    _say("case tile_group %d variant %d" % (group, variant))
+    b_st, b_m = _gpu_steps(spic, ctx2, h, f, sps, h.qoms, 3, sort_every=2)
+    ctx2.close()
+    ora, om = _oracle_steps(h, f, sps, h.qoms, 3)
+    for s in range(4):
+        a, b = P.by_id(a_st[s]), P.by_id(b_st[s])
+        for k in ("x", "y", "z", "u", "v", "w"):
+            assert np.array_equal(a[k], b[k]), k
+        P.assert_moments(b_m[s], a_m[s], 1e-14)
+        P.assert_state(b_st[s], ora[s], h.grid, P.POS64, P.VEL64)
+        P.assert_moments(b_m[s], om[s], P.MOM64)
