@@ -64,25 +64,48 @@ KERNEL_SOURCES = ("paper_2008_04397_amd/csrc/spic_tiled.hip", "paper_2008_04397_
                   "paper_2008_04397_amd/csrc/spic_impl.h")
 
 
-def measured_traffic(launch, dtype_name: str) -> Optional[float]:
-    """HBM bytes per species pass (the fused kernel, or the mover and
-    deposit kernels of the split variant) from the committed rocprofv3
-    FETCH_SIZE/WRITE_SIZE summary of that particle dtype, or None when the
-    kernel sources changed since the counters were taken or the launch
-    configuration differs."""
+SQ_PROFILE = os.path.join(HERE, "profiles", "sq_counters_harris_128x64x32_{}.md")
+
+
+def _profile_fields(path: str, launch) -> Optional[dict]:
+    """The `key: value` lines of a committed profile summary, or None when
+    the kernel sources changed since it was taken or the launch settings
+    differ from the profiled ones."""
     try:
-        txt = open(TRAFFIC_PROFILE.format(dtype_name)).read()
+        txt = open(path).read()
     except OSError:
         return None
     fields = dict(re.findall(r"^(\w+): (.*)$", txt, re.M))
     h = hashlib.sha256(b"".join(open(os.path.join(HERE, p), "rb").read() for p in KERNEL_SOURCES)).hexdigest()
     if fields.get("kernel_source_sha256", "").strip() != h:
         return None
-    cfg = fields.get("config", "")
-    profiled = {k: int(v) for k, v in re.findall(r"(\w+) (\d+)", cfg)}
+    profiled = {k: int(v) for k, v in re.findall(r"(\w+) (\d+)", fields.get("config", ""))}
     if any(launch.get(k) != profiled.get(k) for k in ("tile_variant", "tile_block", "bank_align", "sort_every")):
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    return fields
+
+
+def valu_ceiling(launch, dtype_name: str, bytes_per_pass: float) -> Optional[dict]:
+    """The VALU-issue ceiling of the species pass from the committed SQ
+    counters: VALU wave-instructions per particle-wave, the time they take
+    at one wave-instruction per CU clock (256 CUs x 2.4 GHz), and the HBM
+    fraction the pass could reach if it took only that long."""
+    fields = _profile_fields(SQ_PROFILE.format(dtype_name), launch)
+    if not fields or "valu_issue_us_per_pass" not in fields:
+        return None
+    us = float(fields["valu_issue_us_per_pass"])
+    return {"valu_per_particle_wave": float(fields["valu_per_particle_wave"]), "valu_issue_ms_per_pass": us / 1e3,
+            "hbm_frac_at_valu_issue": bytes_per_pass / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
+
+
+def measured_traffic(launch, dtype_name: str) -> Optional[float]:
+    """HBM bytes per species pass (the fused kernel, or the mover and
+    deposit kernels of the split variant) from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary of that particle dtype, or None when the
+    kernel sources changed since the counters were taken or the launch
+    configuration differs."""
+    fields = _profile_fields(TRAFFIC_PROFILE.format(dtype_name), launch)
+    return float(fields["traffic_bytes_per_launch"]) if fields else None
 
 
 def algorithmic_bytes(n_particles: int, nodes: int, s_p: int, s_f: int) -> float:
@@ -204,7 +227,8 @@ def run_gpu(h, dtype_name: str, steps: int, warmup: int, sort_every: int, path: 
                      "kernel": ("k_fused_tiled (mover) + k_deposit_tiled (sorted register deposit), one pair per "
                                 "species" if launch.get("tile_variant") == 2 else "k_fused_tiled (one launch per species)"),
                      "bytes_per_launch": per_launch_bytes, "avg_launch_ms": avg_launch_s * 1e3,
-                     "traffic_bytes_per_launch": traffic_bytes},
+                     "traffic_bytes_per_launch": traffic_bytes,
+                     "alu_ceiling": valu_ceiling(launch, dtype_name, per_launch_bytes) if not path else None},
     }
 
 
@@ -303,8 +327,16 @@ def bench_ensemble(args):
     tuned = autotune.load(key) if args.tune else None
     if args.tune and tuned is None:
         log("[bench] tuning the engine on the ensemble")
+        snap = [autotune.snapshot(sps) for _, _, sps, _ in data]
+
+        def reset():
+            for (_, _, sps, _), sn in zip(data, snap):
+                autotune.restore(sps, sn)
+
         tuned = autotune.tune_runs(lambda: _engine_ctx(variant=args.variant), make_runs,
-                                   autotune.engine_candidates(quick=True), steps=8, log=log)
+                                   autotune.engine_candidates(quick=True), steps=8, log=log, reset=reset)
+        reset()
+        del snap
         autotune.store(key, tuned)
     ctx = _engine_ctx(variant=args.variant)
     se = 4

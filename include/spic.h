@@ -189,14 +189,14 @@ int spic_version(void);
  *   grid_cap       cap on blocks of grid-stride kernels
  *   path           0 = tiled kernel for sorted species, 1 = unsorted path only
  *   tile_block     threads per block of the tiled kernel (64..512, x64; -1 =
- *                  by variant: 256 for variant 2's deposit launch, else 512)
+ *                  by variant: 512 for variant 0, else 256)
  *   tile_x/y/z     sort tile shape in cells (product <= 64)
  *   halo           cells of halo staged around a tile in LDS (0..8)
  *   lds_max        read only: LDS bytes a workgroup may use on the device
  *   tile_variant   tiled-kernel variant (0..2; -1 = by precision): 0 one
- *                  kernel, every deposit an FP64 LDS atomic (default for
- *                  FP64 particles); 1 as 0 with the 48 field values of a
- *                  thread's last cell in registers; 2 a mover launch, then
+ *                  kernel, every deposit an FP64 LDS atomic; 1 as 0 with
+ *                  the 48 field values of a thread's last cell in registers
+ *                  (default for FP64 particles); 2 a mover launch, then
  *                  a deposit launch into per-lane register sums of sorted
  *                  cells (default for FP32 particles)
  *   mover_cache    variant 2: 1 = the mover launch keeps the 48 field

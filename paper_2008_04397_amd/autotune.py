@@ -100,20 +100,35 @@ def candidates(quick: bool = True, dtype_name: str = "f32") -> Iterable[Dict[str
         yield c
 
 
+def snapshot(species) -> List[Dict]:
+    """Device copies of every species tensor (the state a trial starts from)."""
+    return [{k: v.clone() for k, v in sp.items()} for sp in species]
+
+
+def restore(species, snap) -> None:
+    for sp, sn in zip(species, snap):
+        for k, v in sp.items():
+            v.copy_(sn[k])
+
+
 def tune(h, fields, species, qoms, moments, steps: int = 16, quick: bool = True, log=None,
          dtype_name: str = "f32") -> Dict[str, int]:
     """Time `steps` fused steps (after a first sort) for every candidate on
     the given device-resident inputs; returns the fastest configuration.
-    The inputs are advanced in time by the trials (a real run's state).
-    `steps` is rounded up to a multiple of every candidate cadence, so each
-    trial pays its own sorts in full."""
+    Every trial starts from the same state (the inputs as given, restored
+    from a device copy), so no candidate meets particles that earlier trials
+    have spread, and the inputs are restored once more at the end.  `steps`
+    is rounded up to a multiple of every candidate cadence, so each trial
+    pays its own sorts in full."""
     import torch
     from . import spic
     best, best_ms = None, float("inf")
     cands = list(candidates(quick, dtype_name))
     period = _lcm(c["sort_every"] for c in cands)
     steps = -(-steps // period) * period
+    snap = snapshot(species)
     for cfg in cands:
+        restore(species, snap)
         ctx = spic.Context(0)
         apply(ctx, cfg)
         se = cfg["sort_every"]
@@ -129,6 +144,7 @@ def tune(h, fields, species, qoms, moments, steps: int = 16, quick: bool = True,
             log("[tune] %s -> %.3f ms/step" % (cfg, ms))
         if ms < best_ms:
             best, best_ms = cfg, ms
+    restore(species, snap)
     return best
 
 
@@ -152,18 +168,21 @@ def stream_candidates(quick: bool = True) -> List[Dict[str, int]]:
 
 
 def tune_runs(make_ctx: Callable[[], object], make_runs: Callable[[int, int], Sequence], cands: Sequence[Dict],
-              steps: int = 8, log=None) -> Dict[str, int]:
-    """Engine tuner.  For every candidate: a fresh context from make_ctx()
-    with the candidate's options, one untimed submission of 1 step (kernel
-    and engine warm-up), then `steps` steps of make_runs(sort_every, steps)
-    submitted together, timed from submission to the last spic_wait.
-    `steps` is rounded up to a multiple of every candidate cadence.  Returns
-    the fastest candidate."""
+              steps: int = 8, log=None, reset: Optional[Callable[[], None]] = None) -> Dict[str, int]:
+    """Engine tuner.  For every candidate: reset() (when given: put the
+    runs' inputs back to the state every trial starts from), a fresh context
+    from make_ctx() with the candidate's options, one untimed submission of
+    1 step (kernel and engine warm-up), then `steps` steps of
+    make_runs(sort_every, steps) submitted together, timed from submission
+    to the last spic_wait.  `steps` is rounded up to a multiple of every
+    candidate cadence.  Returns the fastest candidate."""
     from . import spic
     period = _lcm(c.get("sort_every", 1) for c in cands)
     steps = -(-steps // period) * period
     best, best_s = None, float("inf")
     for cfg in cands:
+        if reset is not None:
+            reset()
         ctx = make_ctx()
         try:
             apply(ctx, cfg)

@@ -67,14 +67,6 @@ struct LaunchCfg {
     size_t lds_max = 65536; // LDS bytes a workgroup may use on the device
 };
 
-// Tiled-kernel variants (spic_tiled.hip): 0 one kernel with LDS-atomic
-// deposits, 1 the same with the field corners of a thread's last cell in
-// registers, 2 two launches -- the mover, then the sorted deposit into
-// per-lane register sums.  Defaults, measured fastest on the Harris boxes:
-// 2 for FP32 particles, 0 for FP64 (its 80 register sums take 160 VGPRs,
-// which leaves the deposit two waves per SIMD and spills).  Workgroup size
-// when the options leave it to the library: 256 for the sorted deposit,
-// 512 for the one-kernel forms.
 // Default mapping of tiles to workgroups: groups of 16 consecutive tiles
 // dealt to the XCDs in turn.  Measured as fast as XCD slabs on resident
 // boxes, and it keeps a streamed batch (a contiguous eighth of the tiles)
@@ -90,9 +82,18 @@ inline int tile_chunk(int ntiles, int glog) {
     return ((ntiles + g - 1) / g + 7) / 8 * g;
 }
 
+// Tiled-kernel variants (spic_tiled.hip): 0 one kernel with LDS-atomic
+// deposits, 1 the same with the field corners of a thread's last cell in
+// registers, 2 two launches -- the mover, then the sorted deposit into
+// per-lane register sums.  Defaults, measured fastest on the Harris boxes:
+// 2 for FP32 particles, 1 for FP64 (the sorted deposit's 80 register sums
+// take 160 VGPRs in FP64, which leaves it two waves per SIMD and spills).
+// Workgroup size when the options leave it to the library: 512 for
+// variant 0, 256 otherwise (variant 1's FP64 corner cache allows two
+// waves per SIMD: two workgroups of 256 per CU).
 constexpr int kVariantSplit = 2;
-inline int auto_variant(int dtype, int) { return dtype == SPIC_F32 ? kVariantSplit : 0; }
-inline int auto_tile_block(int variant) { return variant == kVariantSplit ? 256 : 512; }
+inline int auto_variant(int dtype, int) { return dtype == SPIC_F32 ? kVariantSplit : 1; }
+inline int auto_tile_block(int variant) { return variant == 0 ? 512 : 256; }
 inline LaunchCfg resolve_cfg(LaunchCfg c, int dtype, int acc_dtype) {
     if (c.variant < 0) c.variant = auto_variant(dtype, acc_dtype);
     if (c.tile_block < 0) c.tile_block = auto_tile_block(c.variant);

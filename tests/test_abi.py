@@ -143,13 +143,13 @@ def test_options(hctx):
 def test_resolved_launch_comes_from_the_library(hctx):
     """Options left unset resolve inside the library (FP32 particles: the
     split variant, full rows, 256 deposit threads, the bank-preserving
-    layout; FP64: the one-kernel LDS-atomic variant at 512 threads, plain
-    rank blocks, the compact layout); the binding only reads the resolved
-    values."""
+    layout; FP64: the one-kernel variant with the corner cache at 256
+    threads, plain rank blocks, the compact layout); the binding only reads
+    the resolved values."""
     f32, f64 = spic.resolved_launch(hctx, "f32"), spic.resolved_launch(hctx, "f64")
-    assert f32["tile_variant"] == 2 and f64["tile_variant"] == 0
+    assert f32["tile_variant"] == 2 and f64["tile_variant"] == 1
     assert f32["tile_block"] == 256 and f32["sort_rows"] == 1 and f32["halo"] == 1
-    assert f64["tile_block"] == 512 and f64["sort_rows"] == 0
+    assert f64["tile_block"] == 256 and f64["sort_rows"] == 0
     assert f32["bank_align"] == 1 and f64["bank_align"] == 0 and f32["mover_halo"] == 2
     assert f32["tile_group"] == 4 and f64["tile_group"] == 4
     hctx.set_option("tile_variant", 0)

@@ -34,14 +34,19 @@ def test_tune_single_box_then_step_matches_oracle(dtype_name, tmp_path, monkeypa
     species = [spic.to_device(W.make_species(h, s, dtype=npdt), tdt) for s in range(4)]
     moms = spic.moment_buffers(h.grid, 4)
     _say("[autotune] tune() %s on 16x8x8" % dtype_name)
+    initial = [_host(s) for s in species]
     cfg = autotune.tune(h, f, species, h.qoms, moms, steps=4, quick=True, dtype_name=dtype_name)
     cands = list(autotune.candidates(True, dtype_name))
     assert cfg in cands
+    # the trials leave the inputs as they found them
+    for a, b in zip(initial, [_host(s) for s in species]):
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
     key = autotune.workload_class(dtype_name, h.grid, h.ppc)
     autotune.store(key, cfg)
     assert autotune.load(key) == cfg
-    # one step with the tuned settings from the state the trials left
-    start = [_host(s) for s in species]
+    # one step with the tuned settings
+    start = initial
     ctx = spic.Context(0)
     autotune.apply(ctx, cfg)
     assert spic.resolved_launch(ctx, dtype_name)["tile_block"] == cfg["tile_block"]
@@ -78,15 +83,18 @@ def test_tune_runs_on_an_ensemble_then_runs_match_oracle(tmp_path, monkeypatch):
         return [spic.Run(h.grid, spic.make_params(h.dt, h.c, h.niter, se, 0), f, dev, h.qoms, moms, k)
                 for h, f, _, dev, moms in data]
 
+    def reset():  # every trial (and the checked run) starts from the initial states
+        for h, f, sps, dev, moms in data:
+            for d, s in zip(dev, sps):
+                for k in d:
+                    d[k].copy_(torch.from_numpy(s[k]))
+
     cands = autotune.engine_candidates(quick=True)
     _say("[autotune] tune_runs() over %d candidates" % len(cands))
-    cfg = autotune.tune_runs(lambda: spic.Context(0), make_runs, cands, steps=2)
+    cfg = autotune.tune_runs(lambda: spic.Context(0), make_runs, cands, steps=2, reset=reset)
     assert cfg in cands
-    # fresh initial states, 3 steps with the tuned settings, vs the oracle
-    for h, f, sps, dev, moms in data:
-        for d, s in zip(dev, sps):
-            for k in d:
-                d[k].copy_(torch.from_numpy(s[k]))
+    # 3 steps with the tuned settings from the initial states, vs the oracle
+    reset()
     ctx = spic.Context(0)
     autotune.apply(ctx, cfg)
     for t in spic.spic_batch_submit(ctx, make_runs(cfg["sort_every"], 3)):
