@@ -529,6 +529,75 @@ def bench_cadence(args):
             "sustained_rate_last_fifth": sustained}
 
 
+def bench_field(args):
+    """The implicit field cycle (clean with CG, GMRes solve, update) on the
+    128x64x32 box, FP64, with the moments of one mover step of its four
+    species (FP32 particles, FP64 fields and moments).  Reports cycles per
+    second, the iterations, and the roofline of the field-operator kernel:
+    its algorithmic bytes per application are x (24 B), the susceptibility
+    (72 B) and y (24 B) per node, timed with HIP events over repeated
+    spic_field_apply calls."""
+    import torch
+    from paper_2008_04397_amd import spic
+    h = W.harris_128x64x32()
+    g = h.grid
+    N = g.nodes
+    f64 = spic.to_device(W.make_fields(h), torch.float64)
+    moms = spic.moment_buffers(g, 4, torch.float64)
+    ctx = _new_ctx(spic, 0)
+    species = [spic.to_device(W.make_species(h, s, dtype=np.float32, with_id=False), torch.float32)
+               for s in range(4)]
+    spic.spic_mover(ctx, g, spic.make_params(h.dt, h.c, h.niter, 1, 0), f64, species, h.qoms, moms)
+    torch.cuda.synchronize()
+    del species
+    torch.cuda.empty_cache()
+    fp = spic.make_field_params(h.dt, h.c, theta=1.0, tol=args.field_tol, max_iter=400, restart=30)
+    stream = torch.cuda.current_stream()
+    # the field operator alone (the residual's product)
+    x = torch.randn(3, N, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        spic.spic_field_apply(ctx, g, fp, f64, moms, h.qoms, x, y, stream=stream)
+    reps = 50
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(reps):
+        spic.spic_field_apply(ctx, g, fp, f64, moms, h.qoms, x, y, stream=stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    call_ms = a.elapsed_time(b) / reps
+    # whole cycles, fields advanced in place
+    stats = [spic.spic_field_cycle(ctx, g, fp, f64, moms, h.qoms, stream=stream)]  # warm-up
+    cycles = max(1, args.steps // 4)
+    t0 = time.perf_counter()
+    for _ in range(cycles):
+        stats.append(spic.spic_field_cycle(ctx, g, fp, f64, moms, h.qoms, stream=stream))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.close()
+    timed = stats[1:]
+    iters = sum(s.solve_iters for s in timed)
+    bytes_apply = 120.0 * N
+    return {"metric": "field cycles/s (CG cleaning + GMRes implicit field solve + update)", "mode": "field",
+            "value": cycles / wall, "unit": "cycles/s", "n_gpus": 1, "steps": cycles, "higher_is_better": True,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "harris_128x64x32_field_cycle", "nodes": N, "theta": 1.0, "tol": args.field_tol,
+                       "restart": 30, "moments": "one mover step of the 4 species"},
+            "ms_per_cycle": wall / cycles * 1e3,
+            "gmres_iters_per_cycle": iters / cycles, "cg_iters_per_cycle": sum(s.clean_iters for s in timed) / cycles,
+            "ms_per_gmres_iter": wall / max(1, iters) * 1e3,
+            "final_resid": [s.solve_resid for s in timed],
+            "roofline": {"bound": "hbm", "kernel": "k_apply (field operator)",
+                         "achieved": bytes_apply / (call_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": bytes_apply / (call_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                         "bytes_per_launch": bytes_apply,
+                         "avg_call_ms": call_ms,
+                         "note": "spic_field_apply calls timed with events: the susceptibility kernel (recomputed "
+                                 "each call) and the operator kernel; the kernel alone is in the rocprofv3 "
+                                 "summary"}}
+
+
 def bench_serving(args):
     """Poisson request stream: continuous batching vs one at a time."""
     import torch
@@ -563,7 +632,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--sort-every", type=int, default=-1, help="-1: the autotuned cadence")
-    ap.add_argument("--mode", default="main", choices=("main", "ensemble", "streamed", "serving", "cadence"))
+    ap.add_argument("--mode", default="main", choices=("main", "ensemble", "streamed", "serving", "cadence", "field"))
+    ap.add_argument("--field-tol", type=float, default=1e-8, help="field mode: relative residual target")
     ap.add_argument("--fraction", type=float, default=1.0)
     ap.add_argument("--requests", type=int, default=120)
     ap.add_argument("--rate", type=float, default=20.0, help="serving: mean request arrivals per second")
@@ -602,7 +672,7 @@ def main():
     spic.lib()  # fail loudly if the HIP library is missing
     if args.mode != "main":
         out = {"ensemble": bench_ensemble, "streamed": bench_streamed, "serving": bench_serving,
-               "cadence": bench_cadence}[args.mode](args)
+               "cadence": bench_cadence, "field": bench_field}[args.mode](args)
         print(json.dumps(out), flush=True)
         return
 

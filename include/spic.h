@@ -331,6 +331,85 @@ int spic_wait(spic_ctx ctx, uint64_t ticket, double *device_seconds_out);
 /* *done = 1 when the ticket's run is complete, else 0. */
 int spic_poll(spic_ctx ctx, uint64_t ticket, int32_t *done);
 
+/* ------------------------------------------------------------ field solve */
+
+/* The implicit field solve that closes the cycle (Sec. II, step 3: a linear
+ * system from the implicit-in-time discretisation of Maxwell's equations,
+ * solved with GMRes, and a Poisson equation solved with CG each cycle so
+ * that the continuity equation holds -- "divergence cleaning"; Sec. VI
+ * names the solver's residual as the next GPU port).  The paper prints no
+ * discretisation; the one used (FP64 throughout) is:
+ *   grid      the periodic node grid of the particle step; vectors are
+ *             [3][nodes] FP64 device arrays (x, y, z components);
+ *   D_d       central differences (f(+e_d) - f(-e_d)) / (2 dx_d); curl,
+ *             div and grad are built from them; the Poisson operator is
+ *             div grad;
+ *   mu        susceptibility at a node: sum over species s of
+ *             (fourpi / 2) theta dt^2 qom_s rho_s R(b_s), b_s =
+ *             qom_s dt B / (2 c), R(b) the rotation of the mover's Eq. 2
+ *             (R v solves vhat = v + vhat x b);
+ *   Jhat      implicit current: sum_s R(b_s) (J_s - dt/2 div P_s),
+ *             (div P)_a = sum_b D_b P_ab, from the species' moments
+ *             (rho, J, P as spic_moment_array orders them);
+ *   equation  (I + mu) E' + (c theta dt)^2 curl curl E'
+ *                 = E + theta dt (c curl B - fourpi Jhat)
+ *             for E' = E^{n+theta};
+ *   update    E <- (E' - (1 - theta) E) / theta, B <- B - c dt curl E';
+ *   cleaning  before the solve, E <- E - grad phi with
+ *             div grad phi = div E - fourpi rho_bar (CG), rho_bar the total
+ *             charge density without its components along the null space
+ *             of div grad (the modes constant or alternating along each
+ *             axis; alternating only where the node count is even). */
+typedef struct {
+    double dt;
+    double c;
+    double theta;      /* time centring, in (0, 1] */
+    double fourpi;     /* 4 pi of the unit system (>= 0) */
+    double tol;        /* relative residual target of both solves, in (0, 1) */
+    int32_t max_iter;  /* cap on the iterations of each solve, >= 1 */
+    int32_t restart;   /* GMRes Krylov basis size, 1..64 */
+} spic_field_params;
+
+/* E and B of the field cycle: six FP64 device arrays of `nodes` elements
+ * (flat node index (i * ny + j) * nz + k), read and overwritten in place by
+ * spic_field_cycle, read only by spic_field_apply. */
+typedef struct {
+    double *ex, *ey, *ez, *bx, *by, *bz;
+} spic_em_state;
+
+/* Iterations and final relative residuals of one field cycle: clean_resid
+ * is the CG recurrence residual |r| / |r0|, solve_resid the true residual
+ * |b - A E'| / |b| of the GMRes result. */
+typedef struct {
+    int32_t clean_iters;
+    int32_t solve_iters;
+    double clean_resid;
+    double solve_resid;
+} spic_field_stats;
+
+/* y = (I + mu) x + (c theta dt)^2 curl curl x: the field operator (the
+ * residual's matrix-vector product) for the susceptibility of the given
+ * moments and B.
+ *  em           B is read (E is not used); FP64 device arrays
+ *  mom[nsp]     SPIC_F64 moment arrays of the species ([10][nodes])
+ *  qom[nsp]     host array of the species' charge-to-mass ratios
+ *  x, y         [3][nodes] FP64 device arrays (distinct)
+ * Enqueued on hip_stream; library scratch of 12 nodes doubles.
+ * Errors: SPIC_E_ARG (validation; nsp in 0..16), SPIC_E_BUDGET, SPIC_E_HIP. */
+int spic_field_apply(spic_ctx ctx, const spic_grid *grid, const spic_field_params *params,
+                     const spic_em_state *em, const spic_moment_array *mom, const double *qom, int32_t nsp,
+                     const double *x, double *y, void *hip_stream);
+
+/* One field cycle: clean E (CG), solve the field equation for E' (GMRes,
+ * restarted every params->restart iterations, from the cleaned E), update E
+ * and B in place.  Synchronous: the host drives both solves and the call
+ * returns when the update is done (stats, when not NULL, are filled).
+ * Library scratch: about (9 + 6 x 3 + 5 + 3 (restart + 1)) nodes doubles.
+ * Errors: SPIC_E_ARG (validation), SPIC_E_BUDGET, SPIC_E_HIP. */
+int spic_field_cycle(spic_ctx ctx, const spic_grid *grid, const spic_field_params *params, spic_em_state *em,
+                     const spic_moment_array *mom, const double *qom, int32_t nsp, spic_field_stats *stats,
+                     void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

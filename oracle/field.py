@@ -194,7 +194,9 @@ def clean(g, fields, moments, fourpi: float) -> Tuple[np.ndarray, np.ndarray]:
     """Divergence cleaning of E: (E_clean [3, N], phi)."""
     _, _, _, _, div, grad, _ = operators(g)
     E = np.stack([np.asarray(fields[k], np.float64) for k in ("ex", "ey", "ez")])
-    rho = sum(np.asarray(m[0], np.float64) for m in moments)
+    rho = np.zeros(g.nx * g.ny * g.nz)  # no species: vacuum
+    for m in moments:
+        rho = rho + np.asarray(m[0], np.float64)
     r = div @ E.ravel() - fourpi * project_range(g, rho)
     phi = poisson_fft(g, project_range(g, r))
     return E - (grad @ phi).reshape(3, -1), phi

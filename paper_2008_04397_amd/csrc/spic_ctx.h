@@ -101,6 +101,15 @@ struct spic_ctx_s {
     int noalloc_check(const spic_grid &g, const spic_species *sp, int32_t nsp, const spic_moment_array *mom);
     int mover_noalloc(const spic_grid &g, const spic_params &p, const spic_fields &f, spic_species *sp,
                       int32_t nsp, spic_moment_array *mom, hipStream_t s);
+    // the field solve (spic_field.hip)
+    int check_field(const spic_grid *g, const spic_field_params *fp, const spic_em_state *em,
+                    const spic_moment_array *mom, const double *qom, int32_t nsp);
+    int field_apply(const spic_grid &g, const spic_field_params &fp, const spic_em_state &em,
+                    const spic_moment_array *mom, const double *qom, int32_t nsp, const double *x, double *y,
+                    hipStream_t s);
+    int field_cycle(const spic_grid &g, const spic_field_params &fp, spic_em_state &em,
+                    const spic_moment_array *mom, const double *qom, int32_t nsp, spic_field_stats *stats,
+                    hipStream_t s);
     int sort_prepare(const spic_grid &g, const spic_species *sp, int32_t nsp, size_t &need);
     int sort_one(const spic_grid &g, const spic_species &sp, const spic::TileGeom &tg, size_t need, hipStream_t s,
                  uint32_t **toff_out, spic::SpeciesWork *sorted_out);

@@ -96,6 +96,37 @@ int spic_ctx_s::check_fields(const spic_fields *f) {
     return SPIC_OK;
 }
 
+int spic_ctx_s::check_field(const spic_grid *g, const spic_field_params *fp, const spic_em_state *em,
+                            const spic_moment_array *mom, const double *qom, int32_t nsp) {
+    int rc;
+    if ((rc = check_grid(g))) return rc;
+    if (!fp) return fail(SPIC_E_ARG, "field params is NULL");
+    if (!(fp->dt > 0.0) || !std::isfinite(fp->dt)) return fail(SPIC_E_ARG, "field params: dt must be finite and > 0");
+    if (!(fp->c > 0.0) || !std::isfinite(fp->c)) return fail(SPIC_E_ARG, "field params: c must be finite and > 0");
+    if (!(fp->theta > 0.0 && fp->theta <= 1.0)) return fail(SPIC_E_ARG, "field params: theta must be in (0, 1]");
+    if (!(fp->fourpi >= 0.0) || !std::isfinite(fp->fourpi))
+        return fail(SPIC_E_ARG, "field params: fourpi must be finite and >= 0");
+    if (!(fp->tol > 0.0 && fp->tol < 1.0)) return fail(SPIC_E_ARG, "field params: tol must be in (0, 1)");
+    if (fp->max_iter < 1) return fail(SPIC_E_ARG, "field params: max_iter must be >= 1");
+    if (fp->restart < 1 || fp->restart > 64) return fail(SPIC_E_ARG, "field params: restart must be in 1..64");
+    if (!em) return fail(SPIC_E_ARG, "em state is NULL");
+    const double *p[6] = {em->ex, em->ey, em->ez, em->bx, em->by, em->bz};
+    for (int i = 0; i < 6; ++i) {
+        if (!p[i]) return fail(SPIC_E_ARG, "em array %d is NULL", i);
+        if ((uintptr_t)p[i] % 8) return fail(SPIC_E_ARG, "em array %d is misaligned", i);
+    }
+    if (nsp < 0 || nsp > 16) return fail(SPIC_E_ARG, "field solve: nsp must be in 0..16");
+    if (nsp > 0 && (!mom || !qom)) return fail(SPIC_E_ARG, "field solve: moments or qom array is NULL");
+    for (int s = 0; s < nsp; ++s) {
+        if (mom[s].acc_dtype != SPIC_F64)
+            return fail(SPIC_E_ARG, "field solve: species %d moments must be SPIC_F64", s);
+        if (mom[s].reserved != 0) return fail(SPIC_E_ARG, "field solve: species %d moments.reserved must be 0", s);
+        if (!mom[s].m || (uintptr_t)mom[s].m % 8) return fail(SPIC_E_ARG, "field solve: species %d moments", s);
+        if (!std::isfinite(qom[s])) return fail(SPIC_E_ARG, "field solve: species %d qom is not finite", s);
+    }
+    return SPIC_OK;
+}
+
 int spic_ctx_s::check_species(const spic_species *sp, int32_t nsp, bool allow_host) {
     if (nsp < 0) return fail(SPIC_E_ARG, "nsp must be >= 0");
     if (nsp > 0 && !sp) return fail(SPIC_E_ARG, "species array is NULL");
@@ -418,6 +449,34 @@ int spic_sort(spic_ctx ctx, const spic_grid *grid, spic_species *sp, int32_t nsp
     if (ctx->device < 0) return ctx->host_only();
     DeviceGuard dg(ctx->device);
     return ctx->sort(*grid, sp, nsp, (hipStream_t)hip_stream);
+}
+
+int spic_field_apply(spic_ctx ctx, const spic_grid *grid, const spic_field_params *params,
+                     const spic_em_state *em, const spic_moment_array *mom, const double *qom, int32_t nsp,
+                     const double *x, double *y, void *hip_stream) {
+    if (!ctx) return SPIC_E_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->err.clear();
+    int rc;
+    if ((rc = ctx->check_field(grid, params, em, mom, qom, nsp))) return rc;
+    if (!x || !y || x == y || (uintptr_t)x % 8 || (uintptr_t)y % 8)
+        return ctx->fail(SPIC_E_ARG, "field apply: x and y must be distinct, aligned, non-NULL");
+    if (ctx->device < 0) return ctx->host_only();
+    DeviceGuard dg(ctx->device);
+    return ctx->field_apply(*grid, *params, *em, mom, qom, nsp, x, y, (hipStream_t)hip_stream);
+}
+
+int spic_field_cycle(spic_ctx ctx, const spic_grid *grid, const spic_field_params *params, spic_em_state *em,
+                     const spic_moment_array *mom, const double *qom, int32_t nsp, spic_field_stats *stats,
+                     void *hip_stream) {
+    if (!ctx) return SPIC_E_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->err.clear();
+    int rc;
+    if ((rc = ctx->check_field(grid, params, em, mom, qom, nsp))) return rc;
+    if (ctx->device < 0) return ctx->host_only();
+    DeviceGuard dg(ctx->device);
+    return ctx->field_cycle(*grid, *params, *em, mom, qom, nsp, stats, (hipStream_t)hip_stream);
 }
 
 int spic_batch_submit(spic_ctx ctx, const spic_run *runs, int32_t nruns, uint64_t *tickets_out) {

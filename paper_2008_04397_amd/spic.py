@@ -22,7 +22,8 @@ SPIC_F32, SPIC_F64, SPIC_F32C = 1, 2, 3
 
 EXPORTED = ("spic_ctx_create", "spic_ctx_destroy", "spic_last_error", "spic_status_str", "spic_version",
             "spic_set_option", "spic_get_option", "spic_mover", "spic_moments", "spic_sort",
-            "spic_batch_submit", "spic_wait", "spic_poll", "spic_mover_noalloc")
+            "spic_batch_submit", "spic_wait", "spic_poll", "spic_mover_noalloc", "spic_field_apply",
+            "spic_field_cycle")
 
 
 class SpicError(RuntimeError):
@@ -54,6 +55,20 @@ class spic_species(C.Structure):
 
 class spic_moment_array(C.Structure):
     _fields_ = [("acc_dtype", C.c_int32), ("reserved", C.c_int32), ("m", C.c_void_p)]
+
+
+class spic_field_params(C.Structure):
+    _fields_ = [("dt", C.c_double), ("c", C.c_double), ("theta", C.c_double), ("fourpi", C.c_double),
+                ("tol", C.c_double), ("max_iter", C.c_int32), ("restart", C.c_int32)]
+
+
+class spic_em_state(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("ex", "ey", "ez", "bx", "by", "bz")]
+
+
+class spic_field_stats(C.Structure):
+    _fields_ = [("clean_iters", C.c_int32), ("solve_iters", C.c_int32), ("clean_resid", C.c_double),
+                ("solve_resid", C.c_double)]
 
 
 class spic_run(C.Structure):
@@ -92,6 +107,12 @@ def lib():
         L.spic_batch_submit.argtypes = [vp, C.POINTER(spic_run), C.c_int32, C.POINTER(C.c_uint64)]
         L.spic_wait.argtypes = [vp, C.c_uint64, C.POINTER(C.c_double)]
         L.spic_poll.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int32)]
+        L.spic_field_apply.argtypes = [vp, C.POINTER(spic_grid), C.POINTER(spic_field_params),
+                                       C.POINTER(spic_em_state), C.POINTER(spic_moment_array),
+                                       C.POINTER(C.c_double), C.c_int32, vp, vp, vp]
+        L.spic_field_cycle.argtypes = [vp, C.POINTER(spic_grid), C.POINTER(spic_field_params),
+                                       C.POINTER(spic_em_state), C.POINTER(spic_moment_array),
+                                       C.POINTER(C.c_double), C.c_int32, C.POINTER(spic_field_stats), vp]
         for f in EXPORTED:
             if f not in ("spic_last_error", "spic_status_str"):
                 getattr(L, f).restype = C.c_int
@@ -253,6 +274,46 @@ def spic_mover_noalloc(ctx: Context, grid, params: spic_params, fields, species:
     st = lib().spic_mover_noalloc(ctx.handle, C.byref(g), C.byref(params), C.byref(f), sp, len(species), mom,
                                   _stream(stream))
     return st if raw else ctx.check(st)
+
+
+def make_field_params(dt: float, c: float = 1.0, theta: float = 1.0, fourpi: float = 4.0 * np.pi,
+                      tol: float = 1e-10, max_iter: int = 200, restart: int = 30) -> spic_field_params:
+    return spic_field_params(float(dt), float(c), float(theta), float(fourpi), float(tol), int(max_iter),
+                             int(restart))
+
+
+def make_em(fields: dict) -> spic_em_state:
+    """spic_em_state of six FP64 device tensors keyed ex..bz."""
+    return spic_em_state(*[_ptr(fields[k]) for k in ("ex", "ey", "ez", "bx", "by", "bz")])
+
+
+def spic_field_apply(ctx: Context, grid, fparams: spic_field_params, fields: dict, moments: Sequence,
+                     qoms: Sequence[float], x, y, stream=None, raw: bool = False) -> int:
+    """y = the field operator applied to x ([3, nodes] FP64 device tensors)."""
+    g = make_grid(grid)
+    em = make_em(fields)
+    mom = _arr(spic_moment_array, [make_moments(m) for m in moments]) if len(moments) else None
+    q = (C.c_double * max(1, len(qoms)))(*[float(v) for v in qoms])
+    st = lib().spic_field_apply(ctx.handle, C.byref(g), C.byref(fparams), C.byref(em), mom, q, len(moments),
+                                _ptr(x), _ptr(y), _stream(stream))
+    return st if raw else ctx.check(st)
+
+
+def spic_field_cycle(ctx: Context, grid, fparams: spic_field_params, fields: dict, moments: Sequence,
+                     qoms: Sequence[float], stream=None, raw: bool = False):
+    """One field cycle on six FP64 device tensors (updated in place); returns
+    the spic_field_stats (or the status with raw=True)."""
+    g = make_grid(grid)
+    em = make_em(fields)
+    mom = _arr(spic_moment_array, [make_moments(m) for m in moments]) if len(moments) else None
+    q = (C.c_double * max(1, len(qoms)))(*[float(v) for v in qoms])
+    stats = spic_field_stats()
+    st = lib().spic_field_cycle(ctx.handle, C.byref(g), C.byref(fparams), C.byref(em), mom, q, len(moments),
+                                C.byref(stats), _stream(stream))
+    if raw:
+        return st
+    ctx.check(st)
+    return stats
 
 
 def spic_moments(ctx: Context, grid, species: Sequence[dict], moments: Sequence, accumulate: bool = False,

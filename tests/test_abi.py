@@ -346,3 +346,55 @@ def test_noalloc_step_validation_on_a_host_only_context(hctx):
     big.n = 8_000_000  # FP64, about 90 bytes of sort scratch per particle
     assert call(spic.make_params(0.25, 1.0, 3, 1, 0), big) == spic.SPIC_E_BUDGET
     assert "SPIC_NOALLOC_SCRATCH_BYTES" in L.spic_last_error(hctx.handle).decode()
+
+
+def _field_call(ctx, fp, arrs, nsp=2, qoms=(-64.0, 1.0), mutate=None, apply=False):
+    g = spic.make_grid(W.Grid(8, 8, 8))
+    em = spic.make_em(arrs.f)
+    moms = (spic.spic_moment_array * 2)(spic.make_moments(arrs.m), spic.make_moments(arrs.m))
+    q = (C.c_double * 2)(*qoms)
+    x = np.zeros((3, 512))
+    y = np.zeros((3, 512))
+    if mutate:
+        mutate(g, fp, em, moms, x, y)
+    L = spic.lib()
+    if apply:
+        yp = x.ctypes.data if mutate and getattr(mutate, "same", False) else y.ctypes.data
+        return L.spic_field_apply(ctx.handle, C.byref(g), C.byref(fp), C.byref(em), moms, q, nsp,
+                                  x.ctypes.data, yp, None)
+    st = spic.spic_field_stats()
+    return L.spic_field_cycle(ctx.handle, C.byref(g), C.byref(fp), C.byref(em), moms, q, nsp, C.byref(st), None)
+
+
+@pytest.mark.parametrize("what,mut,code", [
+    ("valid", None, spic.SPIC_E_STATE),
+    ("dt 0", lambda g, fp, em, m, x, y: setattr(fp, "dt", 0.0), spic.SPIC_E_ARG),
+    ("c nan", lambda g, fp, em, m, x, y: setattr(fp, "c", float("nan")), spic.SPIC_E_ARG),
+    ("theta 0", lambda g, fp, em, m, x, y: setattr(fp, "theta", 0.0), spic.SPIC_E_ARG),
+    ("theta > 1", lambda g, fp, em, m, x, y: setattr(fp, "theta", 1.5), spic.SPIC_E_ARG),
+    ("fourpi < 0", lambda g, fp, em, m, x, y: setattr(fp, "fourpi", -1.0), spic.SPIC_E_ARG),
+    ("tol 1", lambda g, fp, em, m, x, y: setattr(fp, "tol", 1.0), spic.SPIC_E_ARG),
+    ("max_iter 0", lambda g, fp, em, m, x, y: setattr(fp, "max_iter", 0), spic.SPIC_E_ARG),
+    ("restart 65", lambda g, fp, em, m, x, y: setattr(fp, "restart", 65), spic.SPIC_E_ARG),
+    ("null bz", lambda g, fp, em, m, x, y: setattr(em, "bz", None), spic.SPIC_E_ARG),
+    ("f32 moments", lambda g, fp, em, m, x, y: setattr(m[1], "acc_dtype", spic.SPIC_F32), spic.SPIC_E_ARG),
+    ("bad grid", lambda g, fp, em, m, x, y: setattr(g, "nx", 1), spic.SPIC_E_ARG),
+])
+@pytest.mark.parametrize("apply", [False, True])
+def test_field_solve_validation(hctx, what, mut, code, apply):
+    a = _HostArrays()
+    fp = spic.make_field_params(0.25)
+    st = _field_call(hctx, fp, a, mutate=mut, apply=apply)
+    assert st == code, (what, spic.lib().spic_last_error(hctx.handle))
+
+
+def test_field_solve_species_count_and_aliasing(hctx):
+    a = _HostArrays()
+    fp = spic.make_field_params(0.25)
+    assert _field_call(hctx, fp, a, nsp=17) == spic.SPIC_E_ARG
+    assert _field_call(hctx, fp, a, nsp=0) == spic.SPIC_E_STATE  # vacuum is valid
+
+    def same(g, fp, em, m, x, y):
+        pass
+    same.same = True
+    assert _field_call(hctx, fp, a, mutate=same, apply=True) == spic.SPIC_E_ARG  # x == y

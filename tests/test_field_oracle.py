@@ -224,3 +224,15 @@ def test_f10_theta_one_update():
     B0 = np.stack([f[k] for k in ("bx", "by", "bz")])
     B1 = np.stack([new[k] for k in ("bx", "by", "bz")])
     assert np.allclose(B1, B0 - c * dt * (curl @ E1.ravel()).reshape(3, -1), atol=1e-13)
+
+
+def test_f11_vacuum_cycle():
+    """No species: no susceptibility or current; cleaning removes div E."""
+    g = _grid(6, 4, 5)
+    rng = np.random.default_rng(9)
+    f = _fields(g, rng, 0.1)
+    new = F.field_cycle(g, f, [], [], 0.25, 1.0, 0.5, 4 * np.pi)
+    _, _, _, curl, div, grad, lap = F.operators(g)
+    Ec, _ = F.clean(g, f, [], 4 * np.pi)
+    assert np.abs(div @ Ec.ravel()).max() < 1e-12 * np.abs(Ec).max() / min(F.spacing(g))
+    assert all(np.all(np.isfinite(v)) for v in new.values())
