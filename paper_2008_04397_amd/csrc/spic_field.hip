@@ -45,9 +45,12 @@ struct Species {
     int n;
 };
 
+// a + d wrapped into [0, n) for |d| <= 2 <= n (the grid has at least two
+// nodes per axis): one conditional add or subtract, no division
 __device__ __forceinline__ int wrapi(int a, int n) {
-    a %= n;
-    return a < 0 ? a + n : a;
+    a += a < 0 ? n : 0;
+    a -= a >= n ? n : 0;
+    return a;
 }
 
 // flat index of node (i + di, j + dj, k + dk), periodic
