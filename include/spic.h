@@ -202,6 +202,8 @@ int spic_version(void);
  *   mover_cache    variant 2: 1 = the mover launch keeps the 48 field
  *                  values of a thread's last cell in registers (default), 0 =
  *                  every gather reads LDS
+ *   mover_block    variant 2: threads per workgroup of the mover launch
+ *                  (64..512, x64; default 512)
  *   mover_halo     variant 2: cells of halo of the mover launch's field
  *                  region (-1..8; -1 = the tile halo + 1; a region too large
  *                  for the device's LDS falls back to the tile halo)

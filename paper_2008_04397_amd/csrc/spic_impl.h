@@ -63,6 +63,7 @@ struct LaunchCfg {
     int fixed_geo = 1;      // compile-time region geometry for the default tiling
     int mover_halo = -1;    // variant 2: halo of the mover's field region (-1: tile halo + 1)
     int mover_cache = 1;    // variant 2: the mover keeps the last cell's field corners in registers
+    int mover_block = 512;  // variant 2: threads per workgroup of the mover launch
     int tile_group = 4;     // tiles to workgroups: g >= 0 groups of 2^g tiles dealt to the XCDs, -1 XCD slabs
     size_t lds_max = 65536; // LDS bytes a workgroup may use on the device
 };
@@ -220,6 +221,9 @@ using GeoDense = GeoFixed<4, 4, 4, 1, 2, 0, 1, 2>;
 // the mover launch of the split variant: two cells of halo (particles that
 // drifted since the last sort still gather from LDS)
 using GeoMover2 = GeoFixed<4, 4, 4, 2, 2, 0, 1>;
+// the compact conflict-free layout (the FP64 default of the one-kernel
+// variants)
+using GeoCompact = GeoFixed<4, 4, 4, 1, 2, 0, 1, 0>;
 
 // The tiled kernels address particle arrays with 32-bit byte offsets.
 inline bool tiled_fits(int64_t n, int dtype) {

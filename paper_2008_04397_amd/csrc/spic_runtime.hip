@@ -237,6 +237,7 @@ static const char *const kOptionNames[] = {
     "srpt_aging",   // batch engine: credit, in M particle-steps per second waited, against starvation
     "mover_halo",   // variant 2: halo of the mover's field region (-1: tile halo + 1)
     "mover_cache",  // variant 2: 1 = the mover keeps the last cell's field corners in registers
+    "mover_block",  // variant 2: threads per workgroup of the mover launch (64..512, x64; default 512)
     "tile_group",   // tiles to workgroups: groups of 2^v tiles dealt to the XCDs (default 4); -1 XCD slabs
 };
 
@@ -254,6 +255,7 @@ LaunchCfg spic_ctx_s::launch_cfg() const {
     c.fixed_geo = (int)opt("fixed_geo", 1);
     c.mover_halo = (int)opt("mover_halo", -1);
     c.mover_cache = (int)opt("mover_cache", 1);
+    c.mover_block = (int)opt("mover_block", 512);
     c.tile_group = (int)opt("tile_group", kTileGroup);
     c.lds_max = lds_max;
     return c;
@@ -329,6 +331,8 @@ int spic_set_option(spic_ctx ctx, const char *key, int64_t value) {
                 return ctx->fail(SPIC_E_ARG, "grid_cap must be in [1, 2^24]");
             if (!strcmp(key, "path") && (value < 0 || value > 1))
                 return ctx->fail(SPIC_E_ARG, "path must be 0 (auto) or 1 (generic)");
+            if (!strcmp(key, "mover_block") && (value < 64 || value > 512 || value % 64))
+                return ctx->fail(SPIC_E_ARG, "mover_block must be a multiple of 64 in [64, 512]");
             if (!strcmp(key, "tile_block") && value != -1 && (value < 64 || value > 512 || value % 64))
                 return ctx->fail(SPIC_E_ARG, "tile_block must be -1 or a multiple of 64 in [64, 512]");
             if ((!strcmp(key, "tile_x") || !strcmp(key, "tile_y") || !strcmp(key, "tile_z")) &&

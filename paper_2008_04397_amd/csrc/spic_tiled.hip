@@ -903,13 +903,13 @@ static void split_launch(const TileJob<TP, TF, TA> &job, int chunk, const Launch
     const bool same = mv.tg.halo == tg.halo;
     const bool m2 = cfg.fixed_geo && geo_is<GeoMover2>(mv.tg);
     if (cfg.mover_cache) {
-        if (same) fused_launch<TP, TF, TA, true, true, GEO>(mv, chunk, cfg.tile_group, fl, 512, s);
-        else if (m2) fused_launch<TP, TF, TA, true, true, GeoMover2>(mv, chunk, cfg.tile_group, fl, 512, s);
-        else fused_launch<TP, TF, TA, true, true, GeoRuntime>(mv, chunk, cfg.tile_group, fl, 512, s);
+        if (same) fused_launch<TP, TF, TA, true, true, GEO>(mv, chunk, cfg.tile_group, fl, cfg.mover_block, s);
+        else if (m2) fused_launch<TP, TF, TA, true, true, GeoMover2>(mv, chunk, cfg.tile_group, fl, cfg.mover_block, s);
+        else fused_launch<TP, TF, TA, true, true, GeoRuntime>(mv, chunk, cfg.tile_group, fl, cfg.mover_block, s);
     } else {
-        if (same) fused_launch<TP, TF, TA, false, true, GEO>(mv, chunk, cfg.tile_group, fl, 512, s);
-        else if (m2) fused_launch<TP, TF, TA, false, true, GeoMover2>(mv, chunk, cfg.tile_group, fl, 512, s);
-        else fused_launch<TP, TF, TA, false, true, GeoRuntime>(mv, chunk, cfg.tile_group, fl, 512, s);
+        if (same) fused_launch<TP, TF, TA, false, true, GEO>(mv, chunk, cfg.tile_group, fl, cfg.mover_block, s);
+        else if (m2) fused_launch<TP, TF, TA, false, true, GeoMover2>(mv, chunk, cfg.tile_group, fl, cfg.mover_block, s);
+        else fused_launch<TP, TF, TA, false, true, GeoRuntime>(mv, chunk, cfg.tile_group, fl, cfg.mover_block, s);
     }
     if (!job.mom) return;
     TileJob<TP, TF, TA> dj = job;
@@ -947,6 +947,16 @@ static void tiled_t(const spic_grid &g, const spic_params &prm, const spic_field
     const size_t lds = tiled_lds_bytes(tg, sizeof(TP) == 8 ? SPIC_F64 : SPIC_F32,
                                        sizeof(TA) == 8 ? SPIC_F64 : SPIC_F32, cfg.variant, cfg.tile_block);
     const auto job = make_tile_job<TP, TF, TA>(g, prm, f, w, tg, tile_off);
+    if constexpr (sizeof(TP) == 8) {  // FP64 particles: the one-kernel variants in the compact layout
+        if (cfg.fixed_geo && cfg.variant != kVariantSplit && geo_is<GeoCompact>(tg)) {
+            if (cfg.variant == 1)
+                fused_launch<TP, TF, TA, true, false, GeoCompact>(job, chunk, cfg.tile_group, lds, cfg.tile_block, s);
+            else
+                fused_launch<TP, TF, TA, false, false, GeoCompact>(job, chunk, cfg.tile_group, lds, cfg.tile_block,
+                                                                   s);
+            return;
+        }
+    }
     if (geo_is_default(tg) && cfg.fixed_geo) tiled_variant<TP, TF, TA, GeoDefault>(job, chunk, lds, cfg, s);
     else tiled_variant<TP, TF, TA, GeoRuntime>(job, chunk, lds, cfg, s);
 }
