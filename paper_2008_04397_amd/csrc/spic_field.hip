@@ -178,15 +178,6 @@ __global__ void k_apply(Geo g, int64_t N, const double *__restrict__ mu, const d
     }
 }
 
-// y = -div grad x (positive semidefinite; definite on the range)
-__global__ void k_neg_lap(Geo g, int64_t N, const double *__restrict__ x, double *__restrict__ y) {
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
-        int i, j, k;
-        node_ijk(g, p, i, j, k);
-        y[p] = -(dif2(g, x, i, j, k, 0, 0) + dif2(g, x, i, j, k, 1, 1) + dif2(g, x, i, j, k, 2, 2));
-    }
-}
-
 // b = fourpi rho - div E (the right-hand side of -div grad phi = -(div E - fourpi rho))
 __global__ void k_poisson_rhs(Geo g, int64_t N, const double *__restrict__ E, const double *__restrict__ rho,
                               double fourpi, double *__restrict__ b) {
@@ -358,32 +349,62 @@ __global__ void k_sub(int64_t L, const double *__restrict__ x, const double *__r
         z[t] = x[t] - y[t];
 }
 
-// CG with its scalars on the device (no host round trip per iteration):
-// sc[0] = r.r, sc[1] = p.Ap, sc[2] = the new r.r.
-// phi += alpha p, r -= alpha Ap with alpha = sc[0] / sc[1]; alpha = 0 once
-// r.r <= thr2, so the iterations a batch runs past convergence change
-// nothing (CG continued past convergence lets the residual wander)
-__global__ void k_cg_x(int64_t N, const double *sc, double thr2, const double *__restrict__ p,
-                       const double *__restrict__ Ap, double *__restrict__ phi, double *__restrict__ r) {
-    const double rr = dev_scalar(sc), pap = dev_scalar(sc + 1);
-    const double alpha = (pap > 0.0 && rr > thr2) ? rr / pap : 0.0;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N; t += (int64_t)gridDim.x * blockDim.x) {
-        phi[t] += alpha * p[t];
-        r[t] -= alpha * Ap[t];
+// block-wide sum of one value per thread into part[blockIdx.x]
+__device__ __forceinline__ void block_partial(double acc, double *part) {
+    __shared__ double red[kBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += red[q];
+        part[blockIdx.x] = s;
     }
 }
 
-// p = r + beta p with beta = sc[2] / sc[0]
-__global__ void k_cg_p(int64_t N, const double *sc, const double *__restrict__ r, double *__restrict__ p) {
-    const double rr = dev_scalar(sc), rr1 = dev_scalar(sc + 2);
+// CG with its scalars on the device (no host round trip per iteration), each
+// dot product fused into the kernel that writes its vector; sc[1] = p.Ap,
+// r.r alternates between sc[ia] (current) and sc[ib] (new).
+// Ap = -div grad p, and the block partials of p . Ap
+__global__ void k_cg_ap(Geo g, int64_t N, const double *__restrict__ p, double *__restrict__ Ap,
+                        double *__restrict__ part) {
+    double acc = 0.0;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N; t += (int64_t)gridDim.x * blockDim.x) {
+        int i, j, k;
+        node_ijk(g, t, i, j, k);
+        const double v = -(dif2(g, p, i, j, k, 0, 0) + dif2(g, p, i, j, k, 1, 1) + dif2(g, p, i, j, k, 2, 2));
+        Ap[t] = v;
+        acc += p[t] * v;
+    }
+    block_partial(acc, part);
+}
+
+// phi += alpha p, r -= alpha Ap with alpha = r.r / p.Ap, and the block
+// partials of the new r . r; alpha = 0 once r.r <= thr2, so the iterations
+// a batch runs past convergence change nothing (CG continued past
+// convergence lets the residual wander)
+__global__ void k_cg_x(int64_t N, const double *sc, int ia, double thr2, const double *__restrict__ p,
+                       const double *__restrict__ Ap, double *__restrict__ phi, double *__restrict__ r,
+                       double *__restrict__ part) {
+    const double rr = dev_scalar(sc + ia), pap = dev_scalar(sc + 1);
+    const double alpha = (pap > 0.0 && rr > thr2) ? rr / pap : 0.0;
+    double acc = 0.0;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N; t += (int64_t)gridDim.x * blockDim.x) {
+        phi[t] += alpha * p[t];
+        const double rv = r[t] - alpha * Ap[t];
+        r[t] = rv;
+        acc += rv * rv;
+    }
+    block_partial(acc, part);
+}
+
+// p = r + beta p with beta = new r.r / r.r
+__global__ void k_cg_p(int64_t N, const double *sc, int ia, int ib, const double *__restrict__ r,
+                       double *__restrict__ p) {
+    const double rr = dev_scalar(sc + ia), rr1 = dev_scalar(sc + ib);
     const double beta = rr > 0.0 ? rr1 / rr : 0.0;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N; t += (int64_t)gridDim.x * blockDim.x)
         p[t] = r[t] + beta * p[t];
-}
-
-// sc[0] = sc[2] (one thread; stream order puts it after k_cg_p)
-__global__ void k_cg_roll(double *sc) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) sc[0] = dev_scalar(sc + 2);
 }
 
 __global__ void k_fill0(int64_t L, double *__restrict__ x) {
@@ -536,22 +557,24 @@ int spic_ctx_s::field_cycle(const spic_grid &gr, const spic_field_params &fp, sp
     // iterations (past convergence the device stops moving phi and r)
     constexpr int kCgCheck = 8;
     int it = 0;
-    double *sc = wk.dres;  // [0] r.r, [1] p.Ap, [2] new r.r
+    double *sc = wk.dres;  // [0] / [2] r.r (alternating), [1] p.Ap
     const double thr2 = (tol * bnorm_c) * (tol * bnorm_c);
+    const dim3 gred(nred);
+    int ia = 0, ib = 2;
     while (wk.err == hipSuccess && bnorm_c > 0.0 && std::sqrt(rr) > tol * bnorm_c && it < fp.max_iter) {
         const int batch = std::min(kCgCheck, fp.max_iter - it);
         for (int q = 0; q < batch; ++q) {
-            hipLaunchKernelGGL(k_neg_lap, gn, bk, 0, s, g, N, (const double *)pp, Ap);
-            wk.mdot(pp, 1, Ap, sc + 1, N);
-            hipLaunchKernelGGL(k_cg_x, gn, bk, 0, s, N, (const double *)sc, thr2, (const double *)pp,
-                               (const double *)Ap, phi, r);
-            wk.mdot(r, 1, r, sc + 2, N);
-            hipLaunchKernelGGL(k_cg_p, gn, bk, 0, s, N, (const double *)sc, (const double *)r, pp);
-            hipLaunchKernelGGL(k_cg_roll, dim3(1), dim3(64), 0, s, sc);
+            hipLaunchKernelGGL(k_cg_ap, gred, bk, 0, s, g, N, (const double *)pp, Ap, wk.part);
+            hipLaunchKernelGGL(k_msum, dim3(1), bk, 0, s, (const double *)wk.part, nred, sc + 1, 0);
+            hipLaunchKernelGGL(k_cg_x, gred, bk, 0, s, N, (const double *)sc, ia, thr2, (const double *)pp,
+                               (const double *)Ap, phi, r, wk.part);
+            hipLaunchKernelGGL(k_msum, dim3(1), bk, 0, s, (const double *)wk.part, nred, sc + ib, 0);
+            hipLaunchKernelGGL(k_cg_p, gn, bk, 0, s, N, (const double *)sc, ia, ib, (const double *)r, pp);
+            std::swap(ia, ib);
         }
         wk.launched();
         it += batch;
-        rr = wk.fetch(sc, 1)[0];
+        rr = wk.fetch(sc + ia, 1)[0];
     }
     st.clean_iters = it;
     st.clean_resid = bnorm_c > 0.0 ? std::sqrt(rr) / bnorm_c : 0.0;
