@@ -236,3 +236,100 @@ def test_f11_vacuum_cycle():
     Ec, _ = F.clean(g, f, [], 4 * np.pi)
     assert np.abs(div @ Ec.ravel()).max() < 1e-12 * np.abs(Ec).max() / min(F.spacing(g))
     assert all(np.all(np.isfinite(v)) for v in new.values())
+
+
+def test_f12_right_hand_side_closed_forms():
+    """Vacuum with B_z(x) = cos(2 pi m x / Lx): the right-hand side is
+    E + theta dt c curl B with (curl B)_y = -D_x B_z from the symbol; a
+    uniform current with B = 0 enters as -theta dt fourpi J."""
+    g = _grid(8, 4, 4)
+    N = g.nx * g.ny * g.nz
+    i, _, _ = _node_ijk(g)
+    rng = np.random.default_rng(10)
+    f = _fields(g, rng, 0.1)
+    for k in ("bx", "by", "bz"):
+        f[k][:] = 0.0
+    m = 3
+    f["bz"][:] = np.cos(2 * np.pi * m * i / g.nx)
+    dt, c, theta, fourpi = 0.3, 1.5, 0.7, 4 * np.pi
+    E = np.stack([f[k] for k in ("ex", "ey", "ez")])
+    rhs = F.rhs_vector(g, f, [], [], dt, c, theta, fourpi)
+    s = np.sin(2 * np.pi * m / g.nx) / F.spacing(g)[0]
+    want = E.copy()
+    want[1] += theta * dt * c * s * np.sin(2 * np.pi * m * i / g.nx)
+    assert np.allclose(rhs, want, atol=1e-13)
+    f["bz"][:] = 0.0
+    mom = np.zeros((10, N))
+    mom[1:4] = np.array([0.2, -0.1, 0.05])[:, None]
+    rhs = F.rhs_vector(g, f, [mom], [1.0], dt, c, theta, fourpi)
+    assert np.allclose(rhs, E - theta * dt * fourpi * mom[1:4], atol=1e-13)
+
+
+# plausible mistakes planted in the oracle (each must fail a pin above)
+def _mut_curl_sign(mp):
+    real = F.operators
+
+    def ops(g):
+        Dx, Dy, Dz, curl, div, grad, lap = real(g)
+        Z = F.sp.csr_matrix(Dx.shape)
+        bad = F.sp.bmat([[Z, Dz, Dy], [Dz, Z, -Dx], [-Dy, Dx, Z]]).tocsr()
+        return Dx, Dy, Dz, bad, div, grad, lap
+    mp.setattr(F, "operators", ops)
+
+
+def _mut_mu_factor(mp):
+    real = F.susceptibility
+    mp.setattr(F, "susceptibility", lambda *a: 2.0 * real(*a))
+
+
+def _mut_rotation_sense(mp):
+    real = F.rotation
+    mp.setattr(F, "rotation", lambda b: np.swapaxes(real(b), -1, -2))
+
+
+def _mut_pressure_half(mp):
+    real = F.implicit_current
+
+    def jh(g, fields, moments, qoms, dt, c):
+        return real(g, fields, moments, qoms, 2.0 * dt, c) - 0.0 * dt
+    mp.setattr(F, "implicit_current", jh)
+
+
+def _mut_clean_sign(mp):
+    real = F.clean
+
+    def cl(g, fields, moments, fourpi):
+        Ec, phi = real(g, fields, moments, fourpi)
+        E = np.stack([np.asarray(fields[k], np.float64) for k in ("ex", "ey", "ez")])
+        return 2 * E - Ec, phi
+    mp.setattr(F, "clean", cl)
+
+
+def _mut_rhs_current_sign(mp):
+    real = F.rhs_vector
+
+    def rv(g, fields, moments, qoms, dt, c, theta, fourpi, E=None):
+        return real(g, fields, moments, qoms, dt, c, theta, -fourpi, E=E)
+    mp.setattr(F, "rhs_vector", rv)
+
+
+PINS = [test_f1_difference_of_a_fourier_mode, test_f2_div_curl_and_curl_grad_vanish,
+        test_f3_curl_curl_is_symmetric_semidefinite_and_the_vector_identity,
+        test_f4_rotation_inverts_the_implicit_cross_product, test_f5_susceptibility_without_magnetic_field,
+        test_f6_transverse_wave_is_an_eigenvector, test_f7_field_equation_solution,
+        test_f8_implicit_current_without_magnetic_field, test_f9_divergence_cleaning, test_f10_theta_one_update,
+        test_f11_vacuum_cycle, test_f12_right_hand_side_closed_forms]
+
+
+@pytest.mark.parametrize("mutate", [_mut_curl_sign, _mut_mu_factor, _mut_rotation_sense, _mut_pressure_half,
+                                    _mut_clean_sign, _mut_rhs_current_sign])
+def test_planted_mistakes_fail_a_pin(mutate, monkeypatch):
+    with monkeypatch.context() as mp:
+        mutate(mp)
+        failed = 0
+        for pin in PINS:
+            try:
+                pin()
+            except AssertionError:
+                failed += 1
+    assert failed >= 1, mutate.__name__
