@@ -193,18 +193,20 @@ int spic_version(void);
  *   tile_x/y/z     sort tile shape in cells (product <= 64)
  *   halo           cells of halo staged around a tile in LDS (0..8)
  *   lds_max        read only: LDS bytes a workgroup may use on the device
- *   tile_variant   tiled-kernel variant (0..2; -1 = by precision): 0 one
+ *   tile_variant   tiled-kernel variant (0..3; -1 = by precision): 0 one
  *                  kernel, every deposit an FP64 LDS atomic; 1 as 0 with
  *                  the 48 field values of a thread's last cell in registers
  *                  (default for FP64 particles); 2 a mover launch, then
  *                  a deposit launch into per-lane register sums of sorted
- *                  cells (default for FP32 particles)
+ *                  cells (default for FP32 particles); 3 the mover of 1 and
+ *                  the register deposit of 2 in one launch (FP32
+ *                  particles; FP64 particles run 2)
  *   mover_cache    variant 2: 1 = the mover launch keeps the 48 field
  *                  values of a thread's last cell in registers (default), 0 =
  *                  every gather reads LDS
  *   mover_block    variant 2: threads per workgroup of the mover launch
  *                  (64..512, x64; default 512)
- *   mover_halo     variant 2: cells of halo of the mover launch's field
+ *   mover_halo     variants 2 and 3: cells of halo of the mover's field
  *                  region (-1..8; -1 = the tile halo + 1; a region too large
  *                  for the device's LDS falls back to the tile halo)
  *   tile_group     mapping of tiles to workgroups of a tiled launch: groups
@@ -226,7 +228,7 @@ int spic_version(void);
  *                  n / C rows of C slots, slot (r, c) holding rank r of cell
  *                  c where that exists and the particles of higher ranks
  *                  filling the rest; 0 = plain rank blocks (default 1 for
- *                  tile variant 2, else 0)
+ *                  tile variants 2 and 3, else 0)
  *   graph          batch engine: replay unchanged ticks as a hipGraph (0/1)
  *   batch_particles  batch engine: particles per streamed batch
  *   max_groups     batch engine: cap on workgroups of the persistent launch

@@ -84,14 +84,14 @@ def _lcm(values: Iterable[int]) -> int:
 
 def candidates(quick: bool = True, dtype_name: str = "f32") -> Iterable[Dict[str, int]]:
     """One resident box.  FP32 particles: the split variant (2) and, unless
-    quick, the one-kernel variants 0 and 1; FP64 particles: the one-kernel
-    variants (their LDS-atomic deposit is exact in FP64).  Blocks and
-    cadences as listed; the bank-preserving layout on and off."""
+    quick, the one-kernel variants 0, 1 and 3; FP64 particles: the
+    one-kernel variants (their LDS-atomic deposit is exact in FP64).  Blocks
+    and cadences as listed; the bank-preserving layout on and off."""
     blocks = (256, 512)
     if dtype_name == "f64":
         variants = (0,) if quick else (0, 1)
     else:
-        variants = (2,) if quick else (0, 1, 2)
+        variants = (2,) if quick else (0, 1, 2, 3)
     cadences = (2, 4, 8) if quick else (1, 2, 4, 8, 16)
     aligns = (1, 0)
     for blk, var, se, al in itertools.product(blocks, variants, cadences, aligns):

@@ -33,8 +33,8 @@ std::string spic_ctx_s::layout_key(const spic_grid &g, const spic_species &s) co
 
 // The bank-preserving layout pays off for FP32 particles; FP64 particles
 // keep the compact one (two workgroups per CU for the one-kernel variants)
-// unless bank_align is set.  Full rows for the split variant (the mover's
-// corner cache and the deposit's loads want lane c on cell c); the
+// unless bank_align is set.  Full rows for variants 2 and 3 (the mover's
+// corner cache and the deposit's lane sums want lane c on cell c); the
 // LDS-atomic variants keep plain rank blocks, whose rows never hold one
 // cell twice.
 TileGeom spic_ctx_s::tile_geom(const spic_grid &g, int dtype) const {
@@ -43,7 +43,7 @@ TileGeom spic_ctx_s::tile_geom(const spic_grid &g, int dtype) const {
     const int dflt = dtype == SPIC_F64 ? 0 : 1;
     return make_tile_geom(g, (int)opt("tile_x", 4), (int)opt("tile_y", 4), (int)opt("tile_z", 4),
                           (int)opt("halo", 1), (int)opt("bank_align", dflt),
-                          opt("sort_rows", var == kVariantSplit ? 1 : 0) != 0);
+                          opt("sort_rows", variant_rows(var) ? 1 : 0) != 0);
 }
 
 

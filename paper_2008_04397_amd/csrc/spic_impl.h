@@ -59,7 +59,7 @@ struct LaunchCfg {
     int block = 256;        // generic kernels
     int grid_cap = 1 << 20;
     int tile_block = -1;    // tiled fused kernel (-1: by variant)
-    int variant = -1;       // tiled kernel variant (0, 1, 2; see spic_tiled.hip; -1: 2)
+    int variant = -1;       // tiled kernel variant (0..3; see spic_tiled.hip; -1: by precision)
     int fixed_geo = 1;      // compile-time region geometry for the default tiling
     int mover_halo = -1;    // variant 2: halo of the mover's field region (-1: tile halo + 1)
     int mover_cache = 1;    // variant 2: the mover keeps the last cell's field corners in registers
@@ -93,6 +93,9 @@ inline int tile_chunk(int ntiles, int glog) {
 // variant 0, 256 otherwise (variant 1's FP64 corner cache allows two
 // waves per SIMD: two workgroups of 256 per CU).
 constexpr int kVariantSplit = 2;
+constexpr int kVariantLaneCell = 3;
+// the variants whose deposit wants full rows (lane c on cell c)
+inline bool variant_rows(int v) { return v == kVariantSplit || v == kVariantLaneCell; }
 inline int auto_variant(int dtype, int) { return dtype == SPIC_F32 ? kVariantSplit : 1; }
 inline int auto_tile_block(int variant) { return variant == 0 ? 512 : 256; }
 inline LaunchCfg resolve_cfg(LaunchCfg c, int dtype, int acc_dtype) {

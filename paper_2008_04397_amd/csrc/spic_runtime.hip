@@ -223,11 +223,11 @@ static const char *const kOptionNames[] = {
     "halo",         // cells of halo staged around a tile
     "lds_max",      // read only: LDS bytes per workgroup on the device
     "tile_variant", // tiled kernel: 0 one kernel with LDS-atomic deposits, 1 + field corners in registers,
-                    // 2 mover launch then the sorted register deposit (default)
+                    // 2 mover launch then the sorted register deposit, 3 both in one launch (FP32)
     "fixed_geo",    // tiled kernel: 1 = compile-time region geometry for 4x4x4 tiles, halo 1
     "sort_ordered", // sort: 1 = ranks follow the previous order (a sorted species' tiles walked in order)
     "sort_rows",    // sort: 1 = full rows (lane = cell for all but a few particles), 0 = plain rank blocks
-                    // (default: 1 for variant 2)
+                    // (default: 1 for variants 2 and 3)
     "bank_align",   // tiled kernel LDS layout: 0 compact conflict-free, 1 + slow-axis stride keeps bank pairs,
                     // 2 dense (no padding)
     "graph",        // batch engine: 1 = replay unchanged ticks as a hipGraph
@@ -235,7 +235,7 @@ static const char *const kOptionNames[] = {
     "max_groups",   // batch engine: cap on workgroups of the persistent launch (0 = occupancy)
     "tick_items",   // batch engine: (job, tile) items per tick, shortest runs first (0 = all runs)
     "srpt_aging",   // batch engine: credit, in M particle-steps per second waited, against starvation
-    "mover_halo",   // variant 2: halo of the mover's field region (-1: tile halo + 1)
+    "mover_halo",   // variants 2, 3: halo of the mover's field region (-1: tile halo + 1)
     "mover_cache",  // variant 2: 1 = the mover keeps the last cell's field corners in registers
     "mover_block",  // variant 2: threads per workgroup of the mover launch (64..512, x64; default 512)
     "tile_group",   // tiles to workgroups: groups of 2^v tiles dealt to the XCDs (default 4); -1 XCD slabs
@@ -338,8 +338,8 @@ int spic_set_option(spic_ctx ctx, const char *key, int64_t value) {
             if ((!strcmp(key, "tile_x") || !strcmp(key, "tile_y") || !strcmp(key, "tile_z")) &&
                 (value < 1 || value > 64))
                 return ctx->fail(SPIC_E_ARG, "tile sizes must be in [1, 64]");
-            if (!strcmp(key, "tile_variant") && (value < -1 || value > 2))
-                return ctx->fail(SPIC_E_ARG, "tile_variant must be -1 or in 0..2");
+            if (!strcmp(key, "tile_variant") && (value < -1 || value > 3))
+                return ctx->fail(SPIC_E_ARG, "tile_variant must be -1 or in 0..3");
             if (!strcmp(key, "batch_particles") && (value < 1024 || value > ((int64_t)1 << 29)))
                 return ctx->fail(SPIC_E_ARG, "batch_particles must be in [1024, 2^29]");
             if (!strcmp(key, "tick_items") && (value < 0 || value > ((int64_t)1 << 30)))

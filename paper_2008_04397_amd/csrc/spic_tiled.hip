@@ -15,8 +15,11 @@
 //   1  as 0, with the 48 field values of a thread's last cell in registers
 //      (in sort order a thread's particles share their cell, so most
 //      gathers skip LDS);
-//   2  two launches (the default): variant 1's mover without moments, then
-//      the sorted deposit below over the moved particles.
+//   2  two launches: variant 1's mover without moments, then the sorted
+//      deposit below over the moved particles;
+//   3  one launch (FP32 particles; FP64 particles run variant 2): variant
+//      1's mover hands each moved particle to the sorted deposit's lane
+//      sums, so only the particles that changed cell are read again.
 //
 // Sorted deposit.  The deposit workgroup counting-sorts the moved
 // particles of its tile by their new cell in LDS (an index list), and lane
@@ -339,45 +342,54 @@ __device__ __forceinline__ TilePlace tile_place(const TileGeom &tg, int nx, int 
     return tp;
 }
 
-// One tile of one species: stage the region's fields, move the tile's
-// particles and (unless MOVE_ONLY or J.mom is NULL) deposit each moved
-// particle with FP64 LDS atomics, then flush the region's moments.  Called
-// by the per-species tiled kernel and by the work-list kernels of the batch
-// engine; `t` is uniform across the workgroup.  The particle loop is
-// uniform per wave (lanes past the end of the range idle).
-template <typename TP, typename TF, typename TA, bool CACHE, bool MOVE_ONLY, class GEO>
-__device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, unsigned char *smem) {
-    const GridT<TP> &g = J.g;
-    TileGeom tg = J.tg;
-    apply_geo<GEO>(tg);
-    const FieldPtrs<TF> &f = J.f;
-    const PartPtrs<TP> &p = J.p;
-    TA *__restrict__ mom = MOVE_ONLY ? nullptr : J.mom;
-    const int nn = J.nn;
-    const uint32_t beg = J.tile_off[t], end = J.tile_off[t + 1];
-    if (beg == end) return;  // uniform: no particle in this tile
-
-    const int RNP = tg.rnp;
-    const size_t fbytes = (RNP * sizeof(LdsFieldNode<TP>) + 15) & ~(size_t)15;
-    LdsFieldNode<TP> *fl = (LdsFieldNode<TP> *)smem;
-    TA *ml = (TA *)(smem + fbytes);
-    const TilePlace tp = tile_place(tg, g.nx, g.ny, g.nz, t);
-    const int ox = tp.ox, oy = tp.oy, oz = tp.oz;
+// Stages the node fields of the region with origin (ox, oy, oz) in LDS,
+// node-major, in the particle precision.
+template <typename TP, typename TF>
+__device__ __forceinline__ void stage_fields(const FieldPtrs<TF> &f, const TileGeom &tg, int nx, int ny, int nz,
+                                             int ox, int oy, int oz, LdsFieldNode<TP> *__restrict__ fl) {
     const int RL = tg.rx * tg.ry * tg.rz;  // logical region nodes
-    const int sx = tg.sx, sy = tg.sy, sz = tg.sz;
-
-    // stage the region's node fields, zero the region's moments
     for (int r = threadIdx.x; r < RL; r += blockDim.x) {
-        const RegionNode rn = region_node(tg, g.nx, g.ny, g.nz, ox, oy, oz, r);
+        const RegionNode rn = region_node(tg, nx, ny, nz, ox, oy, oz, r);
         LdsFieldNode<TP> fn;
 #pragma unroll
         for (int m = 0; m < 6; ++m) fn.v[m] = (TP)f.f[m][rn.gnode];
         fl[rn.slot] = fn;
     }
-    if (mom)
-        for (int q = threadIdx.x; q < 10 * RNP; q += blockDim.x) ml[q] = TA(0);
-    __syncthreads();
+}
 
+// Adds the region accumulator [10][rnp] to the global moments, skipping
+// exact zeros (halo nodes no particle reached); consecutive threads take
+// consecutive region nodes, so each moment's atomics are coalesced along
+// the fast axis.
+template <typename TA>
+__device__ __forceinline__ void flush_region(const TileGeom &tg, int nx, int ny, int nz, int ox, int oy, int oz,
+                                             const TA *__restrict__ ml, TA *__restrict__ mom, int nn) {
+    const int RL = tg.rx * tg.ry * tg.rz, RNP = tg.rnp;
+    for (int r = threadIdx.x; r < RL; r += blockDim.x) {
+        const RegionNode rn = region_node(tg, nx, ny, nz, ox, oy, oz, r);
+#pragma unroll
+        for (int m = 0; m < 10; ++m) {
+            const TA val = ml[m * RNP + rn.slot];
+            if (val != TA(0)) atomicAdd(mom + (size_t)m * nn + rn.gnode, val);
+        }
+    }
+}
+
+// Moves the particles [beg, end) of one tile (Eq. 1, Eq. 2, Eq. 5),
+// gathering E and B (Eq. 3, Eq. 4) from the region fields `fl` staged with
+// origin (ox, oy, oz), and stores the new state.  Thread k takes slots
+// beg + k, beg + k + blockDim.x, ...; the loop is uniform per wave, and
+// after each slot every lane calls done(i, valid, x, y, z, u, v, w, q) with
+// the moved particle (valid is false past the range, where the values are
+// stale).
+template <typename TP, typename TF, typename TA, bool CACHE, typename Done>
+__device__ __forceinline__ void move_tile(const TileJob<TP, TF, TA> &J, const TileGeom &tg,
+                                          const LdsFieldNode<TP> *__restrict__ fl, int ox, int oy, int oz,
+                                          uint32_t beg, uint32_t end, Done &&done) {
+    const GridT<TP> &g = J.g;
+    const FieldPtrs<TF> &f = J.f;
+    const PartPtrs<TP> &p = J.p;
+    const int sx = tg.sx, sy = tg.sy, sz = tg.sz;
     const int coff[8] = {0, sx, sy, sx + sy, sz, sx + sz, sy + sz, sx + sy + sz};
     LdsFieldNode<TP> corner[CACHE ? 8 : 1];  // field corners of the cell `cached`
     int cached = -1;
@@ -463,24 +475,50 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
                 st32(p.q, o, qp);
                 if (copy_id) p.id[i] = idp;
             }
-            if (mom)  // deposit of the new state in the accumulation precision
-                deposit_one<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, (TA)xn, (TA)yn, (TA)zn, (TA)qp, (TA)un,
-                                     (TA)vn, (TA)wn);
         }
+        done(i, valid, xn, yn, zn, un, vn, wn, qp);
     }
+}
+
+// One tile of one species: stage the region's fields, move the tile's
+// particles and (unless MOVE_ONLY or J.mom is NULL) deposit each moved
+// particle with FP64 LDS atomics, then flush the region's moments.  Called
+// by the per-species tiled kernel and by the work-list kernels of the batch
+// engine; `t` is uniform across the workgroup.
+template <typename TP, typename TF, typename TA, bool CACHE, bool MOVE_ONLY, class GEO>
+__device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, unsigned char *smem) {
+    const GridT<TP> &g = J.g;
+    TileGeom tg = J.tg;
+    apply_geo<GEO>(tg);
+    TA *__restrict__ mom = MOVE_ONLY ? nullptr : J.mom;
+    const int nn = J.nn;
+    const uint32_t beg = J.tile_off[t], end = J.tile_off[t + 1];
+    if (beg == end) return;  // uniform: no particle in this tile
+
+    const int RNP = tg.rnp;
+    const size_t fbytes = (RNP * sizeof(LdsFieldNode<TP>) + 15) & ~(size_t)15;
+    LdsFieldNode<TP> *fl = (LdsFieldNode<TP> *)smem;
+    TA *ml = (TA *)(smem + fbytes);
+    const TilePlace tp = tile_place(tg, g.nx, g.ny, g.nz, t);
+    const int ox = tp.ox, oy = tp.oy, oz = tp.oz;
+
+    // stage the region's node fields, zero the region's moments
+    stage_fields<TP, TF>(J.f, tg, g.nx, g.ny, g.nz, ox, oy, oz, fl);
+    if (mom)
+        for (int q = threadIdx.x; q < 10 * RNP; q += blockDim.x) ml[q] = TA(0);
+    __syncthreads();
+
+    move_tile<TP, TF, TA, CACHE>(J, tg, fl, ox, oy, oz, beg, end,
+                                 [&](uint32_t, bool valid, TP xn, TP yn, TP zn, TP un, TP vn, TP wn, TP qp)
+                                     __attribute__((always_inline)) {
+                                         // deposit of the new state in the accumulation precision
+                                         if (valid && mom)
+                                             deposit_one<TA, GEO>(J.ga, tg, ox, oy, oz, ml, mom, nn, (TA)xn,
+                                                                  (TA)yn, (TA)zn, (TA)qp, (TA)un, (TA)vn, (TA)wn);
+                                     });
     if (!mom) return;
     __syncthreads();
-    // flush: region accumulator -> global moments (skip exact zeros: halo
-    // nodes no particle reached); consecutive threads take consecutive region
-    // nodes, so each moment's atomics are coalesced along z
-    for (int r = threadIdx.x; r < RL; r += blockDim.x) {
-        const RegionNode rn = region_node(tg, g.nx, g.ny, g.nz, ox, oy, oz, r);
-#pragma unroll
-        for (int m = 0; m < 10; ++m) {
-            const TA val = ml[m * RNP + rn.slot];
-            if (val != TA(0)) atomicAdd(mom + (size_t)m * nn + rn.gnode, val);
-        }
-    }
+    flush_region(tg, g.nx, g.ny, g.nz, ox, oy, oz, ml, mom, nn);
 }
 
 // ------------------------------------------------------- sorted deposit
@@ -528,6 +566,235 @@ __device__ __forceinline__ int local_cell(const TileGeom &tg, const int d[3]) {
     return (d[tg.slow] * t3[tg.mid] + d[tg.mid]) * t3[tg.fast] + d[tg.fast];
 }
 
+// The sorted deposit of one tile.  Lane l of every wave owns local cell l
+// of the tile and keeps the moments of its 8 nodes (80 sums) in registers.
+// The tile's range is taken in rows of 64 slots (after a sort in full rows
+// slot (r, l) holds a particle of cell l): a particle in its slot's cell is
+// added to the lane's sums at once; one that moved to another cell of the
+// tile is binned by its new cell (an index in LDS), one that left the tile
+// (or found its bin full) goes to the out list (dep_route).  Then lane
+// (w, l) adds the entries w, w + W, ... of cell l's bin to its sums, the
+// sums are added to the region, and the out list is deposited 64 at a time,
+// bank-balanced, with FP64 terms and LDS atomics (global atomics beyond the
+// region) (dep_drain).  A tile whose out list overflows (or of 65536
+// particles or more) drops the sums and lists and deposits every particle
+// with LDS atomics instead.  The region is then flushed to the global
+// moments (dep_finish).
+//
+// DepTile holds the tile's LDS (moments [10][rnp] in the dense layout, bin
+// counts, out count and overflow flag, bins, out list, the wave's
+// balancing stage) and the lane's cell.
+template <typename TP, typename TA>
+struct DepTile {
+    TileGeom tg;  // the moments' region, dense layout
+    TilePlace tp;
+    TA *ml;
+    int *bcnt, *ocnt, *oflow;
+    uint16_t *bins, *olist;
+    StagedParticle<TP> *stage;
+    BalanceLds *bal;
+    uint32_t beg, end;
+    int C, nwv, wv, lane, lslot;
+    bool owner;
+};
+
+// Opens the deposit of tile t (particles [beg, end)) in smem: zeroes the
+// region and the counts.  The caller synchronises before the first route.
+template <typename TP, typename TA, class GEO>
+__device__ __forceinline__ DepTile<TP, TA> dep_open(const GridT<TA> &ga, TileGeom tg, int t, uint32_t beg,
+                                                    uint32_t end, unsigned char *smem) {
+    apply_geo<GEO>(tg);
+    if constexpr (!GEO::fixed) {  // the dense layout of the moments
+        const int r3[3] = {tg.rx, tg.ry, tg.rz};
+        int st[3];
+        st[tg.fast] = 1;
+        st[tg.mid] = r3[tg.fast];
+        st[tg.slow] = r3[tg.fast] * r3[tg.mid];
+        tg.sx = st[0]; tg.sy = st[1]; tg.sz = st[2];
+        tg.rnp = tg.rx * tg.ry * tg.rz;
+    }
+    DepTile<TP, TA> d;
+    const int RNP = tg.rnp;
+    d.tg = tg;
+    d.beg = beg;
+    d.end = end;
+    d.C = tg.cells;
+    d.nwv = blockDim.x >> 6;
+    d.wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
+    d.lane = threadIdx.x & 63;
+    d.ml = (TA *)smem;
+    d.bcnt = (int *)(smem + (((size_t)10 * RNP * sizeof(TA) + 15) & ~(size_t)15));
+    d.ocnt = d.bcnt + 64;
+    d.oflow = d.bcnt + 65;
+    d.bins = (uint16_t *)(d.bcnt + 80);
+    d.olist = d.bins + 64 * kDepCap;
+    unsigned char *mine = (unsigned char *)d.bins +
+                          ((((size_t)64 * kDepCap + kDepOutCap) * sizeof(uint16_t) + 15) & ~(size_t)15) +
+                          d.wv * (64 * sizeof(StagedParticle<TP>) + sizeof(BalanceLds));
+    d.stage = (StagedParticle<TP> *)mine;
+    d.bal = (BalanceLds *)(mine + 64 * sizeof(StagedParticle<TP>));
+    d.tp = tile_place(tg, ga.nx, ga.ny, ga.nz, t);
+    // the cell this lane owns: local index `lane` (lanes >= C own none)
+    const int t3[3] = {tg.tx, tg.ty, tg.tz};
+    int lc[3];
+    lc[tg.fast] = d.lane % t3[tg.fast];
+    lc[tg.mid] = (d.lane / t3[tg.fast]) % t3[tg.mid];
+    lc[tg.slow] = d.lane / (t3[tg.fast] * t3[tg.mid]);
+    d.owner = d.lane < d.C;
+    d.lslot = (tg.halo + lc[0]) * tg.sx + (tg.halo + lc[1]) * tg.sy + (tg.halo + lc[2]) * tg.sz;
+    for (int q = threadIdx.x; q < 10 * RNP; q += blockDim.x) d.ml[q] = TA(0);
+    // the 64 bin counts, the out count and the overflow flag
+    for (int q = threadIdx.x; q < 66; q += blockDim.x) d.bcnt[q] = (q == 65 && end - beg >= 65536u) ? 1 : 0;
+    return d;
+}
+
+// A particle record (x, y, z, u, v, w, q) of slot i; an index past the
+// range is clamped to the tile's last particle (read and ignored), so a
+// prefetch slot is refilled in place.
+template <typename TP, typename TA>
+__device__ __forceinline__ void dep_load(const PartPtrs<TP> &p, const DepTile<TP, TA> &d, TP (&dst)[7],
+                                         uint32_t i) {
+    const uint32_t o = min(i, d.end - 1) * (uint32_t)sizeof(TP);
+    dst[0] = ld32(p.x, o); dst[1] = ld32(p.y, o); dst[2] = ld32(p.z, o);
+    dst[3] = ld32(p.u, o); dst[4] = ld32(p.v, o); dst[5] = ld32(p.w, o); dst[6] = ld32(p.q, o);
+}
+
+// A particle into the lane's sums: in-cell offsets in the accumulation
+// precision, the weighted charge rounded once to the particle precision,
+// the ten terms and their sums in the particle precision.  Branch free: a
+// particle that is not the lane's adds its terms with zero charge (a
+// conditional add would make the compiler copy all 80 sums at the join).
+template <typename TP, typename TA>
+__device__ __forceinline__ void dep_add_terms(TP (&sacc)[80], const TP (&rec)[7], TA fx, TA fy, TA fz,
+                                              bool take) {
+    const TA qa = take ? (TA)rec[6] : TA(0);
+    const TA gx = TA(1) - fx, gy = TA(1) - fy, gz = TA(1) - fz;
+    const TP u = rec[3], v = rec[4], w = rec[5];
+    const TP val[10] = {TP(1), u, v, w, u * u, u * v, u * w, v * v, v * w, w * w};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const TA wk = (((k & 1) ? fx : gx) * ((k & 2) ? fy : gy)) * ((k & 4) ? fz : gz);
+        const TP qw = (TP)(qa * wk);
+#pragma unroll
+        for (int m = 0; m < 10; ++m) sacc[k * 10 + m] += qw * val[m];
+    }
+}
+
+// The particle's local tile cell (C when it left the tile); its terms are
+// added when the cell is the lane's and mine_p holds.
+template <typename TP, typename TA>
+__device__ __forceinline__ int dep_add_own(const DepTile<TP, TA> &d, const GridT<TA> &ga, TP (&sacc)[80],
+                                           const TP (&rec)[7], bool mine_p) {
+    TA fx, fy, fz;
+    int c[3];
+    c[0] = dep_locate((TA)rec[0], ga.invd[0], ga.nx, fx) - d.tp.c0[0];
+    c[1] = dep_locate((TA)rec[1], ga.invd[1], ga.ny, fy) - d.tp.c0[1];
+    c[2] = dep_locate((TA)rec[2], ga.invd[2], ga.nz, fz) - d.tp.c0[2];
+    const bool in = (unsigned)c[0] < (unsigned)d.tg.tx && (unsigned)c[1] < (unsigned)d.tg.ty &&
+                    (unsigned)c[2] < (unsigned)d.tg.tz;
+    const int cell = in ? local_cell(d.tg, c) : d.C;
+    dep_add_terms(sacc, rec, fx, fy, fz, mine_p && d.owner && cell == d.lane);
+    return cell;
+}
+
+// Routes the moved particle of slot i (valid false past the range): into
+// the lane's sums, its new cell's bin, or the out list (a full bin or a
+// cell outside the tile; positions counted once per wave).
+template <typename TP, typename TA>
+__device__ __forceinline__ void dep_route(const DepTile<TP, TA> &d, const GridT<TA> &ga, TP (&sacc)[80],
+                                          const TP (&rec)[7], uint32_t i, bool valid) {
+    const int cell = dep_add_own(d, ga, sacc, rec, valid);
+    const bool drift = valid && !(d.owner && cell == d.lane);
+    bool out = drift && cell >= d.C;
+    if (drift && !out) {
+        const int pos = atomicAdd(&d.bcnt[cell], 1);
+        if (pos < kDepCap) d.bins[cell * kDepCap + pos] = (uint16_t)(i - d.beg);
+        else out = true;
+    }
+    const unsigned long long om = __ballot(out);
+    if (om) {
+        const int lead = __ffsll((long long)om) - 1;
+        int b0 = 0;
+        if (d.lane == lead) b0 = atomicAdd(d.ocnt, __popcll(om));
+        const int opos = __shfl(b0, lead) + __popcll(om & ((1ull << d.lane) - 1ull));
+        if (out && opos < kDepOutCap) d.olist[opos] = (uint16_t)(i - d.beg);
+        if (out && opos >= kDepOutCap) *d.oflow = 1;
+    }
+}
+
+// After the barrier that follows the last route, when the out list has not
+// overflowed: drains the bins into the sums (reloading those particles
+// from p), then adds the sums and the out list to the region.
+template <typename TP, typename TA, class GEO>
+__device__ __forceinline__ void dep_drain(const DepTile<TP, TA> &d, const GridT<TA> &ga, const PartPtrs<TP> &p,
+                                          TA *__restrict__ mom, int nn, TP (&sacc)[80]) {
+    const TileGeom &tg = d.tg;
+    const int RNP = tg.rnp, sx = tg.sx, sy = tg.sy, sz = tg.sz;
+    // the bins: lane (wv, l) takes entries wv, wv + W, ... of cell l's
+    const int mc = d.owner ? min(d.bcnt[d.lane], kDepCap) : 0;
+    const int mine_n = mc > d.wv ? (mc - d.wv + d.nwv - 1) / d.nwv : 0;
+    // an empty bin's first entry may be stale: it is loaded (clamped into
+    // the range) and added with zero charge
+    auto at = [&](int m) __attribute__((always_inline)) -> uint32_t {
+        const int j = max(min(d.wv + m * d.nwv, mc - 1), 0);
+        return d.beg + d.bins[(d.owner ? d.lane : 0) * kDepCap + j];
+    };
+    TP ring[kDepPrefetch][7];
+#pragma unroll
+    for (int k = 0; k < kDepPrefetch; ++k) dep_load(p, d, ring[k], at(k));
+    for (int m0 = 0; __ballot(m0 < mine_n); m0 += kDepPrefetch) {
+#pragma unroll
+        for (int k = 0; k < kDepPrefetch; ++k) {
+            (void)dep_add_own(d, ga, sacc, ring[k], m0 + k < mine_n);
+            dep_load(p, d, ring[k], at(m0 + k + kDepPrefetch));
+        }
+    }
+    // the sums stay in the particle precision until here
+    settle(sacc);
+    if (d.owner) {
+        const int coff[8] = {0, sx, sy, sx + sy, sz, sx + sz, sy + sz, sx + sy + sz};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            TA *dst = d.ml + d.lslot + coff[k];
+#pragma unroll
+            for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, (TA)sacc[k * 10 + m]);
+        }
+    }
+    // the particles that left the tile (or found their bin full), 64 per
+    // wave at a time, bank-balanced LDS atomics (a halo cell gets too few of
+    // them, and the cells next to the tile's faces too many, for lanes
+    // owning halo cells to pay off)
+    const int no = *d.ocnt;
+    for (int b0 = d.wv * 64; b0 < no; b0 += (int)blockDim.x) {
+        const int e = b0 + d.lane;
+        TP rec[7];
+        dep_load(p, d, rec, d.beg + d.olist[min(e, no - 1)]);
+        deposit_balanced<TP, TA, GEO>(ga, tg, d.tp.ox, d.tp.oy, d.tp.oz, d.ml, mom, nn, d.stage, d.bal, d.lane,
+                                      e < no, rec[0], rec[1], rec[2], rec[3], rec[4], rec[5], rec[6]);
+    }
+}
+
+// Ends the deposit: after an overflow every particle of the range goes to
+// the region by LDS atomics (the sums and lists are dropped); then the
+// region is flushed to the global moments.
+template <typename TP, typename TA, class GEO>
+__device__ __forceinline__ void dep_finish(const DepTile<TP, TA> &d, const GridT<TA> &ga, const PartPtrs<TP> &p,
+                                           TA *__restrict__ mom, int nn) {
+    const TileGeom &tg = d.tg;
+    const int ox = d.tp.ox, oy = d.tp.oy, oz = d.tp.oz;
+    if (*d.oflow) {  // uniform
+        for (uint32_t i0 = d.beg + (threadIdx.x & ~63u); i0 < d.end; i0 += blockDim.x) {
+            const uint32_t i = i0 + d.lane;
+            TP rec[7];
+            dep_load(p, d, rec, i);
+            deposit_balanced<TP, TA, GEO>(ga, tg, ox, oy, oz, d.ml, mom, nn, d.stage, d.bal, d.lane, i < d.end,
+                                          rec[0], rec[1], rec[2], rec[3], rec[4], rec[5], rec[6]);
+        }
+    }
+    __syncthreads();
+    flush_region(tg, ga.nx, ga.ny, ga.nz, ox, oy, oz, d.ml, mom, nn);
+}
+
 // Deposit of the moved particles of tile t (the second launch of variant
 // 2).  Lane l of every wave owns local cell l of the tile and keeps the
 // moments of its 8 nodes (80 sums) in registers.  The tile's range is read
@@ -562,7 +829,9 @@ __device__ __forceinline__ void deposit_body(const TileJob<TP, TF, TA> &J, int t
     const uint32_t beg = J.tile_off[t], end = J.tile_off[t + 1];
     if (beg == end) return;
     const int RNP = tg.rnp, C = tg.cells;
-    const int nwv = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index is uniform per wave: held in a scalar register it frees
+    // the vector registers the 80 sums need (fewer spills in the bin drain)
+    const int nwv = blockDim.x >> 6, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     TA *ml = (TA *)smem;
     int *bcnt = (int *)(smem + (((size_t)10 * RNP * sizeof(TA) + 15) & ~(size_t)15));
     int *ocnt = bcnt + 64;
@@ -742,6 +1011,40 @@ __device__ __forceinline__ void deposit_body(const TileJob<TP, TF, TA> &J, int t
     }
 }
 
+// One tile in one launch (variant 3): variant 1's mover (the fields of a
+// region with the mover's halo in LDS, the field corners of the lane's cell
+// in registers) hands each moved particle straight to the sorted deposit's
+// route, so only the binned and out-listed particles are read again (after
+// the barrier, from the arrays this workgroup has just written).  J.tg is
+// the mover's region (GEOF), tgm the moments' (GEOM, dense layout).
+template <typename TP, typename TF, typename TA, bool CACHE, class GEOF, class GEOM>
+__device__ __forceinline__ void lanecell_body(const TileJob<TP, TF, TA> &J, const TileGeom &tgm, int t,
+                                              unsigned char *smem) {
+    const GridT<TP> &g = J.g;
+    TileGeom tg = J.tg;
+    apply_geo<GEOF>(tg);
+    const uint32_t beg = J.tile_off[t], end = J.tile_off[t + 1];
+    if (beg == end) return;
+    LdsFieldNode<TP> *fl = (LdsFieldNode<TP> *)smem;
+    const size_t fbytes = (tg.rnp * sizeof(LdsFieldNode<TP>) + 15) & ~(size_t)15;
+    const DepTile<TP, TA> d = dep_open<TP, TA, GEOM>(J.ga, tgm, t, beg, end, smem + fbytes);
+    const TilePlace tp = tile_place(tg, g.nx, g.ny, g.nz, t);
+    stage_fields<TP, TF>(J.f, tg, g.nx, g.ny, g.nz, tp.ox, tp.oy, tp.oz, fl);
+    __syncthreads();
+    TP sacc[80];
+#pragma unroll
+    for (int q = 0; q < 80; ++q) sacc[q] = TP(0);
+    move_tile<TP, TF, TA, CACHE>(J, tg, fl, tp.ox, tp.oy, tp.oz, beg, end,
+                                [&](uint32_t i, bool valid, TP x, TP y, TP z, TP u, TP v, TP w, TP q)
+                                    __attribute__((always_inline)) {
+                                        const TP rec[7] = {x, y, z, u, v, w, q};
+                                        dep_route(d, J.ga, sacc, rec, i, valid);
+                                    });
+    __syncthreads();
+    if (!*d.oflow) dep_drain<TP, TA, GEOM>(d, J.ga, J.p, J.mom, J.nn, sacc);  // uniform
+    dep_finish<TP, TA, GEOM>(d, J.ga, J.p, J.mom, J.nn);
+}
+
 // ---------------------------------------------------------------- kernels
 
 // Tile of workgroup b (workgroup b runs on XCD b % 8).  Slab mapping (glog
@@ -787,6 +1090,19 @@ k_deposit_tiled(TileJob<TP, TF, TA> J, int chunk, int glog) {
     const int t = tile_of_block(b, chunk, glog);
     if (t >= J.tg.ntiles) return;
     deposit_body<TP, TF, TA, GEO>(J, t, smem);
+}
+
+// Variant 3 (FP32 particles): the deposit's 80 sums and, with CACHE, the
+// mover's 48 field corners share the registers: two waves per SIMD with
+// the corners, three without.
+template <typename TP, typename TF, typename TA, bool CACHE, class GEOF, class GEOM>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CACHE ? 2 : 3)))
+k_lanecell_tiled(TileJob<TP, TF, TA> J, TileGeom tgm, int chunk, int glog) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int b = blockIdx.x;
+    const int t = tile_of_block(b, chunk, glog);
+    if (t >= J.tg.ntiles) return;
+    lanecell_body<TP, TF, TA, CACHE, GEOF, GEOM>(J, tgm, t, smem);
 }
 
 // Persistent work-list kernels: workgroups take (job, tile) items from an
@@ -840,9 +1156,14 @@ static int dense_rnp(const TileGeom &tg) { return tg.rx * tg.ry * tg.rz; }
 
 size_t tiled_lds_bytes(const TileGeom &tg, int dtype, int acc_dtype, int variant, int block) {
     const int tb = dtype == SPIC_F64 ? 8 : 4, ab = acc_dtype == SPIC_F64 ? 8 : 4;
-    if (variant == 2) {
+    if (variant == kVariantSplit) {
         // the mover launch (fields, at least the tile's halo) and the deposit launch
         return std::max(fields_lds_bytes(tg, dtype), deposit_lds_bytes(dense_rnp(tg), block, tb, ab));
+    }
+    if (variant == kVariantLaneCell) {
+        if (dtype == SPIC_F64) return tiled_lds_bytes(tg, dtype, acc_dtype, kVariantSplit, block);
+        // one launch: fields (at least the tile's halo) beside the deposit's LDS
+        return fields_lds_bytes(tg, dtype) + deposit_lds_bytes(dense_rnp(tg), block, tb, ab);
     }
     return fields_lds_bytes(tg, dtype) + (((size_t)tg.rnp * 10 * ab + 15) & ~(size_t)15);
 }
@@ -864,6 +1185,14 @@ static void fused_launch(const TileJob<TP, TF, TA> &job, int chunk, int glog, si
     auto k = k_fused_tiled<TP, TF, TA, CACHE, MOVE_ONLY, GEO>;
     allow_lds(k, lds);
     hipLaunchKernelGGL(k, dim3(8 * chunk), dim3(block), lds, s, job, chunk, glog);
+}
+
+// The dense moment region of a tiling (the sorted deposit's LDS layout).
+static TileGeom dense_geom(const TileGeom &tg) {
+    TileGeom dg = tg;
+    const RegionLayout lay = region_layout(tg.tx, tg.ty, tg.tz, tg.halo, tg.slow, tg.mid, tg.fast, 2);
+    dg.sx = lay.sx; dg.sy = lay.sy; dg.sz = lay.sz; dg.rnp = lay.rnp;
+    return dg;
 }
 
 // The mover launch of variant 2 stages its own field region, by default
@@ -913,9 +1242,8 @@ static void split_launch(const TileJob<TP, TF, TA> &job, int chunk, const Launch
     }
     if (!job.mom) return;
     TileJob<TP, TF, TA> dj = job;
-    const RegionLayout lay = region_layout(tg.tx, tg.ty, tg.tz, tg.halo, tg.slow, tg.mid, tg.fast, 2);
-    dj.tg.sx = lay.sx; dj.tg.sy = lay.sy; dj.tg.sz = lay.sz; dj.tg.rnp = lay.rnp;
-    const size_t dl = deposit_lds_bytes(lay.rnp, cfg.tile_block, sizeof(TP), sizeof(TA));
+    dj.tg = dense_geom(tg);
+    const size_t dl = deposit_lds_bytes(dj.tg.rnp, cfg.tile_block, sizeof(TP), sizeof(TA));
     if (cfg.fixed_geo && geo_is<GeoDense>(dj.tg)) {
         auto k = k_deposit_tiled<TP, TF, TA, GeoDense>;
         allow_lds(k, dl);
@@ -927,11 +1255,36 @@ static void split_launch(const TileJob<TP, TF, TA> &job, int chunk, const Launch
     }
 }
 
+// Variant 3: one launch, the mover's field region (mover_geom, within the
+// LDS the deposit leaves) beside the deposit's dense moment region.
+template <typename TP, typename TF, typename TA>
+static void lanecell_launch(const TileJob<TP, TF, TA> &job, int chunk, const LaunchCfg &cfg, hipStream_t s) {
+    constexpr int dt = sizeof(TP) == 8 ? SPIC_F64 : SPIC_F32;
+    const TileGeom tgm = dense_geom(job.tg);
+    const size_t dl = deposit_lds_bytes(tgm.rnp, cfg.tile_block, sizeof(TP), sizeof(TA));
+    TileJob<TP, TF, TA> mv = job;
+    mv.tg = mover_geom(job.tg, cfg.mover_halo, cfg.lds_max > dl ? cfg.lds_max - dl : 0, dt);
+    const size_t lds = fields_lds_bytes(mv.tg, dt) + dl;
+    const bool fixed = cfg.fixed_geo && geo_is<GeoMover2>(mv.tg) && geo_is<GeoDense>(tgm);
+    auto k = cfg.mover_cache ? (fixed ? k_lanecell_tiled<TP, TF, TA, true, GeoMover2, GeoDense>
+                                      : k_lanecell_tiled<TP, TF, TA, true, GeoRuntime, GeoRuntime>)
+                             : (fixed ? k_lanecell_tiled<TP, TF, TA, false, GeoMover2, GeoDense>
+                                      : k_lanecell_tiled<TP, TF, TA, false, GeoRuntime, GeoRuntime>);
+    allow_lds(k, lds);
+    hipLaunchKernelGGL(k, dim3(8 * chunk), dim3(cfg.tile_block), lds, s, mv, tgm, chunk, cfg.tile_group);
+}
+
 template <typename TP, typename TF, typename TA, class GEO>
 static void tiled_variant(const TileJob<TP, TF, TA> &job, int chunk, size_t lds, const LaunchCfg &cfg,
                           hipStream_t s) {
     switch (cfg.variant) {
-        case 2: split_launch<TP, TF, TA, GEO>(job, chunk, cfg, s); break;
+        case kVariantLaneCell:
+            // FP64 particles: 160 VGPRs of sums leave no room for the mover
+            if constexpr (sizeof(TP) == 8) split_launch<TP, TF, TA, GEO>(job, chunk, cfg, s);
+            else if (job.mom) lanecell_launch<TP, TF, TA>(job, chunk, cfg, s);
+            else split_launch<TP, TF, TA, GEO>(job, chunk, cfg, s);  // no moments: the mover launch alone
+            break;
+        case kVariantSplit: split_launch<TP, TF, TA, GEO>(job, chunk, cfg, s); break;
         case 1:
             fused_launch<TP, TF, TA, true, false, GEO>(job, chunk, cfg.tile_group, lds, cfg.tile_block, s);
             break;
@@ -983,8 +1336,8 @@ hipError_t launch_fused_tiled(const spic_grid &g, const spic_params &prm, const 
 //
 // The batch engine drives the persistent work-list kernels over tiles of
 // many (run, species) jobs of one precision combination per launch:
-// variants 0 and 1 in one launch, variant 2 as a mover list and then a
-// deposit list over the same items.
+// variants 0 and 1 in one launch, variants 2 and 3 as a mover list and then
+// a deposit list over the same items.
 
 int job_combo(int dtype, int fdtype, int acc_dtype) {
     if (acc_dtype == SPIC_F32C) return -1;  // compensated FP32: the unsorted spic_mover path only
@@ -1050,7 +1403,8 @@ template <typename TP, typename TF, typename TA, class GEO>
 static WorklistGroups worklist_groups_t(int variant, const TileGeom &tg, int block, int nitems, int max_groups) {
     constexpr int dt = sizeof(TP) == 8 ? SPIC_F64 : SPIC_F32, at = sizeof(TA) == 8 ? SPIC_F64 : SPIC_F32;
     WorklistGroups r{};
-    if (variant == 2) {
+    if (variant == kVariantLaneCell) variant = kVariantSplit;  // the lists run variant 3 as variant 2
+    if (variant == kVariantSplit) {
         r.lds_mover = fields_lds_bytes(tg, dt);
         r.lds_deposit = deposit_lds_bytes(dense_rnp(tg), block, sizeof(TP), sizeof(TA));
         r.mover = resident_groups(k_worklist<TP, TF, TA, true, true, GEO>, r.lds_mover, 512, nitems, max_groups);
@@ -1086,7 +1440,7 @@ static hipError_t worklist_t(int variant, const void *jobs, const uint2 *items, 
                              const WorklistGroups &gr, int block, hipStream_t s) {
     using Job = TileJob<TP, TF, TA>;
     const Job *jb = (const Job *)jobs;
-    if (variant == 2) {
+    if (variant == kVariantSplit || variant == kVariantLaneCell) {
         hipLaunchKernelGGL((k_worklist<TP, TF, TA, true, true, GEO>), dim3(gr.mover), dim3(512), gr.lds_mover, s,
                            jb, items, nitems, counters);
         hipError_t e = hipGetLastError();

@@ -127,9 +127,12 @@ def test_options(hctx):
     hctx.set_option("mover_cache", 0)
     with pytest.raises(spic.SpicError):
         hctx.set_option("mover_cache", 2)
-    for bad in (-2, 3):
+    for bad in (-2, 4):
         with pytest.raises(spic.SpicError):
             hctx.set_option("tile_variant", bad)
+    hctx.set_option("tile_variant", 3)
+    assert hctx.get_option("tile_variant") == 3
+    hctx.set_option("tile_variant", -1)
     assert hctx.get_option("tile_group") == 4  # unset: the library default (groups of 16)
     hctx.set_option("tile_group", -1)
     assert hctx.get_option("tile_group") == -1
@@ -212,7 +215,7 @@ def test_autotune_cache_roundtrip(tmp_path, monkeypatch):
     assert len(list(autotune.candidates(quick=True))) == 12
     # FP64 particles: only the one-kernel variants are candidates
     assert {c["tile_variant"] for c in autotune.candidates(False, "f64")} == {0, 1}
-    assert {c["tile_variant"] for c in autotune.candidates(False, "f32")} == {0, 1, 2}
+    assert {c["tile_variant"] for c in autotune.candidates(False, "f32")} == {0, 1, 2, 3}
     # the engine spaces: block x cadence x batch length, all distinct
     for cands, keys in ((autotune.engine_candidates(True), ("tile_block", "sort_every", "tick_items")),
                         (autotune.engine_candidates(False), ("tile_block", "sort_every", "tick_items")),

@@ -279,14 +279,16 @@ def _fp32_one_step_check(h, run, sps):
     return worst
 
 
-def test_fp32_work_list_run_matches_oracle(spic):
+@pytest.mark.parametrize("variant", [-1, 3])
+def test_fp32_work_list_run_matches_oracle(spic, variant):
     """The batch engine's FP32-particle path (work-list launches, FP64
     moments) on three boxes of different shape: one step each against the
-    oracle."""
+    oracle (variant 3 runs the split lists there)."""
     ctx = spic.Context(0)
+    ctx.set_option("tile_variant", variant)
     boxes = _boxes()
     made = [_run_of(spic, h, 1, dtype=torch.float32) for h in boxes]
-    _say("case batch fp32 work list: 3 boxes x 1 step")
+    _say("case batch fp32 work list: 3 boxes x 1 step, variant %d" % variant)
     for t in spic.spic_batch_submit(ctx, [m[0] for m in made]):
         spic.spic_wait(ctx, t)
     for h, (run, sps) in zip(boxes, made):
@@ -312,14 +314,17 @@ def test_streamed_fp64_run_matches_oracle(spic):
     ctx.close()
 
 
-def test_streamed_fp32_step_matches_oracle(spic):
+@pytest.mark.parametrize("variant", [-1, 3])
+def test_streamed_fp32_step_matches_oracle(spic, variant):
     """The same box streamed with FP32 particles (FP64 moments): one step
-    against the oracle at the FP32 tolerances."""
+    against the oracle at the FP32 tolerances (variant 3: the one-launch
+    kernel per streamed batch)."""
     h = W.harris_32x16x4()
     ctx = spic.Context(0, hbm_budget_bytes=3 << 20)
     ctx.set_option("batch_particles", 8192)
+    ctx.set_option("tile_variant", variant)
     run, sps = _run_of(spic, h, 1, dtype=torch.float32, host=True)
-    _say("case streamed fp32 vs oracle, budget 3 MiB, batches of 8192")
+    _say("case streamed fp32 vs oracle, budget 3 MiB, batches of 8192, variant %d" % variant)
     spic.spic_wait(ctx, spic.spic_batch_submit(ctx, [run])[0])
     _say("streamed fp32: pos/L %.2e vel %.2e mom %.2e" % tuple(_fp32_one_step_check(h, run, sps)))
     ctx.close()

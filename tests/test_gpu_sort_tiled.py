@@ -172,7 +172,7 @@ def test_tiled_fp64_every_step_matches_oracle(spic, ctx, variant):
     _gpu_steps(spic, ctx, h, f, sps, h.qoms, 10, check=check)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_tiled_fp32_one_step(spic, ctx, variant):
     ctx.set_option("tile_variant", variant)
     h = W.harris_32x16x4()
@@ -185,6 +185,59 @@ def test_tiled_fp32_one_step(spic, ctx, variant):
         ora = O.mover(h.grid, h.dt, h.c, h.niter, h.qoms[s], f64, W.upcast(sps[s]))
         P.assert_state(st[s], ora, h.grid, P.POS32, P.VEL32, vscale=max(P.vmax(ora), h.vths[s]))
         P.assert_moments(ms[s], O.deposit(h.grid, W.upcast(st[s])), P.MOM32)
+
+
+# FP32 cases for the one-launch variant: (grid, species maker, tile, halo,
+# steps, sort cadence)
+def _lanecell_case(name):
+    h = W.harris_32x16x4()
+    g = h.grid
+    if name in ("harris", "harris_block512"):
+        return h, W.make_all_species(h), h.qoms, (4, 4, 4), 1, 6, 3
+    if name == "tiles_2x4x8":
+        return h, W.make_all_species(h), h.qoms, (2, 4, 8), 1, 4, 2
+    if name == "tiles_3x3x3_halo2":
+        return h, W.make_all_species(h), h.qoms, (3, 3, 3), 2, 4, 2
+    if name == "fast":  # particles leave their tile and the region
+        return h, [W.random_particles(g, 20011, 2.0, seed=7), W.make_species(h, W.SHEET_I)], [-64.0, 1.0], \
+            (4, 4, 4), 1, 3, 2
+    if name == "crowded":  # one tile: full bins, then an out list past its capacity
+        hc = W.Harris(W.Grid(4, 4, 4, 2.0, 2.0, 2.0), ppc=8)
+        return hc, [W.random_particles(hc.grid, 40000, 0.5, seed=3), W.random_particles(hc.grid, 30000, 0.1, seed=4)], \
+            [-64.0, 1.0], (4, 4, 4), 1, 3, 1
+    hs = W.Harris(W.Grid(5, 3, 2, 3.0, 2.0, 1.0), ppc=8)  # tiny: periodic images alias in the region
+    return hs, [W.make_species(hs, s) for s in range(4)], hs.qoms, (4, 4, 4), 1, 3, 1
+
+
+@pytest.mark.parametrize("case", ["harris", "harris_block512", "tiles_2x4x8", "tiles_3x3x3_halo2", "fast", "crowded",
+                                  "tiny"])
+def test_one_launch_variant_matches_split_fp32(spic, ctx, case):
+    """Variant 3 (the mover and the sorted register deposit in one launch)
+    against variant 2 on the same FP32 input: the particles are bitwise
+    equal by id (the same mover arithmetic), the moments agree to the FP32
+    partial sums' rounding, and the moments of the last step match the
+    oracle's deposit of the moved state."""
+    h, sps, qoms, tile, halo, nsteps, cadence = _lanecell_case(case)
+    f32 = {k: v.astype(np.float32) for k, v in W.make_fields(h).items()}
+    s32 = [W.round_state(x, np.float32) for x in sps]
+    runs = []
+    for variant in (2, 3):
+        c = spic.Context(0)
+        c.set_option("tile_x", tile[0]); c.set_option("tile_y", tile[1]); c.set_option("tile_z", tile[2])
+        c.set_option("halo", halo)
+        c.set_option("tile_variant", variant)
+        if case == "harris_block512":
+            c.set_option("tile_block", 512)
+        _say("case one-launch fp32 %s variant %d (%d steps, sort every %d)" % (case, variant, nsteps, cadence))
+        runs.append(_gpu_steps(spic, c, h, f32, s32, qoms, nsteps, dtype=torch.float32, sort_every=cadence))
+        c.close()
+    (a_st, a_m), (b_st, b_m) = runs
+    for s in range(len(sps)):
+        a, b = P.by_id(a_st[s]), P.by_id(b_st[s])
+        for k in ("x", "y", "z", "u", "v", "w", "q"):
+            assert np.array_equal(a[k], b[k]), (s, k)
+        P.assert_moments(b_m[s], a_m[s], P.MOM32)
+        P.assert_moments(b_m[s], O.deposit(h.grid, W.upcast(b_st[s])), P.MOM32)
 
 
 @pytest.mark.parametrize("tile,halo,variant", [((4, 4, 4), 0, 0), ((4, 4, 4), 0, 2), ((2, 4, 8), 1, 1),
