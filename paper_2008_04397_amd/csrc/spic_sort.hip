@@ -98,6 +98,8 @@ k_sort_keys(GridT<T> g, TileGeom tg, const T *__restrict__ x, const T *__restric
 // that stayed.  Correct for any partition of [0, n).
 constexpr uint32_t kImmigrant = 0x80000000u;
 
+constexpr int kKeysU = 4;
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_sort_keys_tiled(GridT<T> g, TileGeom tg, const T *__restrict__ x, const T *__restrict__ y,
@@ -109,15 +111,29 @@ k_sort_keys_tiled(GridT<T> g, TileGeom tg, const T *__restrict__ x, const T *__r
         __syncthreads();
         const uint32_t b = prev_off[t], e = prev_off[t + 1];
         const uint32_t key0 = (uint32_t)t * (uint32_t)tg.cells;
-        for (uint32_t p = b + threadIdx.x; p < e; p += blockDim.x) {
-            const int i = sort_locate(x[p], g.L[0], g.invL[0], g.invd[0], g.nx);
-            const int j = sort_locate(y[p], g.L[1], g.invL[1], g.invd[1], g.ny);
-            const int k = sort_locate(z[p], g.L[2], g.invL[2], g.invd[2], g.nz);
-            const uint32_t key = tile_key(tg, i, j, k);
-            uint32_t r;
-            if (key - key0 < (uint32_t)tg.cells) r = atomicAdd(&lc[key - key0], 1u);
-            else r = atomicAdd(imm + key, 1u) | kImmigrant;
-            keyrank[p] = make_uint2(key, r);
+        // kKeysU particles per thread: their positions are loaded together
+        // (an index past the range is clamped and its result dropped)
+        for (uint32_t p0 = b + threadIdx.x; p0 < e; p0 += kKeysU * blockDim.x) {
+            T px[kKeysU], py[kKeysU], pz[kKeysU];
+#pragma unroll
+            for (int u = 0; u < kKeysU; ++u) {
+                const uint32_t p = min(p0 + u * blockDim.x, e - 1);
+                px[u] = x[p]; py[u] = y[p]; pz[u] = z[p];
+            }
+#pragma unroll
+            for (int u = 0; u < kKeysU; ++u) {
+                const uint32_t p = p0 + u * blockDim.x;
+                if (p < e) {
+                    const int i = sort_locate(px[u], g.L[0], g.invL[0], g.invd[0], g.nx);
+                    const int j = sort_locate(py[u], g.L[1], g.invL[1], g.invd[1], g.ny);
+                    const int k = sort_locate(pz[u], g.L[2], g.invL[2], g.invd[2], g.nz);
+                    const uint32_t key = tile_key(tg, i, j, k);
+                    uint32_t r;
+                    if (key - key0 < (uint32_t)tg.cells) r = atomicAdd(&lc[key - key0], 1u);
+                    else r = atomicAdd(imm + key, 1u) | kImmigrant;
+                    keyrank[p] = make_uint2(key, r);
+                }
+            }
         }
         __syncthreads();
         if (threadIdx.x < tg.cells) own[key0 + threadIdx.x] = lc[threadIdx.x];
@@ -500,9 +516,12 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 k_sort_gather_tiled(PartPtrs<T> src, PartPtrs<T> dst, int64_t n, const uint32_t *__restrict__ srcidx,
                     const uint32_t *__restrict__ old_off, const uint32_t *__restrict__ offsets, int cells,
-                    int ntiles) {
+                    int ntiles, int chunk, int glog) {
     __shared__ __align__(16) unsigned char lds[kGatherLdsBytes];
-    const int t = blockIdx.x;
+    // tiles dealt to the XCDs in groups, as the tiled kernels do: the
+    // particles that changed tile are read from neighbouring tiles' ranges,
+    // which then sit in the same L2 more often
+    const int t = tile_of_block(blockIdx.x, chunk, glog);
     if (t >= ntiles) return;
     const uint32_t nb = offsets[(uint32_t)t * (uint32_t)cells], ne = offsets[(uint32_t)(t + 1) * (uint32_t)cells];
     // clamped to [0, n] so that stale ranges cannot send a read out of bounds
@@ -665,8 +684,9 @@ static hipError_t sort_t(const spic_grid &g, const SpeciesWork &w, const TileGeo
                            tg.cells, prev ? (const uint32_t *)own : nullptr, srcidx);
     }
     if (prev)  // tile_off still holds the previous sort's tile ranges
-        hipLaunchKernelGGL((k_sort_gather_tiled<T>), dim3(tg.ntiles), dim3(256), 0, s, src, tmp, n, srcidx,
-                           (const uint32_t *)tile_off, offsets, tg.cells, tg.ntiles);
+        hipLaunchKernelGGL((k_sort_gather_tiled<T>), dim3(8 * tile_chunk(tg.ntiles, kTileGroup)), dim3(256), 0, s,
+                           src, tmp, n, srcidx, (const uint32_t *)tile_off, offsets, tg.cells, tg.ntiles,
+                           tile_chunk(tg.ntiles, kTileGroup), kTileGroup);
     else
         hipLaunchKernelGGL((k_sort_gather<T>), dim3(gp > 0 ? gp : 1), dim3(256), 0, s, src, tmp, n, srcidx);
     if (sorted_out) {  // the next kernel reads the reordered copy and writes w's arrays

@@ -1047,19 +1047,6 @@ __device__ __forceinline__ void lanecell_body(const TileJob<TP, TF, TA> &J, cons
 
 // ---------------------------------------------------------------- kernels
 
-// Tile of workgroup b (workgroup b runs on XCD b % 8).  Slab mapping (glog
-// < 0): XCD x takes the contiguous tiles [x * chunk, (x + 1) * chunk), so
-// a slab's fields and moments stay in that XCD's L2.  Group mapping (glog
-// >= 0): groups of 2^glog consecutive tiles are dealt to the XCDs in turn,
-// for launches whose particles occupy a contiguous fraction of the tiles
-// (a streamed batch), which slabs would give to one XCD.  `chunk` is the
-// number of workgroups per XCD (tile_chunk).
-__host__ __device__ __forceinline__ int tile_of_block(int b, int chunk, int glog) {
-    if (glog < 0) return (b & 7) * chunk + (b >> 3);
-    const int r = b >> 3;
-    return ((((r >> glog) << 3) + (b & 7)) << glog) | (r & ((1 << glog) - 1));
-}
-
 // Register budget of the mover-carrying kernels in waves per SIMD: the
 // field-corner cache holds 48 values (96 VGPRs in FP64).
 template <bool CACHE, typename TP>
