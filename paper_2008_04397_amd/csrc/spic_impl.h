@@ -99,7 +99,8 @@ __host__ __device__ __forceinline__ int tile_of_block(int b, int chunk, int glog
 // Tiled-kernel variants (spic_tiled.hip): 0 one kernel with LDS-atomic
 // deposits, 1 the same with the field corners of a thread's last cell in
 // registers, 2 two launches -- the mover, then the sorted deposit into
-// per-lane register sums.  Defaults, measured fastest on the Harris boxes:
+// per-lane register sums, 3 both in one launch (FP32 particles; measured
+// as fast as 2, not faster).  Defaults, measured fastest on the Harris boxes:
 // 2 for FP32 particles, 1 for FP64 (the sorted deposit's 80 register sums
 // take 160 VGPRs in FP64, which leaves it two waves per SIMD and spills).
 // Workgroup size when the options leave it to the library: 512 for

@@ -796,19 +796,12 @@ __device__ __forceinline__ void dep_finish(const DepTile<TP, TA> &d, const GridT
 }
 
 // Deposit of the moved particles of tile t (the second launch of variant
-// 2).  Lane l of every wave owns local cell l of the tile and keeps the
-// moments of its 8 nodes (80 sums) in registers.  The tile's range is read
-// in rows of 64 slots (coalesced; after a sort in full rows slot (r, l)
-// holds a particle of cell l): a particle still in its slot's cell is added
-// to the lane's sums at once; one that moved to another cell of the tile
-// is binned by its new cell (an index in LDS), one that left the tile (or
-// found its bin full) goes to the out list.  Then lane (w, l) adds the
-// entries w, w + W, ... of cell l's bin to its sums, the sums are added to
-// the region, and the out list is deposited 64 at a time, bank-balanced,
-// with FP64 terms and LDS atomics (global atomics beyond the region).  A
-// tile whose out list overflows (or of 65536 particles or more) drops the
-// sums and lists and deposits every particle with LDS atomics instead.  The
-// region is then flushed to the global moments.
+// 2): the sorted deposit described above, over rows of 64 slots read
+// coalesced with kDepPrefetch rows per thread in flight.  It performs the
+// steps of dep_open, dep_route, dep_drain and dep_finish with its own
+// locals rather than through DepTile: written through the helpers, this
+// kernel keeps more values live across its bin drain, spills twice as many
+// registers there, and runs about a tenth slower.
 template <typename TP, typename TF, typename TA, class GEO>
 __device__ __forceinline__ void deposit_body(const TileJob<TP, TF, TA> &J, int t, unsigned char *smem) {
     TileGeom tg = J.tg;
