@@ -362,9 +362,31 @@ __device__ __forceinline__ void block_partial(double acc, double *part) {
     }
 }
 
-// CG with its scalars on the device (no host round trip per iteration), each
-// dot product fused into the kernel that writes its vector; sc[1] = p.Ap,
-// r.r alternates between sc[ia] (current) and sc[ib] (new).
+// The sum of part[0 .. n) in a fixed order, the same bits in every block: a
+// kernel that needs a dot product reduces the previous kernel's block
+// partials itself, in each of its blocks, instead of a one-block reduction
+// launch between the two.
+__device__ __forceinline__ double block_sum(const double *__restrict__ part, int n) {
+    __shared__ double red[kBlock / 64];
+    __shared__ double total;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < n; b += blockDim.x) acc += part[b];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += red[q];
+        total = s;
+    }
+    __syncthreads();
+    return total;
+}
+
+// CG with its scalars on the device (no host round trip per iteration) in
+// three kernels per iteration, each dot product fused into the kernel that
+// writes its vector and reduced by the kernel that uses it; r.r alternates
+// between sc[ia] (current) and sc[ib] (new).
 // Ap = -div grad p, and the block partials of p . Ap
 __global__ void k_cg_ap(Geo g, int64_t N, const double *__restrict__ p, double *__restrict__ Ap,
                         double *__restrict__ part) {
@@ -379,14 +401,15 @@ __global__ void k_cg_ap(Geo g, int64_t N, const double *__restrict__ p, double *
     block_partial(acc, part);
 }
 
-// phi += alpha p, r -= alpha Ap with alpha = r.r / p.Ap, and the block
-// partials of the new r . r; alpha = 0 once r.r <= thr2, so the iterations
-// a batch runs past convergence change nothing (CG continued past
-// convergence lets the residual wander)
+// phi += alpha p, r -= alpha Ap with alpha = r.r / p.Ap (p.Ap from the
+// nap partials of k_cg_ap), and the block partials of the new r . r;
+// alpha = 0 once r.r <= thr2, so the iterations a batch runs past
+// convergence change nothing (CG continued past convergence lets the
+// residual wander)
 __global__ void k_cg_x(int64_t N, const double *sc, int ia, double thr2, const double *__restrict__ p,
                        const double *__restrict__ Ap, double *__restrict__ phi, double *__restrict__ r,
-                       double *__restrict__ part) {
-    const double rr = dev_scalar(sc + ia), pap = dev_scalar(sc + 1);
+                       const double *__restrict__ part_ap, int nap, double *__restrict__ part) {
+    const double rr = dev_scalar(sc + ia), pap = block_sum(part_ap, nap);
     const double alpha = (pap > 0.0 && rr > thr2) ? rr / pap : 0.0;
     double acc = 0.0;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N; t += (int64_t)gridDim.x * blockDim.x) {
@@ -398,10 +421,12 @@ __global__ void k_cg_x(int64_t N, const double *sc, int ia, double thr2, const d
     block_partial(acc, part);
 }
 
-// p = r + beta p with beta = new r.r / r.r
-__global__ void k_cg_p(int64_t N, const double *sc, int ia, int ib, const double *__restrict__ r,
-                       double *__restrict__ p) {
-    const double rr = dev_scalar(sc + ia), rr1 = dev_scalar(sc + ib);
+// p = r + beta p with beta = new r.r / r.r (new r.r from the nrr partials
+// of k_cg_x; block 0 stores it in sc[ib] for the next iteration and the host)
+__global__ void k_cg_p(int64_t N, double *sc, int ia, int ib, const double *__restrict__ r,
+                       double *__restrict__ p, const double *__restrict__ part_rr, int nrr) {
+    const double rr = dev_scalar(sc + ia), rr1 = block_sum(part_rr, nrr);
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc[ib] = rr1;
     const double beta = rr > 0.0 ? rr1 / rr : 0.0;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N; t += (int64_t)gridDim.x * blockDim.x)
         p[t] = r[t] + beta * p[t];
@@ -557,19 +582,19 @@ int spic_ctx_s::field_cycle(const spic_grid &gr, const spic_field_params &fp, sp
     // iterations (past convergence the device stops moving phi and r)
     constexpr int kCgCheck = 8;
     int it = 0;
-    double *sc = wk.dres;  // [0] / [2] r.r (alternating), [1] p.Ap
+    double *sc = wk.dres;  // [0] / [2] r.r (alternating)
+    double *part_ap = wk.part, *part_rr = wk.part + nred;
     const double thr2 = (tol * bnorm_c) * (tol * bnorm_c);
     const dim3 gred(nred);
     int ia = 0, ib = 2;
     while (wk.err == hipSuccess && bnorm_c > 0.0 && std::sqrt(rr) > tol * bnorm_c && it < fp.max_iter) {
         const int batch = std::min(kCgCheck, fp.max_iter - it);
         for (int q = 0; q < batch; ++q) {
-            hipLaunchKernelGGL(k_cg_ap, gred, bk, 0, s, g, N, (const double *)pp, Ap, wk.part);
-            hipLaunchKernelGGL(k_msum, dim3(1), bk, 0, s, (const double *)wk.part, nred, sc + 1, 0);
+            hipLaunchKernelGGL(k_cg_ap, gred, bk, 0, s, g, N, (const double *)pp, Ap, part_ap);
             hipLaunchKernelGGL(k_cg_x, gred, bk, 0, s, N, (const double *)sc, ia, thr2, (const double *)pp,
-                               (const double *)Ap, phi, r, wk.part);
-            hipLaunchKernelGGL(k_msum, dim3(1), bk, 0, s, (const double *)wk.part, nred, sc + ib, 0);
-            hipLaunchKernelGGL(k_cg_p, gn, bk, 0, s, N, (const double *)sc, ia, ib, (const double *)r, pp);
+                               (const double *)Ap, phi, r, (const double *)part_ap, nred, part_rr);
+            hipLaunchKernelGGL(k_cg_p, gn, bk, 0, s, N, sc, ia, ib, (const double *)r, pp, (const double *)part_rr,
+                               nred);
             std::swap(ia, ib);
         }
         wk.launched();
