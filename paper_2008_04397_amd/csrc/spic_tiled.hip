@@ -525,9 +525,13 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
 //
 // kDepCap indices per cell hold the particles that moved into a tile cell
 // other than the one their slot belongs to; kDepOutCap those that left the
-// tile (16-bit indices into the tile's range).  kDepPrefetch particles per
-// thread are in flight while one is deposited.
-constexpr int kDepCap = 48;
+// tile or found their bin full (16-bit indices into the tile's range).  The
+// bins are drained by the cell's owner lanes, so the fullest bin sets the
+// length of the drain; past kDepCap a particle is cheaper in the out list,
+// which is deposited 64 at a time (measured on the 128x64x32 box: 24 beats
+// 48, 32, 16, 12 and 8).  kDepPrefetch particles per thread are in flight
+// while one is deposited.
+constexpr int kDepCap = 24;
 constexpr int kDepOutCap = 2048;
 constexpr int kDepPrefetch = 2;
 constexpr int kDepWaves = 3;  // register budget: waves per SIMD (FP32 particles)
