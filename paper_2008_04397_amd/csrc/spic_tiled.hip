@@ -375,17 +375,41 @@ __device__ __forceinline__ void flush_region(const TileGeom &tg, int nx, int ny,
     }
 }
 
+// The first particle of thread k's slots in a tile (beg + k), loaded by the
+// caller before it stages the tile's fields, so the load overlaps that
+// staging and its barrier instead of following them.
+template <typename TP>
+struct FirstRec {
+    TP x, y, z, u, v, w, q;
+    int64_t id;
+};
+
+template <typename TP, typename TF, typename TA>
+__device__ __forceinline__ FirstRec<TP> load_first(const TileJob<TP, TF, TA> &J, uint32_t beg, uint32_t end) {
+    FirstRec<TP> r{};
+    const uint32_t i = beg + threadIdx.x;
+    const PartPtrs<TP> &pin = J.in;
+    if (i < end) {
+        const uint32_t o = i * (uint32_t)sizeof(TP);
+        r.x = ld32(pin.x, o); r.y = ld32(pin.y, o); r.z = ld32(pin.z, o);
+        r.u = ld32(pin.u, o); r.v = ld32(pin.v, o); r.w = ld32(pin.w, o); r.q = ld32(pin.q, o);
+        if (J.copy_rest && pin.id) r.id = pin.id[i];
+    }
+    return r;
+}
+
 // Moves the particles [beg, end) of one tile (Eq. 1, Eq. 2, Eq. 5),
 // gathering E and B (Eq. 3, Eq. 4) from the region fields `fl` staged with
 // origin (ox, oy, oz), and stores the new state.  Thread k takes slots
-// beg + k, beg + k + blockDim.x, ...; the loop is uniform per wave, and
+// beg + k, beg + k + blockDim.x, ... (the first one in `first`, from
+// load_first); the loop is uniform per wave, and
 // after each slot every lane calls done(i, valid, x, y, z, u, v, w, q) with
 // the moved particle (valid is false past the range, where the values are
 // stale).
 template <typename TP, typename TF, typename TA, bool CACHE, typename Done>
 __device__ __forceinline__ void move_tile(const TileJob<TP, TF, TA> &J, const TileGeom &tg,
                                           const LdsFieldNode<TP> *__restrict__ fl, int ox, int oy, int oz,
-                                          uint32_t beg, uint32_t end, Done &&done) {
+                                          uint32_t beg, uint32_t end, const FirstRec<TP> &first, Done &&done) {
     const GridT<TP> &g = J.g;
     const FieldPtrs<TF> &f = J.f;
     const PartPtrs<TP> &p = J.p;
@@ -397,16 +421,10 @@ __device__ __forceinline__ void move_tile(const TileJob<TP, TF, TA> &J, const Ti
     const uint32_t stride = blockDim.x;
     constexpr uint32_t ES = sizeof(TP);
     uint32_t i = beg + threadIdx.x;
-    TP nx_ = 0, ny_ = 0, nz_ = 0, nu_ = 0, nv_ = 0, nw_ = 0, nq_ = 0;
-    int64_t nid_ = 0;
+    TP nx_ = first.x, ny_ = first.y, nz_ = first.z, nu_ = first.u, nv_ = first.v, nw_ = first.w, nq_ = first.q;
+    int64_t nid_ = first.id;
     const PartPtrs<TP> &pin = J.in;
     const bool copy_id = J.copy_rest && pin.id;  // ids move with the sort's copy
-    if (i < end) {
-        const uint32_t o = i * ES;
-        nx_ = ld32(pin.x, o); ny_ = ld32(pin.y, o); nz_ = ld32(pin.z, o);
-        nu_ = ld32(pin.u, o); nv_ = ld32(pin.v, o); nw_ = ld32(pin.w, o); nq_ = ld32(pin.q, o);
-        if (copy_id) nid_ = pin.id[i];
-    }
     // uniform per wave: the first index of this wave's lane 0
     for (uint32_t i0 = beg + (threadIdx.x & ~63u); i0 < end; i0 += stride, i += stride) {
         const bool valid = i < end;
@@ -502,13 +520,15 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
     const TilePlace tp = tile_place(tg, g.nx, g.ny, g.nz, t);
     const int ox = tp.ox, oy = tp.oy, oz = tp.oz;
 
-    // stage the region's node fields, zero the region's moments
+    // the first particle in flight while the region's node fields are
+    // staged and its moments zeroed
+    const FirstRec<TP> first = load_first(J, beg, end);
     stage_fields<TP, TF>(J.f, tg, g.nx, g.ny, g.nz, ox, oy, oz, fl);
     if (mom)
         for (int q = threadIdx.x; q < 10 * RNP; q += blockDim.x) ml[q] = TA(0);
     __syncthreads();
 
-    move_tile<TP, TF, TA, CACHE>(J, tg, fl, ox, oy, oz, beg, end,
+    move_tile<TP, TF, TA, CACHE>(J, tg, fl, ox, oy, oz, beg, end, first,
                                  [&](uint32_t, bool valid, TP xn, TP yn, TP zn, TP un, TP vn, TP wn, TP qp)
                                      __attribute__((always_inline)) {
                                          // deposit of the new state in the accumulation precision
@@ -841,6 +861,22 @@ __device__ __forceinline__ void deposit_body(const TileJob<TP, TF, TA> &J, int t
     StagedParticle<TP> *stage = (StagedParticle<TP> *)mine;
     BalanceLds *bal = (BalanceLds *)(mine + 64 * sizeof(StagedParticle<TP>));
 
+    constexpr uint32_t ES = sizeof(TP);
+    // unconditional loads (an index past the range is clamped to the
+    // tile's last particle, read and ignored), so a slot is refilled in place
+    auto load = [&](TP (&dst)[7], uint32_t i) __attribute__((always_inline)) {
+        const uint32_t o = min(i, end - 1) * ES;
+        dst[0] = ld32(p.x, o); dst[1] = ld32(p.y, o); dst[2] = ld32(p.z, o);
+        dst[3] = ld32(p.u, o); dst[4] = ld32(p.v, o); dst[5] = ld32(p.w, o); dst[6] = ld32(p.q, o);
+    };
+    // the first kDepPrefetch rows are in flight while the region and the
+    // counts are zeroed (unused if the tile turns out to overflow)
+    const uint32_t stride = blockDim.x;
+    uint32_t ii = beg + threadIdx.x;
+    TP ring[kDepPrefetch][7];
+#pragma unroll
+    for (int k = 0; k < kDepPrefetch; ++k) load(ring[k], ii + k * stride);
+
     const TilePlace tp = tile_place(tg, ga.nx, ga.ny, ga.nz, t);
     const int ox = tp.ox, oy = tp.oy, oz = tp.oz;
     const int RL = tg.rx * tg.ry * tg.rz;
@@ -858,15 +894,6 @@ __device__ __forceinline__ void deposit_body(const TileJob<TP, TF, TA> &J, int t
     lc[tg.slow] = lane / (t3[tg.fast] * t3[tg.mid]);
     const bool owner = lane < C;
     const int lslot = (tg.halo + lc[0]) * sx + (tg.halo + lc[1]) * sy + (tg.halo + lc[2]) * sz;
-    constexpr uint32_t ES = sizeof(TP);
-
-    // unconditional loads (an index past the range is clamped to the
-    // tile's last particle, read and ignored), so a slot is refilled in place
-    auto load = [&](TP (&dst)[7], uint32_t i) __attribute__((always_inline)) {
-        const uint32_t o = min(i, end - 1) * ES;
-        dst[0] = ld32(p.x, o); dst[1] = ld32(p.y, o); dst[2] = ld32(p.z, o);
-        dst[3] = ld32(p.u, o); dst[4] = ld32(p.v, o); dst[5] = ld32(p.w, o); dst[6] = ld32(p.q, o);
-    };
 
     if (!*oflow) {
         TP sacc[80];
@@ -906,13 +933,9 @@ __device__ __forceinline__ void deposit_body(const TileJob<TP, TF, TA> &J, int t
             return cell;
         };
 
-        // rows of 64 slots, lane l on slot l of each row
+        // rows of 64 slots, lane l on slot l of each row (ring and ii from
+        // the loads issued before the zeroing)
         {
-            const uint32_t stride = blockDim.x;
-            uint32_t ii = beg + threadIdx.x;
-            TP ring[kDepPrefetch][7];
-#pragma unroll
-            for (int k = 0; k < kDepPrefetch; ++k) load(ring[k], ii + k * stride);
             for (uint32_t i0 = beg + (threadIdx.x & ~63u); i0 < end; i0 += kDepPrefetch * stride,
                           ii += kDepPrefetch * stride) {
 #pragma unroll
@@ -1026,12 +1049,13 @@ __device__ __forceinline__ void lanecell_body(const TileJob<TP, TF, TA> &J, cons
     const size_t fbytes = (tg.rnp * sizeof(LdsFieldNode<TP>) + 15) & ~(size_t)15;
     const DepTile<TP, TA> d = dep_open<TP, TA, GEOM>(J.ga, tgm, t, beg, end, smem + fbytes);
     const TilePlace tp = tile_place(tg, g.nx, g.ny, g.nz, t);
+    const FirstRec<TP> first = load_first(J, beg, end);
     stage_fields<TP, TF>(J.f, tg, g.nx, g.ny, g.nz, tp.ox, tp.oy, tp.oz, fl);
     __syncthreads();
     TP sacc[80];
 #pragma unroll
     for (int q = 0; q < 80; ++q) sacc[q] = TP(0);
-    move_tile<TP, TF, TA, CACHE>(J, tg, fl, tp.ox, tp.oy, tp.oz, beg, end,
+    move_tile<TP, TF, TA, CACHE>(J, tg, fl, tp.ox, tp.oy, tp.oz, beg, end, first,
                                 [&](uint32_t i, bool valid, TP x, TP y, TP z, TP u, TP v, TP w, TP q)
                                     __attribute__((always_inline)) {
                                         const TP rec[7] = {x, y, z, u, v, w, q};
