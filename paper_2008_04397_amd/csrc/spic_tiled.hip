@@ -988,6 +988,15 @@ __device__ __forceinline__ void deposit_body(const TileJob<TP, TF, TA> &J, int t
             }
             // the sums stay in the particle precision until here
             settle(sacc);
+            // the particles that left the tile (or found their bin full),
+            // 64 per wave at a time, bank-balanced LDS atomics (a halo cell
+            // gets too few of them, and the cells next to the tile's faces
+            // too many, for lanes owning halo cells to pay off); the wave's
+            // first 64 are loaded before the sums go to the region
+            const int no = *ocnt;
+            int b0 = wv * 64;
+            TP rec[7];
+            if (b0 < no) load(rec, beg + olist[min(b0 + lane, no - 1)]);  // uniform
             if (owner) {
                 const int coff[8] = {0, sx, sy, sx + sy, sz, sx + sz, sy + sz, sx + sy + sz};
 #pragma unroll
@@ -997,17 +1006,12 @@ __device__ __forceinline__ void deposit_body(const TileJob<TP, TF, TA> &J, int t
                     for (int m = 0; m < 10; ++m) atomicAdd(dst + m * RNP, (TA)sacc[k * 10 + m]);
                 }
             }
-            // the particles that left the tile (or found their bin full),
-            // 64 per wave at a time, bank-balanced LDS atomics (a halo cell
-            // gets too few of them, and the cells next to the tile's faces
-            // too many, for lanes owning halo cells to pay off)
-            const int no = *ocnt;
-            for (int b0 = wv * 64; b0 < no; b0 += (int)blockDim.x) {
+            for (; b0 < no; b0 += (int)blockDim.x) {
                 const int e = b0 + lane;
-                TP rec[7];
-                load(rec, beg + olist[min(e, no - 1)]);
                 deposit_balanced<TP, TA, GEO>(ga, tg, ox, oy, oz, ml, mom, nn, stage, bal, lane, e < no, rec[0],
                                               rec[1], rec[2], rec[3], rec[4], rec[5], rec[6]);
+                const int en = b0 + (int)blockDim.x;
+                if (en < no) load(rec, beg + olist[min(en + lane, no - 1)]);  // uniform
             }
         }
     }
