@@ -549,8 +549,8 @@ __device__ __forceinline__ void tile_body(const TileJob<TP, TF, TA> &J, int t, u
 // bins are drained by the cell's owner lanes, so the fullest bin sets the
 // length of the drain; past kDepCap a particle is cheaper in the out list,
 // which is deposited 64 at a time (measured on the 128x64x32 box: 24 beats
-// 48, 32, 16, 12 and 8).  kDepPrefetch particles per thread are in flight
-// while one is deposited.
+// 48, 32, 16, 12 and 8).  In the pass over the rows kDepPrefetch particles
+// per thread are in flight while one is deposited.
 constexpr int kDepCap = 24;
 constexpr int kDepOutCap = 2048;
 constexpr int kDepPrefetch = 2;
@@ -976,15 +976,13 @@ __device__ __forceinline__ void deposit_body(const TileJob<TP, TF, TA> &J, int t
                 const int j = max(min(wv + m * nwv, mc - 1), 0);
                 return beg + bins[(owner ? lane : 0) * kDepCap + j];
             };
-            TP ring[kDepPrefetch][7];
-#pragma unroll
-            for (int k = 0; k < kDepPrefetch; ++k) load(ring[k], at(k));
-            for (int m0 = 0; __ballot(m0 < mine_n); m0 += kDepPrefetch) {
-#pragma unroll
-                for (int k = 0; k < kDepPrefetch; ++k) {
-                    (void)add_own(ring[k], m0 + k < mine_n);
-                    load(ring[k], at(m0 + k + kDepPrefetch));
-                }
+            // one entry in flight: a second slot here costs the kernel ten
+            // spilled VGPRs, whose reloads then wait for every load in flight
+            TP dr[7];
+            load(dr, at(0));
+            for (int m0 = 0; __ballot(m0 < mine_n); ++m0) {
+                (void)add_own(dr, m0 < mine_n);
+                load(dr, at(m0 + 1));
             }
             // the sums stay in the particle precision until here
             settle(sacc);
