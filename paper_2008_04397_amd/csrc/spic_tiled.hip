@@ -1118,8 +1118,7 @@ k_lanecell_tiled(TileJob<TP, TF, TA> J, TileGeom tgm, int chunk, int glog) {
 // Persistent work-list kernels: workgroups take (job, tile) items from an
 // atomic counter until the list is drained; every workgroup exits once the
 // counter passes nitems.  The counter must be zero at launch.  KIND 0:
-// variant 0/1 tile body (mover and LDS-atomic deposit), 1: mover only, 2:
-// sorted deposit.
+// variant 0/1 tile body (mover and LDS-atomic deposit), 1: mover only.
 template <int KIND, typename TP, typename TF, typename TA, bool CACHE, class GEO>
 __device__ __forceinline__ void worklist_loop(const TileJob<TP, TF, TA> *__restrict__ jobs,
                                               const uint2 *__restrict__ items, int nitems,
@@ -1132,8 +1131,7 @@ __device__ __forceinline__ void worklist_loop(const TileJob<TP, TF, TA> *__restr
         if (it >= nitems) break;
         const uint2 item = items[it];
         const TileJob<TP, TF, TA> J = jobs[item.x];
-        if constexpr (KIND == 2) deposit_body<TP, TF, TA, GEO>(J, (int)item.y, smem);
-        else tile_body<TP, TF, TA, CACHE, KIND == 1, GEO>(J, (int)item.y, smem);
+        tile_body<TP, TF, TA, CACHE, KIND == 1, GEO>(J, (int)item.y, smem);
     }
 }
 
@@ -1146,13 +1144,16 @@ k_worklist(const TileJob<TP, TF, TA> *__restrict__ jobs, const uint2 *__restrict
     worklist_loop<MOVE_ONLY ? 1 : 0, TP, TF, TA, CACHE, GEO>(jobs, items, nitems, counter, smem, &cur);
 }
 
+// The deposit list: one workgroup per (job, tile) item, the hardware
+// dispatcher balancing them.  A persistent loop over the items kept its own
+// state beside the deposit's 80 sums and spilled registers inside the bin
+// drain.
 template <typename TP, typename TF, typename TA, class GEO>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(DepositWaves<TP>::value)))
-k_worklist_deposit(const TileJob<TP, TF, TA> *__restrict__ jobs, const uint2 *__restrict__ items, int nitems,
-                   unsigned *__restrict__ counter) {
+k_items_deposit(const TileJob<TP, TF, TA> *__restrict__ jobs, const uint2 *__restrict__ items) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int cur;
-    worklist_loop<2, TP, TF, TA, false, GEO>(jobs, items, nitems, counter, smem, &cur);
+    const uint2 item = items[blockIdx.x];
+    deposit_body<TP, TF, TA, GEO>(jobs[item.x], (int)item.y, smem);
 }
 
 // ------------------------------------------------------------- host side
@@ -1418,8 +1419,8 @@ static WorklistGroups worklist_groups_t(int variant, const TileGeom &tg, int blo
         r.lds_mover = fields_lds_bytes(tg, dt);
         r.lds_deposit = deposit_lds_bytes(dense_rnp(tg), block, sizeof(TP), sizeof(TA));
         r.mover = resident_groups(k_worklist<TP, TF, TA, true, true, GEO>, r.lds_mover, 512, nitems, max_groups);
-        r.deposit = resident_groups(k_worklist_deposit<TP, TF, TA, typename DenseOf<GEO>::type>, r.lds_deposit, block, nitems,
-                                    max_groups);
+        allow_lds(k_items_deposit<TP, TF, TA, typename DenseOf<GEO>::type>, r.lds_deposit);
+        r.deposit = nitems;  // one workgroup per item
     } else {
         r.lds_mover = tiled_lds_bytes(tg, dt, at, variant, block);
         if (variant == 1)
@@ -1455,8 +1456,8 @@ static hipError_t worklist_t(int variant, const void *jobs, const uint2 *items, 
                            jb, items, nitems, counters);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_worklist_deposit<TP, TF, TA, typename DenseOf<GEO>::type>), dim3(gr.deposit), dim3(block),
-                           gr.lds_deposit, s, jb, items, nitems, counters + 1);
+        hipLaunchKernelGGL((k_items_deposit<TP, TF, TA, typename DenseOf<GEO>::type>), dim3(nitems), dim3(block),
+                           gr.lds_deposit, s, jb, items);
     } else if (variant == 1) {
         hipLaunchKernelGGL((k_worklist<TP, TF, TA, true, false, GEO>), dim3(gr.mover), dim3(block), gr.lds_mover, s,
                            jb, items, nitems, counters);
