@@ -231,7 +231,8 @@ int spic_version(void);
  *                  tile variants 2 and 3, else 0)
  *   graph          batch engine: replay unchanged ticks as a hipGraph (0/1)
  *   batch_particles  batch engine: particles per streamed batch
- *   max_groups     batch engine: cap on workgroups of the persistent launch
+ *   max_groups     batch engine: cap on workgroups of the persistent
+ *                  (mover) launch
  *   tick_items     batch engine: a tick steps the runs with the least
  *                  remaining work until it holds this many (run, species,
  *                  tile) items (default 4096; 0 = every active run)

@@ -3,9 +3,9 @@
 //
 // A scheduler thread owns three streams (compute, host->device,
 // device->host) and advances all resident runs together in "ticks": one
-// tick is one fused step of every active run, executed as ONE launch of the
-// persistent work-list kernel over the (run, species, tile) items of all of
-// them (plus the cell sort of the runs whose cadence is due, and one batched
+// tick is one fused step of every active run, executed as one work-list
+// launch (two for the split variants: mover, then deposit) over the (run,
+// species, tile) items of all of them (plus the cell sort of the runs whose cadence is due, and one batched
 // zeroing of their moments).  While the set of active runs does not change
 // and no sort is due, the tick is captured once as a hipGraph and replayed.
 //

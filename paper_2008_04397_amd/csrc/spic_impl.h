@@ -390,9 +390,10 @@ int job_combo(int dtype, int fdtype, int acc_dtype);
 size_t tile_job_bytes(int combo);
 void write_tile_job(int combo, void *dst, const spic_grid &g, const spic_params &prm, const spic_fields &f,
                     const SpeciesWork &w, const TileGeom &tg, const uint32_t *tile_off);
-// Launch sizes of one combination's persistent launches: variant 2 runs a
-// mover list (512 threads, fields) and then a deposit list (`block`
-// threads); variants 0 and 1 one list (`block` threads, `mover` fields).
+// Launch sizes of one combination's work-list launches: variant 2 runs a
+// persistent mover list (512 threads, fields) and then a deposit list of
+// one `block`-thread workgroup per item; variants 0 and 1 one persistent
+// list (`block` threads, `mover` fields).
 struct WorklistGroups {
     int mover, deposit;
     size_t lds_mover, lds_deposit;

@@ -1345,10 +1345,10 @@ hipError_t launch_fused_tiled(const spic_grid &g, const spic_params &prm, const 
 
 // ------------------------------------------------------------ work lists
 //
-// The batch engine drives the persistent work-list kernels over tiles of
-// many (run, species) jobs of one precision combination per launch:
-// variants 0 and 1 in one launch, variants 2 and 3 as a mover list and then
-// a deposit list over the same items.
+// The batch engine drives the work-list kernels over tiles of many (run,
+// species) jobs of one precision combination per launch: variants 0 and 1
+// in one persistent launch, variants 2 and 3 as a persistent mover list and
+// then a deposit list of one workgroup per item over the same items.
 
 int job_combo(int dtype, int fdtype, int acc_dtype) {
     if (acc_dtype == SPIC_F32C) return -1;  // compensated FP32: the unsorted spic_mover path only
@@ -1407,9 +1407,10 @@ static int resident_groups(K k, size_t lds, int block, int nitems, int max_group
 }
 
 // Workgroups of the persistent launches (the mover list at 512 threads, the
-// deposit list and the one-launch variants at `block`): resident workgroups
-// per CU times CUs, capped by the item count (and by max_groups when > 0).
-// Also allows the LDS size; call before any stream capture.
+// one-launch variants at `block`): resident workgroups per CU times CUs,
+// capped by the item count (and by max_groups when > 0); the deposit list
+// has one workgroup (`block` threads) per item.  Also allows the LDS sizes;
+// call before any stream capture.
 template <typename TP, typename TF, typename TA, class GEO>
 static WorklistGroups worklist_groups_t(int variant, const TileGeom &tg, int block, int nitems, int max_groups) {
     constexpr int dt = sizeof(TP) == 8 ? SPIC_F64 : SPIC_F32, at = sizeof(TA) == 8 ? SPIC_F64 : SPIC_F32;
